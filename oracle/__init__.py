@@ -1,0 +1,276 @@
+"""CPU oracle for the semiring sparse contraction -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg import
+this package.  The product path (the HIP library and its binding) never
+imports, links or calls anything here, and this package imports nothing from
+the product.  The heavy loops live in plain C (``oracle.c``, built with gcc
+and OpenMP); this module marshals numpy arrays to it and holds the few
+numpy-level definitions (mode folding of tensor keys).
+
+Semiring names: ``plus_times``, ``min_plus``, ``or_and``, ``max_times``.
+Value types: ``f64``, ``f32``, ``i32``, ``bool`` (uint8 0/1).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SEMIRINGS = {"plus_times": 0, "min_plus": 1, "or_and": 2, "max_times": 3}
+DTYPES = {"f64": 0, "f32": 1, "i32": 2, "bool": 3}
+NP_DTYPES = {"f64": np.float64, "f32": np.float32, "i32": np.int32, "bool": np.uint8}
+
+# Tropical additive identity on int32: half of INT_MAX (Section 3.1).
+INT_INF = (2 ** 31 - 1) // 2
+
+
+def default_add_id(semiring: str, dtype: str):
+    """Additive identity used when the caller gives none (Section 3.1 for
+    (+,x) and (min,+) int; +inf for float (min,+); 0 for (max,x) on the
+    non-negative domain; false for (or,and))."""
+    if semiring == "plus_times":
+        return 0.0
+    if semiring == "min_plus":
+        return INT_INF if dtype == "i32" else float("inf")
+    if semiring == "max_times":
+        return 0.0
+    return 0
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle.c`` to ``liboracle.so`` with gcc (-O2, OpenMP,
+    no floating-point contraction so the error-free transformations stay
+    exact)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+            "-shared", "-fPIC", _SRC, "-o", tmp, "-lm",
+        ])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        I = ctypes.c_int
+        L.orc_num_threads.restype = I
+        L.orc_set_threads.argtypes = [I]
+        L.orc_fold.argtypes = [I, I, P, I64, P, P, P, I64, P, P, P, P]
+        L.orc_spgemm_rows.argtypes = [I, I, I, P, I64, P, P, P, P, P, P, P, P, P, P, I64, P, P, P, P]
+        L.orc_spmm.argtypes = [I, I, P, I64, I64, P, P, P, P, I, P, P]
+        L.orc_bellman_ford.argtypes = [I, I, P, I64, I64, P, P, P, P, I64, P]
+        L.orc_bfs.argtypes = [I64, P, P, P, I64, P]
+        L.orc_dijkstra.argtypes = [I64, P, P, P, P, I64, I64, P]
+        L.orc_floyd_warshall.argtypes = [I64, P, I64]
+        for f in ("orc_fold", "orc_spgemm_rows", "orc_spmm", "orc_bellman_ford", "orc_bfs",
+                  "orc_dijkstra", "orc_floyd_warshall"):
+            getattr(L, f).restype = I
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def set_threads(t: int) -> None:
+    lib().orc_set_threads(int(t))
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _id_buf(semiring, dtype, add_id):
+    if add_id is None:
+        add_id = default_add_id(semiring, dtype)
+    return np.array([add_id], dtype=NP_DTYPES[dtype])
+
+
+class CSR:
+    """Host CSR matrix: int64 rowptr, int32 col, values (numpy)."""
+
+    def __init__(self, rowptr, col, val, nrows, ncols):
+        self.rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.val = np.ascontiguousarray(val)
+        self.nrows = int(nrows)
+        self.ncols = int(ncols)
+
+    @property
+    def nnz(self):
+        return int(self.rowptr[-1])
+
+    def row(self, i):
+        a, b = self.rowptr[i], self.rowptr[i + 1]
+        return self.col[a:b], self.val[a:b]
+
+
+def fold(semiring, dtype, rows, cols, vals, nrows, ncols, add_id=None) -> CSR:
+    """Index-value pairs -> CSR: stable sort by (row, col), duplicates
+    combined with the additive operator in input order, identity entries
+    dropped (Section 3.2 index-value pairs; readings in ``oracle.c``)."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    vals = np.ascontiguousarray(vals, dtype=NP_DTYPES[dtype])
+    nnz = rows.size
+    rp = np.zeros(nrows + 1, dtype=np.int64)
+    oc = np.zeros(max(nnz, 1), dtype=np.int32)
+    ov = np.zeros(max(nnz, 1), dtype=NP_DTYPES[dtype])
+    on = np.zeros(1, dtype=np.int64)
+    idb = _id_buf(semiring, dtype, add_id)
+    rc = lib().orc_fold(SEMIRINGS[semiring], DTYPES[dtype], _p(idb), nnz, _p(rows), _p(cols),
+                        _p(vals), nrows, _p(rp), _p(oc), _p(ov), _p(on))
+    if rc != 0:
+        raise MemoryError("oracle fold failed")
+    k = int(on[0])
+    return CSR(rp, oc[:k].copy(), ov[:k].copy(), nrows, ncols)
+
+
+def mode_split(keys, dims):
+    """Per-mode indices of linearized keys (last mode fastest)."""
+    keys = np.asarray(keys, dtype=np.int64)
+    out = []
+    rem = keys.copy()
+    for d in reversed(dims):
+        out.append(rem % d)
+        rem //= d
+    return list(reversed(out))
+
+
+def linearize(idx_list, dims):
+    """Linear key of per-mode indices (last mode fastest)."""
+    key = np.zeros_like(idx_list[0]) if idx_list else np.zeros(0, dtype=np.int64)
+    for i, d in zip(idx_list, dims):
+        key = key * d + i
+    return key
+
+
+def fold_tensor(semiring, dtype, keys, vals, dims, idx, row_idx, col_idx, add_id=None) -> CSR:
+    """Fold an order-d COO tensor to a matrix: rows linearize the modes named
+    by ``row_idx`` (in that order), columns those named by ``col_idx``.  A
+    contraction maps three groups of indices onto the three indices of a
+    matrix product (Section 5.1)."""
+    modes = mode_split(keys, dims)
+    pos = {c: t for t, c in enumerate(idx)}
+    rdims = [dims[pos[c]] for c in row_idx]
+    cdims = [dims[pos[c]] for c in col_idx]
+    rows = linearize([modes[pos[c]] for c in row_idx], rdims)
+    cols = linearize([modes[pos[c]] for c in col_idx], cdims)
+    return fold(semiring, dtype, rows, cols, vals, int(np.prod(rdims, dtype=np.int64)),
+                int(np.prod(cdims, dtype=np.int64)), add_id)
+
+
+def spgemm(semiring, dtype, A: CSR, B: CSR, add_id=None, rows=None, C_old: CSR = None,
+           threads=None):
+    """Rows of C = A (x) B [(+) C_old] by the contraction's definition.
+
+    Returns a CSR over the selected rows (``rows`` = None means all rows, in
+    order).  (+,x) values are fp64 (Dot2 accumulation); other semirings keep
+    the stored type.
+    """
+    if threads:
+        set_threads(threads)
+    if A.ncols != B.nrows:
+        raise ValueError("inner dimensions differ")
+    sel = np.arange(A.nrows, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    idb = _id_buf(semiring, dtype, add_id)
+    sr, dt = SEMIRINGS[semiring], DTYPES[dtype]
+    counts = np.zeros(max(sel.size, 1), dtype=np.int64)
+    va = np.ascontiguousarray(A.val, dtype=NP_DTYPES[dtype])
+    vb = np.ascontiguousarray(B.val, dtype=NP_DTYPES[dtype])
+    rc_ = cc_ = vc_ = None
+    if C_old is not None:
+        rc_, cc_ = C_old.rowptr, C_old.col
+        vc_ = np.ascontiguousarray(C_old.val, dtype=NP_DTYPES[dtype])
+    L = lib()
+    args = (sr, dt, _p(idb), B.ncols, _p(A.rowptr), _p(A.col), _p(va), _p(B.rowptr), _p(B.col),
+            _p(vb), _p(rc_), _p(cc_), _p(vc_), _p(sel), sel.size)
+    if L.orc_spgemm_rows(0, *args, _p(counts), None, None, None) != 0:
+        raise MemoryError("oracle spgemm failed")
+    counts = counts[: sel.size]
+    rp = np.zeros(sel.size + 1, dtype=np.int64)
+    np.cumsum(counts, out=rp[1:])
+    total = int(rp[-1])
+    oc = np.zeros(max(total, 1), dtype=np.int32)
+    odt = np.float64 if semiring == "plus_times" else NP_DTYPES[dtype]
+    ov = np.zeros(max(total, 1), dtype=odt)
+    offs = np.ascontiguousarray(rp[:-1])
+    if L.orc_spgemm_rows(1, *args, None, _p(offs), _p(oc), _p(ov)) != 0:
+        raise MemoryError("oracle spgemm failed")
+    return CSR(rp, oc[:total], ov[:total], sel.size, B.ncols)
+
+
+def spmm(semiring, dtype, A: CSR, X, add_id=None, self_term=False):
+    """Y = [X (+)] A (x) X for dense row-major X (n x s).  Returns (Y, changed).
+    (+,x) gives fp64; other semirings keep the stored type."""
+    X = np.ascontiguousarray(X, dtype=NP_DTYPES[dtype])
+    s = X.shape[1] if X.ndim == 2 else 1
+    odt = np.float64 if semiring == "plus_times" else NP_DTYPES[dtype]
+    Y = np.zeros((A.nrows, s), dtype=odt)
+    ch = np.zeros(1, dtype=np.int32)
+    idb = _id_buf(semiring, dtype, add_id)
+    va = np.ascontiguousarray(A.val, dtype=NP_DTYPES[dtype])
+    lib().orc_spmm(SEMIRINGS[semiring], DTYPES[dtype], _p(idb), A.nrows, s, _p(A.rowptr),
+                   _p(A.col), _p(va), _p(X), int(self_term), _p(Y), _p(ch))
+    return Y, bool(ch[0])
+
+
+def bellman_ford(semiring, dtype, A: CSR, P0, add_id=None, max_iters=None):
+    """Bellman-Ford fixpoint P <- P (+) A (x) P (Section 4.2).
+    Returns (P, iterations, converged)."""
+    P = np.array(P0, dtype=NP_DTYPES[dtype], copy=True, order="C")
+    if P.ndim == 1:
+        P = P[:, None]
+    n, s = P.shape
+    if max_iters is None:
+        max_iters = n
+    it = np.zeros(1, dtype=np.int64)
+    idb = _id_buf(semiring, dtype, add_id)
+    va = np.ascontiguousarray(A.val, dtype=NP_DTYPES[dtype])
+    rc = lib().orc_bellman_ford(SEMIRINGS[semiring], DTYPES[dtype], _p(idb), n, s, _p(A.rowptr),
+                                _p(A.col), _p(va), _p(P), int(max_iters), _p(it))
+    if rc < 0:
+        raise ValueError("oracle bellman-ford failed")
+    return P, int(it[0]), rc == 0
+
+
+def bfs_levels(A: CSR, sources):
+    """Queue BFS levels over edges j -> i (A[i][j] stored); -1 = unreachable."""
+    src = np.ascontiguousarray(sources, dtype=np.int64)
+    lev = np.zeros((A.nrows, src.size), dtype=np.int32)
+    lib().orc_bfs(A.nrows, _p(A.rowptr), _p(A.col), _p(src), src.size, _p(lev))
+    return lev
+
+
+def dijkstra(A: CSR, sources, inf_value=INT_INF):
+    """Dijkstra distances (int64) from each source; unreachable = inf_value."""
+    src = np.ascontiguousarray(sources, dtype=np.int64)
+    w = np.ascontiguousarray(A.val, dtype=np.int32)
+    d = np.zeros((A.nrows, src.size), dtype=np.int64)
+    lib().orc_dijkstra(A.nrows, _p(A.rowptr), _p(A.col), _p(w), _p(src), src.size,
+                       int(inf_value), _p(d))
+    return d
+
+
+def floyd_warshall(D, inf_value=INT_INF):
+    """All-pairs distances from a dense n x n matrix (D[i][j] = w(j -> i))."""
+    D = np.array(D, dtype=np.int64, copy=True, order="C")
+    lib().orc_floyd_warshall(D.shape[0], _p(D), int(inf_value))
+    return D

@@ -1,0 +1,366 @@
+"""Pins for the CPU oracle: each check ties it to something other than its own
+code -- brute force on tiny inputs, closed forms, library routines (scipy),
+and invariants of the algebra.  CPU only."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from gen import synth
+from brute import INT_INF, csr_to_dense, dense_product
+
+PAIRS = [("plus_times", "f64"), ("plus_times", "f32"), ("min_plus", "i32"),
+         ("min_plus", "f32"), ("or_and", "bool"), ("max_times", "f32"),
+         ("max_times", "f64")]
+
+
+def rand_matrix(semiring, dtype, m, n, density, seed, tag):
+    key = synth.stream_key(seed, tag)
+    u = synth.uniform_f64(key, m * n)
+    mask = u < density
+    rows, cols = np.nonzero(mask.reshape(m, n))
+    k = rows.size
+    if dtype == "i32":
+        vals = synth.randint(synth.stream_key(seed, tag + 1), k, -20, 100).astype(np.int32)
+        if semiring == "min_plus":
+            vals = np.abs(vals).astype(np.int32) + 1
+    elif dtype == "bool":
+        vals = np.ones(k, dtype=np.uint8)
+    elif dtype == "f32":
+        vals = synth.uniform_f32(synth.stream_key(seed, tag + 1), k) + np.float32(0.0625)
+    else:
+        vals = synth.uniform_f64(synth.stream_key(seed, tag + 1), k) + 0.0625
+    return oracle.fold(semiring, dtype, rows, cols, vals, m, n)
+
+
+def identity_fill(semiring, dtype):
+    if semiring == "min_plus":
+        return INT_INF if dtype == "i32" else np.inf
+    return 0
+
+
+@pytest.mark.parametrize("semiring,dtype", PAIRS)
+@settings(max_examples=12, deadline=None)
+@given(m=st.integers(0, 24), k=st.integers(0, 24), n=st.integers(0, 24),
+       density=st.floats(0.0, 0.9), seed=st.integers(0, 2 ** 32))
+def test_spgemm_matches_brute_force(semiring, dtype, m, k, n, density, seed):
+    A = rand_matrix(semiring, dtype, m, k, density, seed, 1)
+    B = rand_matrix(semiring, dtype, k, n, density, seed, 7)
+    C = oracle.spgemm(semiring, dtype, A, B)
+    npdt = oracle.NP_DTYPES[dtype]
+    fill = identity_fill(semiring, dtype)
+    DA, MA = csr_to_dense(A, fill, npdt)
+    DB, MB = csr_to_dense(B, fill, npdt)
+    DC, MC = dense_product(semiring, dtype, DA, MA, DB, MB)
+    got = np.zeros((m, n), dtype=np.float64)
+    gm = np.zeros((m, n), dtype=bool)
+    for i in range(m):
+        c, v = C.row(i)
+        assert np.all(np.diff(c) > 0), "columns ascending"
+        got[i, c] = v
+        gm[i, c] = True
+    assert np.array_equal(gm, MC)
+    if semiring == "plus_times":
+        np.testing.assert_allclose(got[MC], DC[MC], rtol=1e-14)
+    else:
+        assert np.array_equal(got[MC], DC[MC].astype(np.float64))
+
+
+def test_fold_duplicates_and_identity():
+    # brute force with a dict over a tiny COO list
+    rows = np.array([2, 0, 2, 1, 2, 0, 1, 1])
+    cols = np.array([1, 0, 1, 3, 1, 0, 0, 3])
+    vals_f = np.array([1.0, 2.0, 4.0, 0.0, 8.0, -2.0, 5.0, 3.0])
+    A = oracle.fold("plus_times", "f64", rows, cols, vals_f, 3, 4)
+    # (0,0): 2 + -2 = 0 -> dropped; (1,3): 0 is absent, 3 kept; (2,1): 13
+    assert A.rowptr.tolist() == [0, 0, 2, 3]
+    assert A.col.tolist() == [0, 3, 1]
+    assert A.val.tolist() == [5.0, 3.0, 13.0]
+    vals_i = np.array([7, 3, 5, INT_INF, 9, 4, 1, 2], dtype=np.int32)
+    T = oracle.fold("min_plus", "i32", rows, cols, vals_i, 3, 4)
+    assert T.col.tolist() == [0, 0, 3, 1]
+    assert T.val.tolist() == [3, 1, 2, 5]
+    assert T.rowptr.tolist() == [0, 1, 3, 4]
+
+
+def test_fold_matches_scipy_sum_duplicates():
+    src, dst = synth.rmat_edges(10, 8, 0.57, 0.19, 0.19, seed=11)
+    vals = synth.edge_values("i32", src.size, 11, lo=1, hi=9).astype(np.float64)
+    A = oracle.fold("plus_times", "f64", dst, src, vals, 1024, 1024)
+    S = sp.coo_matrix((vals, (dst, src)), shape=(1024, 1024)).tocsr()
+    S.sum_duplicates()
+    S.sort_indices()
+    assert np.array_equal(A.rowptr, S.indptr)
+    assert np.array_equal(A.col, S.indices)
+    assert np.array_equal(A.val, S.data)   # small integers: sums are exact
+
+
+def test_fold_tensor_modes():
+    dims = (5, 6, 7)
+    keys = synth.bernoulli_keys(dims, 0.2, seed=3)
+    vals = synth.uniform_f32(synth.stream_key(3, 1), keys.size)
+    F = oracle.fold_tensor("plus_times", "f32", keys, vals, dims, "ijk", "ki", "j")
+    i, j, k = np.unravel_index(keys, dims)
+    D = np.zeros((7 * 5, 6), dtype=np.float32)
+    D[k * 5 + i, j] = vals
+    G = np.zeros_like(D)
+    for r in range(F.nrows):
+        c, v = F.row(r)
+        G[r, c] = v
+    assert np.array_equal(D, G)
+
+
+def test_plus_times_matches_scipy_and_dot2():
+    src, dst = synth.er_edges(300, 6, seed=5)
+    v = synth.uniform_f64(synth.stream_key(5, 9), src.size)
+    A = oracle.fold("plus_times", "f64", dst, src, v, 300, 300)
+    C = oracle.spgemm("plus_times", "f64", A, A)
+    S = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(300, 300))
+    R = (S @ S).tocsr()
+    R.sort_indices()
+    R.eliminate_zeros()
+    assert np.array_equal(C.rowptr, R.indptr) and np.array_equal(C.col, R.indices)
+    np.testing.assert_allclose(C.val, R.data, rtol=1e-13)
+    # Dot2: 1e16 + 1 - 1e16 is 1 exactly, which plain fp64 summation loses
+    A1 = oracle.fold("plus_times", "f64", [0, 0, 0], [0, 1, 2], [1e16, 1.0, -1e16], 1, 3)
+    B1 = oracle.fold("plus_times", "f64", [0, 1, 2], [0, 0, 0], [1.0, 1.0, 1.0], 3, 1)
+    assert oracle.spgemm("plus_times", "f64", A1, B1).val.tolist() == [1.0]
+
+
+def path_graph(n, w):
+    src = np.arange(n - 1)
+    dst = src + 1
+    return oracle.fold("min_plus", "i32", dst, src, w, n, n)
+
+
+def test_path_graph_closed_forms():
+    n = 40
+    w = synth.randint(synth.stream_key(9, 1), n - 1, 1, 100).astype(np.int32)
+    A = path_graph(n, w)
+    C = oracle.spgemm("min_plus", "i32", A, A)
+    # (A (x) A)[i+2, i] = w_i + w_{i+1}; nothing else
+    assert C.nnz == n - 2
+    for i in range(n - 2):
+        c, v = C.row(i + 2)
+        assert c.tolist() == [i] and v.tolist() == [w[i] + w[i + 1]]
+    P0 = np.full((n, 1), INT_INF, dtype=np.int32)
+    P0[0, 0] = 0
+    P, iters, conv = oracle.bellman_ford("min_plus", "i32", A, P0)
+    assert conv and iters == n          # n-1 relaxations plus one unchanged step
+    assert np.array_equal(P[:, 0], np.concatenate([[0], np.cumsum(w)]))
+    lev = oracle.bfs_levels(A, [0])
+    assert np.array_equal(lev[:, 0], np.arange(n))
+    # boolean A^k is a shift by k
+    Ab = oracle.fold("or_and", "bool", np.arange(1, n), np.arange(n - 1), np.ones(n - 1, np.uint8), n, n)
+    Pk = Ab
+    for k in range(2, 6):
+        Pk = oracle.spgemm("or_and", "bool", Pk, Ab)
+        assert Pk.nnz == n - k
+        assert all(Pk.row(i + k)[0].tolist() == [i] for i in range(n - k))
+
+
+def test_bf_not_converged_cap():
+    n = 10
+    A = path_graph(n, np.ones(n - 1, np.int32))
+    P0 = np.full((n, 1), INT_INF, dtype=np.int32)
+    P0[0, 0] = 0
+    _, iters, conv = oracle.bellman_ford("min_plus", "i32", A, P0, max_iters=5)
+    assert not conv and iters == 5
+
+
+def test_star_closed_form():
+    L = 50
+    hub = np.zeros(L, dtype=np.int64)
+    leaves = np.arange(1, L + 1)
+    rows = np.concatenate([hub, leaves])
+    cols = np.concatenate([leaves, hub])
+    A = oracle.fold("plus_times", "f64", rows, cols, np.ones(2 * L), L + 1, L + 1)
+    C = oracle.spgemm("plus_times", "f64", A, A)
+    assert C.nnz == L * L + 1
+    assert C.row(0)[0].tolist() == [0] and C.row(0)[1].tolist() == [float(L)]
+    for i in range(1, L + 1):
+        c, v = C.row(i)
+        assert c.tolist() == list(range(1, L + 1)) and np.all(v == 1.0)
+    T = oracle.fold("min_plus", "i32", rows, cols, np.ones(2 * L, np.int32), L + 1, L + 1)
+    CT = oracle.spgemm("min_plus", "i32", T, T)
+    assert CT.nnz == L * L + 1 and np.all(CT.val == 2)
+
+
+@pytest.mark.parametrize("semiring,dtype", PAIRS)
+def test_identity_matrix_is_neutral(semiring, dtype):
+    A = rand_matrix(semiring, dtype, 30, 30, 0.2, 77, 3)
+    one = {"plus_times": 1, "min_plus": 0, "or_and": 1, "max_times": 1}[semiring]
+    I = oracle.fold(semiring, dtype, np.arange(30), np.arange(30),
+                    np.full(30, one, dtype=oracle.NP_DTYPES[dtype]), 30, 30)
+    for C in (oracle.spgemm(semiring, dtype, I, A), oracle.spgemm(semiring, dtype, A, I)):
+        assert np.array_equal(C.rowptr, A.rowptr) and np.array_equal(C.col, A.col)
+        assert np.array_equal(C.val.astype(np.float64), A.val.astype(np.float64))
+
+
+def test_all_ones_square():
+    n = 33
+    r, c = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    J = oracle.fold("plus_times", "f32", r.ravel(), c.ravel(), np.ones(n * n, np.float32), n, n)
+    C = oracle.spgemm("plus_times", "f32", J, J)
+    assert C.nnz == n * n and np.all(C.val == n)
+    E = oracle.spgemm("plus_times", "f32", oracle.fold("plus_times", "f32", [], [], [], n, n), J)
+    assert E.nnz == 0
+
+
+def test_stencil27_square_closed_form():
+    g = 7
+    src, dst = synth.stencil27_edges(g)
+    N = g ** 3
+    A = oracle.fold("plus_times", "f64", dst, src, np.ones(src.size), N, N)
+    C = oracle.spgemm("plus_times", "f64", A, A)
+    cnt = {0: 3, 1: 2, 2: 1}
+    ctr = (3 * g + 3) * g + 3          # interior point (3,3,3)
+    c, v = C.row(ctr)
+    assert c.size == 125
+    for col, val in zip(c, v):
+        x, y, z = col // (g * g), (col // g) % g, col % g
+        assert val == cnt[abs(x - 3)] * cnt[abs(y - 3)] * cnt[abs(z - 3)]
+    T = oracle.fold("min_plus", "i32", dst, src, np.ones(src.size, np.int32), N, N)
+    assert np.all(oracle.spgemm("min_plus", "i32", T, T, rows=[ctr]).val[
+        oracle.spgemm("min_plus", "i32", T, T, rows=[ctr]).col != ctr] == 2)
+    lev = oracle.bfs_levels(T, [0])[:, 0]
+    xs, ys, zs = np.unravel_index(np.arange(N), (g, g, g))
+    assert np.array_equal(lev, np.maximum(np.maximum(xs, ys), zs))
+
+
+def er_weighted(n, d, seed):
+    src, dst = synth.er_edges(n, d, seed)
+    w = synth.edge_values("i32", src.size, seed, lo=1, hi=100)
+    return oracle.fold("min_plus", "i32", dst, src, w, n, n), src, dst, w
+
+
+def test_apsp_floyd_warshall_equals_path_doubling_and_scipy():
+    n = 64
+    A, src, dst, w = er_weighted(n, 8, synth.SEED_CFG0)
+    D = np.full((n, n), INT_INF, dtype=np.int64)
+    D[A.rowptr.searchsorted(np.arange(A.nnz), side="right") - 1, A.col] = A.val
+    np.fill_diagonal(D, 0)
+    FW = oracle.floyd_warshall(D)
+    # scipy: graph[u, v] = weight of u -> v, i.e. the transpose of D
+    G = sp.csr_matrix((A.val.astype(np.float64), A.col,
+                       A.rowptr), shape=(n, n)).T
+    ref = csg.floyd_warshall(G, directed=True).T
+    fin = np.isfinite(ref)
+    assert np.array_equal(FW[fin], ref[fin].astype(np.int64)) and np.all(FW[~fin] == INT_INF)
+    # path doubling: A <- A (+) A (x) A, ceil(log2 n) rounds, from I (+) A
+    I = oracle.fold("min_plus", "i32", np.arange(n), np.arange(n), np.zeros(n, np.int32), n, n)
+    P = oracle.spgemm("min_plus", "i32", I, I, C_old=A)   # (I (+) A)
+    rounds = 0
+    l = 1
+    while l < n:
+        P = oracle.spgemm("min_plus", "i32", P, P, C_old=P)
+        l <<= 1
+        rounds += 1
+    assert rounds == 6
+    Dp = np.full((n, n), INT_INF, dtype=np.int64)
+    for i in range(n):
+        c, v = P.row(i)
+        Dp[i, c] = v
+    assert np.array_equal(Dp, FW)
+
+
+def test_sssp_bellman_ford_equals_dijkstra_and_scipy():
+    n = 2000
+    A, src, dst, w = er_weighted(n, 6, 17)
+    sources = synth.pick_sources(n, src, 8, 17)
+    P0 = np.full((n, sources.size), INT_INF, dtype=np.int32)
+    P0[sources, np.arange(sources.size)] = 0
+    P, iters, conv = oracle.bellman_ford("min_plus", "i32", A, P0)
+    assert conv
+    Dj = oracle.dijkstra(A, sources)
+    assert np.array_equal(P.astype(np.int64), Dj)
+    G = sp.csr_matrix((A.val.astype(np.float64), A.col, A.rowptr), shape=(n, n)).T.tocsr()
+    ref = csg.dijkstra(G, directed=True, indices=sources).T
+    fin = np.isfinite(ref)
+    assert np.array_equal(Dj[fin], ref[fin].astype(np.int64)) and np.all(Dj[~fin] == INT_INF)
+    # BFS levels vs scipy unweighted shortest paths
+    lev = oracle.bfs_levels(A, sources)
+    hop = csg.shortest_path(G, directed=True, unweighted=True, indices=sources).T
+    fin = np.isfinite(hop)
+    assert np.array_equal(lev[fin], hop[fin].astype(np.int32)) and np.all(lev[~fin] == -1)
+
+
+def test_bf_iterates_are_hop_bounded_distances():
+    # After r BSP steps P holds shortest distances over paths of <= r edges;
+    # checked against Dijkstra on the layered (hop, vertex) graph.
+    n, s = 300, 3
+    A, src, dst, w = er_weighted(n, 3, 23)
+    sources = synth.pick_sources(n, src, s, 23)
+    P0 = np.full((n, s), INT_INF, dtype=np.int32)
+    P0[sources, np.arange(s)] = 0
+    for r in (1, 2, 3, 5):
+        P, it, _ = oracle.bellman_ford("min_plus", "i32", A, P0, max_iters=r)
+        # layered graph: node (h, v), edges (h, u) -> (h+1, v) weight w, (h, v) -> (h+1, v) weight 0
+        L = r + 1
+        rr, cc, ww = [], [], []
+        rows_of = np.repeat(np.arange(n), np.diff(A.rowptr))
+        for h in range(r):
+            rr += list(h * n + A.col); cc += list((h + 1) * n + rows_of); ww += list(A.val)
+            rr += list(h * n + np.arange(n)); cc += list((h + 1) * n + np.arange(n)); ww += [0] * n
+        G = sp.csr_matrix((np.array(ww, float) + 1e-9, (rr, cc)), shape=(L * n, L * n))
+        ref = csg.dijkstra(G, directed=True, indices=sources)[:, r * n:(r + 1) * n].T
+        fin = np.isfinite(ref)
+        assert np.array_equal(P[fin].astype(np.int64), np.rint(ref[fin]).astype(np.int64))
+        assert np.all(P[~fin] == INT_INF)
+
+
+def test_algebraic_invariants():
+    for semiring, dtype in (("min_plus", "i32"), ("or_and", "bool")):
+        A = rand_matrix(semiring, dtype, 20, 15, 0.2, 5, 1)
+        B = rand_matrix(semiring, dtype, 15, 25, 0.2, 5, 3)
+        C = rand_matrix(semiring, dtype, 25, 10, 0.2, 5, 5)
+        L = oracle.spgemm(semiring, dtype, oracle.spgemm(semiring, dtype, A, B), C)
+        R = oracle.spgemm(semiring, dtype, A, oracle.spgemm(semiring, dtype, B, C))
+        assert np.array_equal(L.rowptr, R.rowptr) and np.array_equal(L.col, R.col)
+        assert np.array_equal(L.val, R.val)
+
+    def transpose(M, semiring, dtype):
+        rows = np.repeat(np.arange(M.nrows), np.diff(M.rowptr))
+        return oracle.fold(semiring, dtype, M.col, rows, M.val, M.ncols, M.nrows)
+
+    for semiring, dtype in (("min_plus", "i32"), ("min_plus", "f32"), ("or_and", "bool"),
+                            ("max_times", "f32")):
+        A = rand_matrix(semiring, dtype, 20, 15, 0.3, 8, 1)
+        B = rand_matrix(semiring, dtype, 15, 25, 0.3, 8, 3)
+        L = transpose(oracle.spgemm(semiring, dtype, A, B), semiring, dtype)
+        R = oracle.spgemm(semiring, dtype, transpose(B, semiring, dtype), transpose(A, semiring, dtype))
+        assert np.array_equal(L.col, R.col) and np.array_equal(L.val, R.val)
+    # same pattern across semirings for positive values
+    src, dst = synth.er_edges(200, 5, 31)
+    pats = []
+    for semiring, dtype, v in (("or_and", "bool", np.ones(src.size, np.uint8)),
+                               ("min_plus", "i32", np.ones(src.size, np.int32)),
+                               ("plus_times", "f64", np.ones(src.size))):
+        A = oracle.fold(semiring, dtype, dst, src, v, 200, 200)
+        C = oracle.spgemm(semiring, dtype, A, A)
+        pats.append((C.rowptr, C.col))
+        prods = int(sum(np.diff(A.rowptr)[A.col]))
+        assert C.nnz <= prods
+    for p in pats[1:]:
+        assert np.array_equal(p[0], pats[0][0]) and np.array_equal(p[1], pats[0][1])
+
+
+@pytest.mark.parametrize("semiring,dtype", PAIRS)
+def test_spmm_matches_brute_force(semiring, dtype):
+    A = rand_matrix(semiring, dtype, 23, 19, 0.3, 41, 1)
+    X = rand_matrix(semiring, dtype, 19, 5, 0.6, 41, 3)
+    fill = identity_fill(semiring, dtype)
+    npdt = oracle.NP_DTYPES[dtype]
+    DX, MX = csr_to_dense(X, fill, npdt)
+    Y, _ = oracle.spmm(semiring, dtype, A, DX)
+    DA, MA = csr_to_dense(A, fill, npdt)
+    DC, MC = dense_product(semiring, dtype, DA, MA, DX, MX)
+    idv = fill if semiring != "or_and" else 0
+    exp = np.where(MC, DC, idv)
+    if semiring == "plus_times":
+        np.testing.assert_allclose(Y, exp, rtol=1e-14)
+    else:
+        assert np.array_equal(Y.astype(np.float64), exp.astype(np.float64))
