@@ -1,0 +1,286 @@
+/*
+ * srtc -- semiring sparse tensor contraction on AMD MI355X (gfx950).
+ *
+ * C-ABI of the library libsrtc.so.  The operation is the generalized tensor
+ * contraction of Solomonik and Hoefler, "Sparse Tensor Algebra as a Parallel
+ * Programming Model" (arXiv:1512.00066):
+ *
+ *     C["c"] (+)= A["a"] (x) B["b"]
+ *
+ * over a semiring ((+), additive identity, (x)) chosen by the caller
+ * (Section 3.1, Table 1), with operands given by index strings in Einstein
+ * notation (Section 3.3.1): an index in A and B but not C is contracted, an
+ * index in A (or B) and C is a free row (column) index, an index in all three
+ * tensors enumerates independent problems.  Every contraction is folded to a
+ * matrix product first (Section 5.1): rows = free indices of A, inner =
+ * contracted indices, columns = free indices of B.  Contracting two sparse
+ * tensors, and producing sparse output, are the extensions the paper leaves
+ * open (Sections 1 and 7); this library computes both.
+ *
+ * Conventions for every call:
+ *   - Pointers inside srtc_tensor are DEVICE pointers unless stated; host
+ *     pointers are marked "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Work is enqueued on it; calls that must know an output size
+ *     synchronize that stream once (documented per call).
+ *   - Inputs are borrowed: they must stay valid until the stream work ends.
+ *   - Every device buffer the library needs (outputs and scratch) comes from
+ *     the context's allocator callback; outputs become the caller's, scratch
+ *     is returned through the free callback before the call returns (the
+ *     allocator must therefore be stream-ordered, e.g. a caching allocator
+ *     bound to `stream`, or a synchronous one).
+ *   - No call aborts and no C++ exception crosses the ABI: failures return a
+ *     negative srtc_status and srtc_last_error() describes the last one.
+ *   - An operand entry equal to the additive identity is absent; output
+ *     entries equal to it are dropped (a new sparse tensor holds no entries,
+ *     a dense one holds the additive identity: Section 3.2).
+ */
+#ifndef SRTC_H
+#define SRTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- statuses -- */
+typedef enum srtc_status {
+  SRTC_OK = 0,
+  SRTC_ERR_ARG = -1,           /* null pointer, negative size, bad enum value */
+  SRTC_ERR_INDEX = -2,         /* bad index string: length, repeated index,
+                                  index in only one tensor (reductions and maps
+                                  of Section 3.3.1 are not part of this API) */
+  SRTC_ERR_DIM = -3,           /* dimensions of matched indices differ */
+  SRTC_ERR_DTYPE = -4,         /* value type not defined for the semiring */
+  SRTC_ERR_FORMAT = -5,        /* malformed CSR/COO (checked when validate=1) */
+  SRTC_ERR_ALIAS = -6,         /* output storage overlaps an input */
+  SRTC_ERR_OOM = -7,           /* the allocator returned NULL */
+  SRTC_ERR_NOT_CONVERGED = -8, /* fixpoint still changing after max_iters */
+  SRTC_ERR_UNSUPPORTED = -9,   /* well-formed request outside this library */
+  SRTC_ERR_DEVICE = -10        /* HIP runtime error (message has the text) */
+} srtc_status;
+
+/* ------------------------------------------------------------ semirings -- */
+/* Section 3.1: a semiring is (additive op, additive identity, multiplicative
+ * op, multiplicative identity).  The additive identity is passed by the
+ * caller (add_id, a host pointer to one value of the operand dtype; NULL
+ * selects the default listed here). */
+typedef enum srtc_semiring {
+  SRTC_PLUS_TIMES = 0, /* (+, 0, x, 1) on F64/F32.  F32 products are formed
+                          exactly and summed in fp64, rounded once.  add_id
+                          must be 0. */
+  SRTC_MIN_PLUS = 1,   /* tropical (min, id, +, 0) on I32 (default id
+                          INT32_MAX/2, Section 3.1) or F32 (default +inf).
+                          I32 results at or above id are clamped to id, hence
+                          absent; operands must lie in [-id, id]. */
+  SRTC_OR_AND = 2,     /* boolean (or, false, and, true) on BOOL8 (any nonzero
+                          byte is true) and BITS64 frontiers */
+  SRTC_MAX_TIMES = 3   /* (max, id, x, 1) on F32/F64; default id 0 (for
+                          non-negative values) */
+} srtc_semiring;
+
+typedef enum srtc_dtype {
+  SRTC_F64 = 0,
+  SRTC_F32 = 1,
+  SRTC_I32 = 2,
+  SRTC_BOOL8 = 3,  /* uint8 0/1 */
+  SRTC_BITS64 = 4  /* dense boolean frontier: bit s of word v = source s */
+} srtc_dtype;
+
+typedef enum srtc_format {
+  SRTC_DENSE = 0, /* row-major, last mode fastest, prod(dims) values */
+  SRTC_COO = 1,   /* nnz index-value pairs: coo_keys[t] = linearized index
+                     (last mode fastest), vals[t]; duplicates allowed (they
+                     are combined with the additive op) */
+  SRTC_CSR = 2    /* rows = leading `split` modes, columns = the rest;
+                     rowptr[rows+1] int64, colidx[nnz] int32 ascending and
+                     unique within a row, vals[nnz] */
+} srtc_format;
+
+#define SRTC_MAX_ORDER 8
+
+typedef struct srtc_tensor {
+  int32_t order;                 /* 0..SRTC_MAX_ORDER */
+  int32_t format;                /* srtc_format */
+  int32_t dtype;                 /* srtc_dtype */
+  int32_t split;                 /* CSR: number of leading modes in the row */
+  int64_t dims[SRTC_MAX_ORDER];  /* extent of each mode */
+  int64_t nnz;                   /* COO/CSR: stored entries */
+  int64_t *coo_keys;             /* COO */
+  int64_t *rowptr;               /* CSR */
+  int32_t *colidx;               /* CSR */
+  void *vals;                    /* COO/CSR: nnz values; DENSE: prod(dims) */
+} srtc_tensor;
+
+/* Allocator callback: return `bytes` of device memory (256-byte aligned) or
+ * NULL.  Free callback: release a pointer returned by the allocator. */
+typedef void *(*srtc_alloc_fn)(void *user, size_t bytes);
+typedef void (*srtc_free_fn)(void *user, void *ptr);
+
+typedef struct srtc_ctx srtc_ctx;
+
+/* Number of SpGEMM schedules (the variant/binning presets the autotuner and
+ * the selector choose among). */
+#define SRTC_NUM_SCHEDULES 8
+#define SRTC_NUM_FEATURES 32
+
+typedef struct srtc_opts {
+  int32_t schedule; /* -1: choose (selector if trained, else autotune cache,
+                       else the default); 0..SRTC_NUM_SCHEDULES-1: force */
+  int32_t sorted;   /* 1: output rows list columns ascending (default) */
+  int32_t validate; /* 1: check operand structure (SRTC_ERR_FORMAT) */
+  int32_t reserved;
+} srtc_opts;
+
+/* ------------------------------------------------------------- context -- */
+
+/* Create a context bound to HIP device `device`.  alloc/free may be NULL:
+ * then hipMalloc/hipFree are used (synchronous).  One context per host
+ * thread. */
+srtc_status srtc_ctx_create(int device, srtc_alloc_fn alloc, srtc_free_fn free_fn, void *user,
+                            srtc_ctx **out);
+srtc_status srtc_ctx_destroy(srtc_ctx *ctx);
+/* Message for the last failed call on this context (never NULL). */
+const char *srtc_last_error(const srtc_ctx *ctx);
+const char *srtc_status_string(srtc_status st);
+
+/* ---------------------------------------------------------------- fold -- */
+
+/* Fold (Section 5.1, local transposition of Section 6.2): rearrange a COO or
+ * CSR tensor `src`, whose modes carry the letters of `isrc`, into a CSR
+ * matrix whose row key linearizes the modes named by `rows` (in that order)
+ * and whose column key linearizes those named by `cols`.  Every letter of
+ * isrc must appear exactly once in rows+cols.  Duplicate keys are combined
+ * with the semiring's additive op in input order (float (+) in fp64, rounded
+ * once), identity entries are dropped.  A CSR source is transposed this way.
+ * On success `out` is a CSR tensor of order |rows|+|cols| with
+ * split = |rows|; its arrays come from the allocator and belong to the
+ * caller.  Synchronizes `stream` once (output size). */
+srtc_status srtc_fold(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const char *isrc,
+                      const srtc_tensor *src, const char *rows, const char *cols,
+                      srtc_tensor *out, void *stream);
+
+/* ----------------------------------------------------------- contract -- */
+
+/* C["ic"] (+)= A["ia"] (x) B["ib"] (Section 3.3.1; accumulate = 0 gives
+ * C = A (x) B).  Forms:
+ *   sparse A x sparse B -> sparse C (CSR, allocated here; with accumulate the
+ *       previous C joins the sum and is replaced by new arrays -- the old
+ *       arrays stay the caller's).  Synchronizes once (output size).
+ *   sparse A x dense B  -> dense C (caller-allocated, fully asynchronous).
+ *   dense A x dense B   -> dense C, (+,x) only, on the matrix cores.
+ * Index rules: each letter appears at most once per tensor and in at least
+ * two tensors; in C all column letters (those of B only) follow all row
+ * letters.  Sparse operands may be COO (folded on the fly) or CSR whose
+ * split matches the fold.  Right-hand sides are read before C is written
+ * (out-of-place); C may not share storage with A or B (SRTC_ERR_ALIAS). */
+srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int accumulate,
+                          const char *ia, const srtc_tensor *A, const char *ib,
+                          const srtc_tensor *B, const char *ic, srtc_tensor *C,
+                          const srtc_opts *opts, void *stream);
+
+/* ----------------------------------------------------------- fixpoint -- */
+
+/* Bellman-Ford as repeated semiring products (Section 4.2):
+ *   X <- X (+) A (x) X
+ * on a dense n x s frontier X (row-major, updated in place) until a step
+ * changes nothing.  A is an n x n CSR whose entry (i, j) is the weight of
+ * edge j -> i.  Steps are replayed as captured HIP graphs of
+ * `steps_per_check` steps; the host reads the change flags once per replay.
+ * *iters_out (host) = number of steps up to and including the first
+ * unchanged one.  Returns SRTC_ERR_NOT_CONVERGED if step `max_iters` (<= 0:
+ * n) still changed something (a negative cycle, for (min,+)); X then holds
+ * that iterate.  Supported: MIN_PLUS (I32, F32), MAX_TIMES (F32, F64),
+ * OR_AND (BOOL8). */
+srtc_status srtc_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
+                          const srtc_tensor *A, srtc_tensor *X, int64_t max_iters,
+                          int32_t steps_per_check, int64_t *iters_out, void *stream);
+
+/* Multi-source breadth-first levels over the (or,and) semiring with a
+ * bit-packed frontier (one uint64 per vertex, bit t = source t, nsrc <= 64).
+ * A's pattern gives the edges (entry (i, j) = edge j -> i; values ignored).
+ * sources: host array of nsrc vertex ids.  levels: device n x nsrc int32,
+ * level 0 at the source, -1 if unreachable.  *depth_out (host) = largest
+ * level.  Synchronizes once per level. */
+srtc_status srtc_bfs_levels(srtc_ctx *ctx, const srtc_tensor *A, const int64_t *sources,
+                            int32_t nsrc, int32_t *levels, int32_t *depth_out, void *stream);
+
+/* -------------------------------------------------------------- batch -- */
+
+/* Independent problems (an index shared by all three tensors, Sections
+ * 3.3.1 and 5.1): C_b = A_b (x) B_b for b < ninst, all sparse CSR matrices,
+ * in one set of launches over every instance's rows (persistent work-queue
+ * kernels) instead of one set per instance.  Cs[b] receives CSR arrays that
+ * point into shared allocations: Cs[0].rowptr/colidx/vals own the memory
+ * (free those three to release every instance).  Synchronizes once. */
+srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
+                                int32_t ninst, const srtc_tensor *As, const srtc_tensor *Bs,
+                                srtc_tensor *Cs, const srtc_opts *opts, void *stream);
+
+/* Batched Bellman-Ford: X_b <- X_b (+) A_b (x) X_b for every instance until
+ * each is unchanged; converged instances drop out.  All X_b have the same
+ * width s.  iters_out: host array of ninst step counts. */
+srtc_status srtc_batch_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
+                                int32_t ninst, const srtc_tensor *As, srtc_tensor *Xs,
+                                int64_t max_iters, int32_t steps_per_check, int64_t *iters_out,
+                                void *stream);
+
+/* --------------------------------------------------------- scheduling -- */
+
+/* The 32 scale-free features of an SpGEMM problem A (x) B (both CSR
+ * matrices): histograms of row lengths and row product counts, sizes, a
+ * sampled compression-ratio estimate, skew measures and the semiring/dtype.
+ * out: host float[SRTC_NUM_FEATURES].  Synchronizes once. */
+srtc_status srtc_features(srtc_ctx *ctx, srtc_semiring sr, const srtc_tensor *A,
+                          const srtc_tensor *B, float *out, void *stream);
+
+/* Exhaustive autotuner: time every schedule on A (x) B (median of `reps`
+ * runs after one warm-up, the paper's Section 6 protocol), cache the winner
+ * under the feature vector, return it in *best and the median times in
+ * times_ms (host float[SRTC_NUM_SCHEDULES], may be NULL). */
+srtc_status srtc_autotune(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
+                          const srtc_tensor *A, const srtc_tensor *B, int32_t reps,
+                          int32_t *best, float *times_ms, void *stream);
+
+/* Learned selector: schedule predicted for a feature vector (host float[32])
+ * by the context's MLP (32 -> 64 -> 64 -> SRTC_NUM_SCHEDULES, ReLU),
+ * evaluated on the GPU.  SRTC_ERR_UNSUPPORTED if no network is loaded. */
+srtc_status srtc_select(srtc_ctx *ctx, const float *features, int32_t *schedule);
+
+typedef struct srtc_train_cfg {
+  int32_t epochs;      /* passes over the data */
+  int32_t batch;       /* minibatch size (<= 1024) */
+  float lr;            /* Adam step size */
+  float beta1, beta2, eps;
+  uint64_t seed;       /* weight initialization and shuffling */
+} srtc_train_cfg;
+
+/* Train the selector on nsamples rows of features X (host, nsamples x 32)
+ * and per-schedule targets T (host, nsamples x SRTC_NUM_SCHEDULES: log2
+ * time, centered per sample) with the MSE loss and Adam; forward, backward
+ * and update run as HIP kernels.  Features are standardized with statistics
+ * kept in the network.  *final_loss (host) = mean loss of the last epoch. */
+srtc_status srtc_selector_train(srtc_ctx *ctx, const float *X, const float *T, int32_t nsamples,
+                                const srtc_train_cfg *cfg, float *final_loss, void *stream);
+srtc_status srtc_selector_save(srtc_ctx *ctx, const char *path);
+srtc_status srtc_selector_load(srtc_ctx *ctx, const char *path);
+
+/* Raw MLP kernels, for checking gradients against a reference.  All
+ * pointers device, fp32, row-major.  params = [W1 (64x32), b1 (64), W2
+ * (64x64), b2 (64), W3 (Kx64), b3 (K)], K = SRTC_NUM_SCHEDULES; X is
+ * n x 32; Y (forward output) n x K; with T given, *loss (device) receives
+ * mean over samples of sum_k (Y-T)^2 / K and grads (same layout as params)
+ * its gradient. */
+srtc_status srtc_mlp_forward(srtc_ctx *ctx, const float *params, const float *X, int32_t n,
+                             float *Y, void *stream);
+srtc_status srtc_mlp_loss_grad(srtc_ctx *ctx, const float *params, const float *X,
+                               const float *T, int32_t n, float *loss, float *grads,
+                               void *stream);
+int64_t srtc_mlp_num_params(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SRTC_H */

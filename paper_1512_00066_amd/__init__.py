@@ -1,0 +1,460 @@
+"""Python binding of libsrtc: semiring sparse tensor contraction on MI355X.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library (``libsrtc.so``, C-ABI declared in ``include/srtc.h``).  PyTorch
+provides device memory and the current stream; outputs the library
+allocates come from torch through an allocator callback and are returned as
+torch tensors.  Importing works without a GPU; calling needs one, and the
+library must have been built (``paper_1512_00066_amd.build.build()``) --
+there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsrtc.so")
+
+# ------------------------------------------------------------------ enums --
+PLUS_TIMES, MIN_PLUS, OR_AND, MAX_TIMES = 0, 1, 2, 3
+SEMIRINGS = {"plus_times": PLUS_TIMES, "min_plus": MIN_PLUS, "or_and": OR_AND, "max_times": MAX_TIMES}
+F64, F32, I32, BOOL8, BITS64 = 0, 1, 2, 3, 4
+DENSE, COO_FMT, CSR_FMT = 0, 1, 2
+NUM_SCHEDULES = 8
+NUM_FEATURES = 32
+
+_TORCH_TO_DT = {torch.float64: F64, torch.float32: F32, torch.int32: I32, torch.uint8: BOOL8}
+_DT_TO_TORCH = {F64: torch.float64, F32: torch.float32, I32: torch.int32, BOOL8: torch.uint8, BITS64: torch.int64}
+_DT_CTYPE = {F64: ctypes.c_double, F32: ctypes.c_float, I32: ctypes.c_int32, BOOL8: ctypes.c_uint8}
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "invalid index string", -3: "dimension mismatch",
+          -4: "value type not defined for the semiring", -5: "malformed sparse operand",
+          -6: "output overlaps an input", -7: "out of memory", -8: "fixpoint not reached",
+          -9: "unsupported", -10: "device error"}
+
+
+class SrtcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class NotConverged(SrtcError):
+    def __init__(self, status, message, iters):
+        super().__init__(status, message)
+        self.iters = iters
+
+
+class _Tensor(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("format", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("split", ctypes.c_int32), ("dims", ctypes.c_int64 * 8), ("nnz", ctypes.c_int64),
+                ("coo_keys", ctypes.c_void_p), ("rowptr", ctypes.c_void_p), ("colidx", ctypes.c_void_p),
+                ("vals", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("sorted", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _TrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1512_00066_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32_, I64_ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        T = ctypes.POINTER(_Tensor)
+        S = ctypes.c_char_p
+        sig = {
+            "srtc_ctx_create": ([ctypes.c_int, _ALLOC, _FREE, P, ctypes.POINTER(P)], ctypes.c_int),
+            "srtc_ctx_destroy": ([P], ctypes.c_int),
+            "srtc_last_error": ([P], ctypes.c_char_p),
+            "srtc_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "srtc_fold": ([P, ctypes.c_int, P, S, T, S, S, T, P], ctypes.c_int),
+            "srtc_contract": ([P, ctypes.c_int, P, ctypes.c_int, S, T, S, T, S, T, ctypes.POINTER(_Opts), P],
+                              ctypes.c_int),
+            "srtc_fixpoint": ([P, ctypes.c_int, P, T, T, I64_, I32_, ctypes.POINTER(I64_), P], ctypes.c_int),
+            "srtc_bfs_levels": ([P, T, ctypes.POINTER(I64_), I32_, P, ctypes.POINTER(I32_), P], ctypes.c_int),
+            "srtc_batch_contract": ([P, ctypes.c_int, P, I32_, T, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
+            "srtc_batch_fixpoint": ([P, ctypes.c_int, P, I32_, T, T, I64_, I32_, ctypes.POINTER(I64_), P],
+                                    ctypes.c_int),
+            "srtc_features": ([P, ctypes.c_int, T, T, ctypes.POINTER(ctypes.c_float), P], ctypes.c_int),
+            "srtc_autotune": ([P, ctypes.c_int, P, T, T, I32_, ctypes.POINTER(I32_), ctypes.POINTER(ctypes.c_float),
+                               P], ctypes.c_int),
+            "srtc_select": ([P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(I32_)], ctypes.c_int),
+            "srtc_selector_train": ([P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), I32_,
+                                     ctypes.POINTER(_TrainCfg), ctypes.POINTER(ctypes.c_float), P], ctypes.c_int),
+            "srtc_selector_save": ([P, S], ctypes.c_int),
+            "srtc_selector_load": ([P, S], ctypes.c_int),
+            "srtc_mlp_forward": ([P, P, P, I32_, P, P], ctypes.c_int),
+            "srtc_mlp_loss_grad": ([P, P, P, P, I32_, P, P, P], ctypes.c_int),
+            "srtc_mlp_num_params": ([], I64_),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------- tensors --
+@dataclass
+class CSR:
+    """A CSR tensor on the device: rows = leading ``split`` modes."""
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+    dims: tuple
+    split: int = 1
+    _keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @property
+    def shape(self):
+        r = int(np.prod(self.dims[: self.split], dtype=np.int64))
+        c = int(np.prod(self.dims[self.split:], dtype=np.int64))
+        return (r, c)
+
+    def to_host(self):
+        return (self.rowptr.cpu().numpy(), self.col.cpu().numpy(), self.val.cpu().numpy())
+
+
+@dataclass
+class COO:
+    """Index-value pairs: linearized keys (last mode fastest) and values."""
+    keys: torch.Tensor
+    val: torch.Tensor
+    dims: tuple
+
+
+def csr_from_host(rowptr, col, val, dims, device="cuda", split=1) -> CSR:
+    return CSR(torch.as_tensor(np.ascontiguousarray(rowptr, dtype=np.int64), device=device),
+               torch.as_tensor(np.ascontiguousarray(col, dtype=np.int32), device=device),
+               torch.as_tensor(np.ascontiguousarray(val), device=device), tuple(int(d) for d in dims), split)
+
+
+def _dt(t: torch.Tensor) -> int:
+    try:
+        return _TORCH_TO_DT[t.dtype]
+    except KeyError:
+        raise SrtcError(-4, f"unsupported value type {t.dtype}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None or t.numel() == 0:
+        return None
+    if not t.is_contiguous():
+        raise SrtcError(-1, "tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _desc(x) -> _Tensor:
+    d = _Tensor()
+    if isinstance(x, CSR):
+        d.order = len(x.dims)
+        d.format = CSR_FMT
+        d.dtype = _dt(x.val)
+        d.split = x.split
+        for i, v in enumerate(x.dims):
+            d.dims[i] = int(v)
+        d.nnz = x.nnz
+        d.rowptr = _ptr(x.rowptr)
+        d.colidx = _ptr(x.col)
+        d.vals = _ptr(x.val)
+    elif isinstance(x, COO):
+        d.order = len(x.dims)
+        d.format = COO_FMT
+        d.dtype = _dt(x.val)
+        for i, v in enumerate(x.dims):
+            d.dims[i] = int(v)
+        d.nnz = int(x.keys.numel())
+        d.coo_keys = _ptr(x.keys)
+        d.vals = _ptr(x.val)
+    elif isinstance(x, torch.Tensor):
+        d.order = x.dim()
+        d.format = DENSE
+        d.dtype = _dt(x)
+        for i, v in enumerate(x.shape):
+            d.dims[i] = int(v)
+        d.vals = _ptr(x)
+    else:
+        raise SrtcError(-1, f"not a tensor: {type(x)}")
+    return d
+
+
+def _add_id(add_id, dtype):
+    if add_id is None:
+        return None
+    return ctypes.byref(_DT_CTYPE[dtype](add_id))
+
+
+def _sr(semiring) -> int:
+    if isinstance(semiring, str):
+        return SEMIRINGS[semiring]
+    return int(semiring)
+
+
+class Context:
+    """A library context on one device; device buffers it returns are torch
+    tensors allocated on that device."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        self._live = {}
+        live = self._live
+        dev = self.device
+
+        def _a(user, nbytes):
+            t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
+            p = t.data_ptr()
+            live[p] = t
+            return p
+
+        def _f(user, ptr):
+            live.pop(ptr, None)
+
+        self._cb = (_ALLOC(_a), _FREE(_f))
+        h = ctypes.c_void_p()
+        st = lib().srtc_ctx_create(device, self._cb[0], self._cb[1], None, ctypes.byref(h))
+        if st != 0:
+            raise SrtcError(st, "context creation failed")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.srtc_ctx_destroy(h)
+            self._h = None
+
+    # -------------------------------------------------------- internals --
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _check(self, st, extra=None):
+        if st != 0:
+            msg = lib().srtc_last_error(self._h).decode()
+            if st == -8:
+                raise NotConverged(st, msg, extra)
+            raise SrtcError(st, msg)
+
+    def _take(self, ptr, count, dtype, base=None, offset_bytes=0):
+        """Torch tensor over library output memory (owned via the callback)."""
+        if base is None:
+            t = self._live.pop(ptr)
+            offset_bytes = 0
+        else:
+            t = base
+        esize = torch.empty((), dtype=dtype).element_size()
+        if count == 0:
+            return torch.empty(0, dtype=dtype, device=self.device)
+        return t[offset_bytes: offset_bytes + count * esize].view(dtype)
+
+    def _csr_out(self, d: _Tensor) -> CSR:
+        order = d.order
+        dims = tuple(int(d.dims[i]) for i in range(order))
+        rows = int(np.prod(dims[: d.split], dtype=np.int64))
+        rp = self._take(d.rowptr, rows + 1, torch.int64)
+        col = self._take(d.colidx, d.nnz, torch.int32) if d.nnz else self._drop(d.colidx, torch.int32)
+        val = self._take(d.vals, d.nnz, _DT_TO_TORCH[d.dtype]) if d.nnz else self._drop(d.vals, _DT_TO_TORCH[d.dtype])
+        return CSR(rp, col, val, dims, d.split)
+
+    def _drop(self, ptr, dtype):
+        if ptr:
+            self._live.pop(ptr, None)
+        return torch.empty(0, dtype=dtype, device=self.device)
+
+    # --------------------------------------------------------------- API --
+    def fold(self, semiring, src, isrc: str, rows: str, cols: str, add_id=None) -> CSR:
+        """Fold a COO/CSR tensor into a CSR matrix (rows/cols name its modes)."""
+        sd = _desc(src)
+        out = _Tensor()
+        st = lib().srtc_fold(self._h, _sr(semiring), _add_id(add_id, sd.dtype), isrc.encode(), ctypes.byref(sd),
+                             rows.encode(), cols.encode(), ctypes.byref(out), self._stream())
+        self._check(st)
+        return self._csr_out(out)
+
+    def contract(self, semiring, ia: str, A, ib: str, B, ic: str, C=None, accumulate=False, add_id=None,
+                 schedule: int = -1, sorted: bool = True, out_dims=None):
+        """C[ic] (+)= A[ia] (x) B[ib].  Sparse x sparse returns a CSR; with a
+        dense operand C must be a preallocated dense tensor (returned)."""
+        ad, bd = _desc(A), _desc(B)
+        opts = _Opts(schedule, 1 if sorted else 0, 0, 0)
+        if C is None:
+            # sparse result: dims of C from the index strings
+            ext = {}
+            for s_, t in ((ia, A), (ib, B)):
+                dims = t.dims if not isinstance(t, torch.Tensor) else tuple(t.shape)
+                for ch, e in zip(s_, dims):
+                    ext[ch] = int(e)
+            cd = _Tensor()
+            cd.order = len(ic)
+            cd.format = CSR_FMT
+            cd.dtype = ad.dtype
+            for i, ch in enumerate(ic):
+                cd.dims[i] = ext.get(ch, 1)
+        else:
+            cd = _desc(C)
+        st = lib().srtc_contract(self._h, _sr(semiring), _add_id(add_id, ad.dtype), int(bool(accumulate)),
+                                 ia.encode(), ctypes.byref(ad), ib.encode(), ctypes.byref(bd), ic.encode(),
+                                 ctypes.byref(cd), ctypes.byref(opts), self._stream())
+        self._check(st)
+        if C is None or isinstance(C, CSR):
+            return self._csr_out(cd)
+        return C
+
+    def fixpoint(self, semiring, A: CSR, X: torch.Tensor, max_iters: int = 0, steps_per_check: int = 4,
+                 add_id=None) -> int:
+        """X <- X (+) A (x) X until unchanged (in place); returns the step count."""
+        ad, xd = _desc(A), _desc(X)
+        it = ctypes.c_int64(0)
+        st = lib().srtc_fixpoint(self._h, _sr(semiring), _add_id(add_id, ad.dtype), ctypes.byref(ad),
+                                 ctypes.byref(xd), int(max_iters), int(steps_per_check), ctypes.byref(it),
+                                 self._stream())
+        self._check(st, it.value)
+        return it.value
+
+    def bfs_levels(self, A: CSR, sources: Sequence[int]):
+        """Levels (n x nsrc int32, -1 unreachable) and depth of a multi-source BFS."""
+        src = np.ascontiguousarray(sources, dtype=np.int64)
+        n = A.shape[0]
+        levels = torch.empty((n, src.size), dtype=torch.int32, device=self.device)
+        depth = ctypes.c_int32(0)
+        ad = _desc(A)
+        st = lib().srtc_bfs_levels(self._h, ctypes.byref(ad), src.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   int(src.size), _ptr(levels), ctypes.byref(depth), self._stream())
+        self._check(st)
+        return levels, depth.value
+
+    def batch_contract(self, semiring, As: List[CSR], Bs: List[CSR], add_id=None, schedule: int = -1,
+                       sorted: bool = True) -> List[CSR]:
+        """C_b = A_b (x) B_b for every instance in one set of launches."""
+        n = len(As)
+        arrA = (_Tensor * n)(*[_desc(a) for a in As])
+        arrB = (_Tensor * n)(*[_desc(b) for b in Bs])
+        arrC = (_Tensor * n)()
+        opts = _Opts(schedule, 1 if sorted else 0, 0, 0)
+        st = lib().srtc_batch_contract(self._h, _sr(semiring), _add_id(add_id, arrA[0].dtype), n, arrA, arrB, arrC,
+                                       ctypes.byref(opts), self._stream())
+        self._check(st)
+        c0 = arrC[0]
+        base_rp = self._live.pop(c0.rowptr)
+        base_col = self._live.pop(c0.colidx)
+        base_val = self._live.pop(c0.vals)
+        dt = _DT_TO_TORCH[c0.dtype]
+        es = torch.empty((), dtype=dt).element_size()
+        out = []
+        for b in range(n):
+            d = arrC[b]
+            rows = int(d.dims[0])
+            rp = self._take(None, rows + 1, torch.int64, base_rp, d.rowptr - c0.rowptr)
+            col = self._take(None, d.nnz, torch.int32, base_col, d.colidx - c0.colidx)
+            val = self._take(None, d.nnz, dt, base_val, d.vals - c0.vals)
+            out.append(CSR(rp, col, val, (int(d.dims[0]), int(d.dims[1])), 1, [base_rp, base_col, base_val]))
+        return out
+
+    def batch_fixpoint(self, semiring, As: List[CSR], Xs: List[torch.Tensor], max_iters: int = 0,
+                       steps_per_check: int = 4, add_id=None) -> List[int]:
+        n = len(As)
+        arrA = (_Tensor * n)(*[_desc(a) for a in As])
+        arrX = (_Tensor * n)(*[_desc(x) for x in Xs])
+        iters = (ctypes.c_int64 * n)()
+        st = lib().srtc_batch_fixpoint(self._h, _sr(semiring), _add_id(add_id, arrA[0].dtype), n, arrA, arrX,
+                                       int(max_iters), int(steps_per_check), iters, self._stream())
+        self._check(st, list(iters))
+        return list(iters)
+
+    def features(self, semiring, A: CSR, B: CSR) -> np.ndarray:
+        out = (ctypes.c_float * NUM_FEATURES)()
+        ad, bd = _desc(A), _desc(B)
+        st = lib().srtc_features(self._h, _sr(semiring), ctypes.byref(ad), ctypes.byref(bd), out, self._stream())
+        self._check(st)
+        return np.array(out[:], dtype=np.float32)
+
+    def autotune(self, semiring, A: CSR, B: CSR, reps: int = 10, add_id=None):
+        """(best schedule, median ms per schedule)."""
+        ad, bd = _desc(A), _desc(B)
+        best = ctypes.c_int32(-1)
+        times = (ctypes.c_float * NUM_SCHEDULES)()
+        st = lib().srtc_autotune(self._h, _sr(semiring), _add_id(add_id, ad.dtype), ctypes.byref(ad),
+                                 ctypes.byref(bd), int(reps), ctypes.byref(best), times, self._stream())
+        self._check(st)
+        return best.value, np.array(times[:], dtype=np.float32)
+
+    def select(self, features) -> int:
+        f = np.ascontiguousarray(features, dtype=np.float32)
+        out = ctypes.c_int32(-1)
+        st = lib().srtc_select(self._h, f.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(out))
+        self._check(st)
+        return out.value
+
+    def selector_train(self, X, T, epochs=200, batch=128, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                       seed=0) -> float:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        cfg = _TrainCfg(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps), int(seed))
+        loss = ctypes.c_float(0)
+        st = lib().srtc_selector_train(self._h, X.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                       T.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(X.shape[0]),
+                                       ctypes.byref(cfg), ctypes.byref(loss), self._stream())
+        self._check(st)
+        return loss.value
+
+    def selector_save(self, path: str):
+        self._check(lib().srtc_selector_save(self._h, path.encode()))
+
+    def selector_load(self, path: str):
+        self._check(lib().srtc_selector_load(self._h, path.encode()))
+
+    def mlp_forward(self, params: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+        Y = torch.empty((X.shape[0], NUM_SCHEDULES), dtype=torch.float32, device=self.device)
+        self._check(lib().srtc_mlp_forward(self._h, _ptr(params), _ptr(X), int(X.shape[0]), _ptr(Y),
+                                           self._stream()))
+        return Y
+
+    def mlp_loss_grad(self, params: torch.Tensor, X: torch.Tensor, T: torch.Tensor):
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        grads = torch.empty_like(params)
+        self._check(lib().srtc_mlp_loss_grad(self._h, _ptr(params), _ptr(X), _ptr(T), int(X.shape[0]),
+                                             _ptr(loss), _ptr(grads), self._stream()))
+        return loss, grads
+
+
+def mlp_num_params() -> int:
+    return int(lib().srtc_mlp_num_params())
+
+
+_default = None
+
+
+def context() -> Context:
+    """A process-wide context on cuda:0."""
+    global _default
+    if _default is None:
+        _default = Context(0)
+    return _default

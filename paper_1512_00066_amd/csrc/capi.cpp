@@ -1,0 +1,637 @@
+// C-ABI entry points of libsrtc (declared in include/srtc.h).
+//
+// This layer validates arguments, turns index strings into a fold plan
+// (Section 5.1: each index of a contraction is a batch, row, inner or column
+// index according to which tensors carry it, Section 3.3.1), and dispatches
+// to the kernels.  No exception crosses the ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "spmm_plan.hpp"
+
+namespace srtc {
+
+// ------------------------------------------------------------- memory --
+void *Ctx::raw_alloc(size_t bytes, int kind) {
+  if (bytes == 0) bytes = 1;
+  void *p = nullptr;
+  if (kind == OUTPUT && alloc) {
+    p = alloc(user, bytes);
+  } else if (kind == OUTPUT) {
+    if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  } else {
+    if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
+  }
+  if (!p) fail(SRTC_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  return p;
+}
+
+void Ctx::raw_free(void *p, int kind) {
+  if (!p) return;
+  if (kind == OUTPUT) {
+    if (free_fn) free_fn(user, p);
+    else (void)hipFree(p);
+  } else {
+    (void)hipFreeAsync(p, stream);
+  }
+}
+
+void *Ctx::host_scratch(size_t bytes) {
+  if (bytes > pinned_bytes) {
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    size_t nb = std::max<size_t>(bytes, 1 << 16);
+    SRTC_HIP(hipHostMalloc(&pinned, nb, hipHostMallocDefault));
+    pinned_bytes = nb;
+  }
+  return pinned;
+}
+
+Buf::Buf(Ctx *c, size_t n, int k) : ctx(c), p(nullptr), bytes(n), kind(k) { p = c->raw_alloc(n, k); }
+Buf &Buf::operator=(Buf &&o) noexcept {
+  if (this != &o) {
+    if (p && ctx) ctx->raw_free(p, kind);
+    ctx = o.ctx;
+    p = o.p;
+    bytes = o.bytes;
+    kind = o.kind;
+    o.p = nullptr;
+  }
+  return *this;
+}
+Buf::~Buf() {
+  if (p && ctx) ctx->raw_free(p, kind);
+}
+
+void mlp_destroy(Mlp *m);  // mlp.hip
+
+namespace {
+
+// ------------------------------------------------------------ helpers --
+bool semiring_ok(int sr, int dt) {
+  switch (sr) {
+    case SRTC_PLUS_TIMES: return dt == SRTC_F64 || dt == SRTC_F32;
+    case SRTC_MIN_PLUS: return dt == SRTC_I32 || dt == SRTC_F32;
+    case SRTC_OR_AND: return dt == SRTC_BOOL8;
+    case SRTC_MAX_TIMES: return dt == SRTC_F32 || dt == SRTC_F64;
+  }
+  return false;
+}
+
+// The additive identity: the caller's value or the default (Section 3.1).
+IdVal make_id(int sr, int dt, const void *add_id) {
+  if (sr < 0 || sr > 3) fail(SRTC_ERR_ARG, "unknown semiring");
+  if (!semiring_ok(sr, dt)) fail(SRTC_ERR_DTYPE, "value type not defined for this semiring");
+  IdVal v{0.0, 0};
+  switch (sr) {
+    case SRTC_PLUS_TIMES: {
+      double x = 0.0;
+      if (add_id) x = dt == SRTC_F64 ? *(const double *)add_id : (double)*(const float *)add_id;
+      if (x != 0.0) fail(SRTC_ERR_ARG, "(+,x) additive identity must be 0");
+      break;
+    }
+    case SRTC_MIN_PLUS:
+      if (dt == SRTC_I32) {
+        v.i = add_id ? *(const int32_t *)add_id : (int32_t)(INT32_MAX / 2);
+        if (v.i <= 0) fail(SRTC_ERR_ARG, "(min,+) int identity must be positive");
+      } else {
+        v.f = add_id ? (double)*(const float *)add_id : (double)std::numeric_limits<float>::infinity();
+      }
+      break;
+    case SRTC_OR_AND:
+      if (add_id && *(const uint8_t *)add_id != 0) fail(SRTC_ERR_ARG, "(or,and) identity must be false");
+      break;
+    case SRTC_MAX_TIMES:
+      if (add_id) v.f = dt == SRTC_F64 ? *(const double *)add_id : (double)*(const float *)add_id;
+      break;
+  }
+  return v;
+}
+
+int64_t prod_dims(const srtc_tensor *t) {
+  int64_t p = 1;
+  for (int i = 0; i < t->order; i++) p *= t->dims[i];
+  return p;
+}
+
+void check_tensor(const srtc_tensor *t, const char *name) {
+  if (!t) fail(SRTC_ERR_ARG, std::string(name) + ": null tensor");
+  if (t->order < 0 || t->order > SRTC_MAX_ORDER) fail(SRTC_ERR_ARG, std::string(name) + ": bad order");
+  for (int i = 0; i < t->order; i++)
+    if (t->dims[i] <= 0) fail(SRTC_ERR_DIM, std::string(name) + ": nonpositive dimension");
+  if (t->format < SRTC_DENSE || t->format > SRTC_CSR) fail(SRTC_ERR_ARG, std::string(name) + ": bad format");
+  if (t->format != SRTC_DENSE && t->nnz < 0) fail(SRTC_ERR_ARG, std::string(name) + ": negative nnz");
+  if (t->format == SRTC_COO && t->nnz > 0 && (!t->coo_keys || !t->vals))
+    fail(SRTC_ERR_ARG, std::string(name) + ": COO without keys/values");
+  if (t->format == SRTC_CSR) {
+    if (!t->rowptr) fail(SRTC_ERR_ARG, std::string(name) + ": CSR without rowptr");
+    if (t->nnz > 0 && (!t->colidx || !t->vals)) fail(SRTC_ERR_ARG, std::string(name) + ": CSR without cols/values");
+    if (t->split < 0 || t->split > t->order) fail(SRTC_ERR_ARG, std::string(name) + ": bad split");
+  }
+  if (t->format == SRTC_DENSE && prod_dims(t) > 0 && !t->vals) fail(SRTC_ERR_ARG, std::string(name) + ": no values");
+}
+
+std::string letters(const char *s, const srtc_tensor *t, const char *name) {
+  if (!s) fail(SRTC_ERR_INDEX, std::string(name) + ": null index string");
+  std::string r(s);
+  if ((int)r.size() != t->order) fail(SRTC_ERR_INDEX, std::string(name) + ": index string length differs from order");
+  for (size_t i = 0; i < r.size(); i++)
+    for (size_t j = i + 1; j < r.size(); j++)
+      if (r[i] == r[j]) fail(SRTC_ERR_INDEX, std::string(name) + ": repeated index (diagonals are not supported)");
+  return r;
+}
+
+int64_t row_extent(const srtc_tensor *t) {
+  int64_t r = 1;
+  for (int i = 0; i < t->split; i++) r *= t->dims[i];
+  return r;
+}
+
+CsrView csr_view(const srtc_tensor *t) {
+  CsrView v;
+  v.m = row_extent(t);
+  v.n = 1;
+  for (int i = t->split; i < t->order; i++) v.n *= t->dims[i];
+  v.nnz = t->nnz;
+  v.rowptr = t->rowptr;
+  v.col = t->colidx;
+  v.val = t->vals;
+  return v;
+}
+
+// Fold a sparse tensor (COO or CSR) to a CSR matrix with the given row and
+// column letters; returns a view (borrowed if the layout already matches).
+struct Folded {
+  CsrOut own;
+  CsrView view;
+  bool owned = false;
+};
+
+void fold_sparse(Ctx *c, int sr, IdVal id, const srtc_tensor *t, const std::string &idx, const std::string &rows,
+                 const std::string &cols, Folded *f, hipStream_t s, bool force = false) {
+  if (!force && t->format == SRTC_CSR && idx == rows + cols && t->split == (int)rows.size()) {
+    f->view = csr_view(t);
+    f->owned = false;
+    return;
+  }
+  std::vector<int> rm, cm;
+  for (char ch : rows) rm.push_back((int)idx.find(ch));
+  for (char ch : cols) cm.push_back((int)idx.find(ch));
+  int64_t nr = 1, nc = 1;
+  for (int q : rm) nr *= t->dims[q];
+  for (int q : cm) nc *= t->dims[q];
+  const int64_t nnz = t->nnz;
+  Buf keys(c, sizeof(int64_t) * (size_t)std::max<int64_t>(nnz, 1));
+  const int64_t *src_keys = t->coo_keys;
+  Buf tmp;
+  if (t->format == SRTC_CSR) {
+    CsrView v = csr_view(t);
+    tmp = Buf(c, sizeof(int64_t) * (size_t)std::max<int64_t>(nnz, 1));
+    csr_to_keys(v, tmp.as<int64_t>(), s);
+    src_keys = tmp.as<int64_t>();
+  }
+  remap_keys(c, src_keys, nnz, t->order, t->dims, (int)rm.size(), rm.data(), (int)cm.size(), cm.data(),
+             keys.as<int64_t>(), s);
+  if (!force) f->own.kind = SCRATCH;
+  fold_keys_to_csr(c, sr, t->dtype, id, keys.as<int64_t>(), t->vals, nnz, nr, nc, &f->own, s);
+  f->owned = true;
+  f->view.m = f->own.m;
+  f->view.n = f->own.n;
+  f->view.nnz = f->own.nnz;
+  f->view.rowptr = f->own.rowptr.as<int64_t>();
+  f->view.col = f->own.col.as<int32_t>();
+  f->view.val = f->own.val.p;
+}
+
+void set_csr_out(srtc_tensor *out, CsrOut &o, int order, const int64_t *dims, int split, int dtype) {
+  out->order = order;
+  for (int i = 0; i < SRTC_MAX_ORDER; i++) out->dims[i] = i < order ? dims[i] : 0;
+  out->format = SRTC_CSR;
+  out->dtype = dtype;
+  out->split = split;
+  out->nnz = o.nnz;
+  out->coo_keys = nullptr;
+  out->rowptr = (int64_t *)o.rowptr.release();
+  out->colidx = (int32_t *)o.col.release();
+  out->vals = o.val.release();
+}
+
+bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
+  if (!a || !b || an == 0 || bn == 0) return false;
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + bn && y < x + an;
+}
+
+size_t tensor_value_bytes(const srtc_tensor *t) {
+  const size_t es = dtype_size(t->dtype);
+  if (t->format == SRTC_DENSE) return es * (size_t)prod_dims(t);
+  return es * (size_t)t->nnz;
+}
+
+__global__ void col_mod_kernel(int32_t *col, int64_t n, int64_t mod) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    col[i] = (int32_t)(col[i] % mod);
+}
+
+// ------------------------------------------------------------- planning --
+struct Plan {
+  std::string batch, M, K, N;  // letters
+  std::map<char, int64_t> dim;
+};
+
+Plan plan_contraction(const std::string &a, const srtc_tensor *A, const std::string &b, const srtc_tensor *B,
+                      const std::string &cidx, const srtc_tensor *C) {
+  Plan p;
+  auto add_dims = [&](const std::string &s, const srtc_tensor *t) {
+    for (size_t i = 0; i < s.size(); i++) {
+      auto it = p.dim.find(s[i]);
+      if (it == p.dim.end()) p.dim[s[i]] = t->dims[i];
+      else if (it->second != t->dims[i]) fail(SRTC_ERR_DIM, std::string("index '") + s[i] + "' has two extents");
+    }
+  };
+  add_dims(a, A);
+  add_dims(b, B);
+  add_dims(cidx, C);
+  for (char ch : cidx) {
+    const bool ia = a.find(ch) != std::string::npos, ib = b.find(ch) != std::string::npos;
+    if (ia && ib) p.batch += ch;
+    else if (ia) p.M += ch;
+    else if (ib) p.N += ch;
+    else fail(SRTC_ERR_INDEX, std::string("index '") + ch + "' appears only in the output");
+  }
+  for (char ch : a) {
+    const bool ib = b.find(ch) != std::string::npos, ic = cidx.find(ch) != std::string::npos;
+    if (ib && !ic) p.K += ch;
+    else if (!ib && !ic) fail(SRTC_ERR_INDEX, std::string("index '") + ch + "' appears only in A (reduction)");
+  }
+  for (char ch : b)
+    if (a.find(ch) == std::string::npos && cidx.find(ch) == std::string::npos)
+      fail(SRTC_ERR_INDEX, std::string("index '") + ch + "' appears only in B (reduction)");
+  // C: every column letter after every row letter
+  size_t last_row = 0, first_col = cidx.size();
+  for (size_t i = 0; i < cidx.size(); i++) {
+    if (p.N.find(cidx[i]) != std::string::npos) first_col = std::min(first_col, i);
+    else last_row = i + 1;
+  }
+  if (!p.N.empty() && first_col < last_row)
+    fail(SRTC_ERR_UNSUPPORTED, "output index order interleaves row and column indices");
+  return p;
+}
+
+int64_t extent(const Plan &p, const std::string &s) {
+  int64_t e = 1;
+  for (char ch : s) e *= p.dim.at(ch);
+  return e;
+}
+
+std::string rows_of_c(const std::string &cidx, const Plan &p) {
+  std::string r;
+  for (char ch : cidx)
+    if (p.N.find(ch) == std::string::npos) r += ch;
+  return r;
+}
+
+__global__ void bfs_init(const int64_t *src, int nsrc, uint64_t *front, uint64_t *visited, int32_t *levels) {
+  const int t = threadIdx.x;
+  if (t < nsrc) {
+    atomicOr((unsigned long long *)&front[src[t]], 1ull << t);
+    atomicOr((unsigned long long *)&visited[src[t]], 1ull << t);
+    levels[src[t] * nsrc + t] = 0;
+  }
+}
+
+}  // namespace
+
+IdVal make_id_public(int sr, int dt, const void *add_id) { return make_id(sr, dt, add_id); }
+
+std::string tune_key(int sr, int dt, const float *f) {
+  std::string k = std::to_string(sr) + ":" + std::to_string(dt);
+  char buf[32];
+  for (int q = 0; q < SRTC_NUM_FEATURES; q++) {
+    snprintf(buf, sizeof(buf), ":%.3g", (double)f[q]);
+    k += buf;
+  }
+  return k;
+}
+
+}  // namespace srtc
+
+using namespace srtc;
+
+extern "C" {
+
+const char *srtc_status_string(srtc_status st) {
+  switch (st) {
+    case SRTC_OK: return "ok";
+    case SRTC_ERR_ARG: return "invalid argument";
+    case SRTC_ERR_INDEX: return "invalid index string";
+    case SRTC_ERR_DIM: return "dimension mismatch";
+    case SRTC_ERR_DTYPE: return "value type not defined for the semiring";
+    case SRTC_ERR_FORMAT: return "malformed sparse operand";
+    case SRTC_ERR_ALIAS: return "output overlaps an input";
+    case SRTC_ERR_OOM: return "out of memory";
+    case SRTC_ERR_NOT_CONVERGED: return "fixpoint not reached";
+    case SRTC_ERR_UNSUPPORTED: return "unsupported";
+    case SRTC_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+srtc_status srtc_ctx_create(int device, srtc_alloc_fn alloc, srtc_free_fn free_fn, void *user, srtc_ctx **out) {
+  if (!out) return SRTC_ERR_ARG;
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return SRTC_ERR_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SRTC_ERR_DEVICE;
+  srtc_ctx *c = new (std::nothrow) srtc_ctx();
+  if (!c) return SRTC_ERR_OOM;
+  c->c.device = device;
+  c->c.alloc = alloc;
+  c->c.free_fn = free_fn;
+  c->c.user = user;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    c->c.num_cus = prop.multiProcessorCount;
+    c->c.lds_per_block = prop.sharedMemPerBlock;
+  }
+  // keep freed scratch in the device's stream-ordered pool
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  *out = c;
+  return SRTC_OK;
+}
+
+srtc_status srtc_ctx_destroy(srtc_ctx *ctx) {
+  if (!ctx) return SRTC_ERR_ARG;
+  if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
+  mlp_destroy(ctx->c.mlp);
+  delete ctx;
+  return SRTC_OK;
+}
+
+const char *srtc_last_error(const srtc_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+srtc_status srtc_fold(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const char *isrc, const srtc_tensor *src,
+                      const char *rows, const char *cols, srtc_tensor *out, void *stream) {
+  return guard(ctx, [&] {
+    check_tensor(src, "src");
+    if (!out) fail(SRTC_ERR_ARG, "out: null");
+    if (src->format == SRTC_DENSE) fail(SRTC_ERR_UNSUPPORTED, "fold takes a sparse (COO/CSR) tensor");
+    const std::string idx = letters(isrc, src, "src");
+    if (!rows || !cols) fail(SRTC_ERR_INDEX, "null row/col string");
+    const std::string r(rows), cl(cols);
+    std::string all = r + cl;
+    if (all.size() != idx.size()) fail(SRTC_ERR_INDEX, "rows+cols must name every source index once");
+    for (char ch : all)
+      if (idx.find(ch) == std::string::npos || std::count(all.begin(), all.end(), ch) != 1)
+        fail(SRTC_ERR_INDEX, "rows+cols must name every source index once");
+    const IdVal id = make_id(sr, src->dtype, add_id);
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    Folded f;
+    fold_sparse(&ctx->c, sr, id, src, idx, r, cl, &f, s, true);
+    int64_t dims[SRTC_MAX_ORDER];
+    for (size_t q = 0; q < all.size(); q++) dims[q] = src->dims[idx.find(all[q])];
+    set_csr_out(out, f.own, (int)all.size(), dims, (int)r.size(), src->dtype);
+  });
+}
+
+srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int accumulate, const char *ia,
+                          const srtc_tensor *A, const char *ib, const srtc_tensor *B, const char *ic, srtc_tensor *C,
+                          const srtc_opts *opts, void *stream) {
+  return guard(ctx, [&] {
+    check_tensor(A, "A");
+    check_tensor(B, "B");
+    if (!C) fail(SRTC_ERR_ARG, "C: null");
+    if (C->order < 0 || C->order > SRTC_MAX_ORDER) fail(SRTC_ERR_ARG, "C: bad order");
+    const std::string a = letters(ia, A, "A"), b = letters(ib, B, "B"), cidx = letters(ic, C, "C");
+    if (A->dtype != B->dtype) fail(SRTC_ERR_DTYPE, "A and B value types differ");
+    const int dt = A->dtype;
+    const IdVal id = make_id(sr, dt, add_id);
+    const Plan p = plan_contraction(a, A, b, B, cidx, C);
+    srtc_opts o{-1, 1, 0, 0};
+    if (opts) o = *opts;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    Ctx *c = &ctx->c;
+    const std::string crow = rows_of_c(cidx, p);  // batch + M letters in C order
+    std::string acol = p.batch, brow = p.batch, bcol = p.batch;
+    acol += p.K;
+    brow += p.K;
+    bcol += p.N;
+    const bool a_sparse = A->format != SRTC_DENSE, b_sparse = B->format != SRTC_DENSE;
+    if (a_sparse && b_sparse) {
+      if (C->format == SRTC_DENSE) fail(SRTC_ERR_UNSUPPORTED, "sparse x sparse gives a sparse (CSR) C");
+      Folded fa, fb;
+      fold_sparse(c, sr, id, A, a, crow, acol, &fa, s);
+      fold_sparse(c, sr, id, B, b, brow, bcol, &fb, s);
+      int sched = o.schedule;
+      if (sched >= SRTC_NUM_SCHEDULES) fail(SRTC_ERR_ARG, "schedule id out of range");
+      if (sched < 0) {
+        // autotune cache first, then the learned selector, else the default
+        sched = 0;
+        if (c->mlp || !c->tune_cache.empty()) {
+          float feat[SRTC_NUM_FEATURES];
+          spgemm_features(c, sr, dt, fa.view, fb.view, feat, s);
+          auto hit = c->tune_cache.find(tune_key(sr, dt, feat));
+          int32_t pick = 0;
+          if (hit != c->tune_cache.end()) sched = hit->second;
+          else if (c->mlp && srtc_select(ctx, feat, &pick) == SRTC_OK) sched = pick;
+        }
+      }
+      CsrOut t;
+      SpgemmStats st;
+      spgemm(c, sr, dt, id, fa.view, fb.view, sched, o.sorted, &t, &st, s);
+      if (!p.batch.empty() && t.nnz > 0) {
+        col_mod_kernel<<<4096, 256, 0, s>>>(t.col.as<int32_t>(), t.nnz, extent(p, p.N));
+        SRTC_LAUNCH_CHECK("col_mod_kernel");
+      }
+      t.n = extent(p, p.N);
+      if (accumulate && C->format == SRTC_CSR && C->nnz > 0) {
+        // previous C joins the sum: C_new = C_old (+) T (old entries first)
+        if (C->split != (int)crow.size()) fail(SRTC_ERR_FORMAT, "C: split differs from the row indices");
+        CsrView cv = csr_view(C);
+        CsrView tv{t.m, t.n, t.nnz, t.rowptr.as<int64_t>(), t.col.as<int32_t>(), t.val.p};
+        CsrOut u;
+        ewise_add(c, sr, dt, id, cv, tv, &u, s);
+        t = std::move(u);
+      }
+      int64_t dims[SRTC_MAX_ORDER];
+      for (size_t q = 0; q < cidx.size(); q++) dims[q] = p.dim.at(cidx[q]);
+      set_csr_out(C, t, (int)cidx.size(), dims, (int)crow.size(), dt);
+      return;
+    }
+    if (C->format != SRTC_DENSE) fail(SRTC_ERR_UNSUPPORTED, "a dense operand gives a dense C");
+    if (C->dtype != dt) fail(SRTC_ERR_DTYPE, "C value type differs");
+    if (!C->vals) fail(SRTC_ERR_ARG, "C: no values");
+    const size_t cbytes = tensor_value_bytes(C);
+    if (overlaps(C->vals, cbytes, A->vals, tensor_value_bytes(A)) ||
+        overlaps(C->vals, cbytes, B->vals, tensor_value_bytes(B)))
+      fail(SRTC_ERR_ALIAS, "C overlaps an operand");
+    // dense B must be laid out as (batch, K) rows x N columns
+    auto dense_in_order = [&](const srtc_tensor *T, const std::string &idx, const std::string &want, Buf *tmp)
+        -> const void * {
+      if (idx == want) return T->vals;
+      std::vector<int> perm;
+      for (char ch : want) perm.push_back((int)idx.find(ch));
+      *tmp = Buf(c, tensor_value_bytes(T));
+      dense_permute(T->vals, tmp->p, (int)dtype_size(dt), T->order, T->dims, perm.data(), s);
+      return tmp->p;
+    };
+    if (a_sparse && !b_sparse) {
+      Folded fa;
+      fold_sparse(c, sr, id, A, a, crow, acol, &fa, s);
+      Buf tb;
+      const void *Bd = dense_in_order(B, b, brow + p.N, &tb);
+      spmm(c, sr, dt, id, fa.view, Bd, extent(p, p.N), C->vals, accumulate, s);
+      return;
+    }
+    if (!a_sparse && !b_sparse) {
+      if (sr != SRTC_PLUS_TIMES) fail(SRTC_ERR_UNSUPPORTED, "dense x dense is defined for (+,x) only");
+      if (!p.batch.empty()) fail(SRTC_ERR_UNSUPPORTED, "dense x dense with a batch index");
+      Buf ta, tb;
+      const void *Ad = dense_in_order(A, a, p.M + p.K, &ta);
+      const void *Bd = dense_in_order(B, b, p.K + p.N, &tb);
+      if (crow != p.M) fail(SRTC_ERR_UNSUPPORTED, "dense output row order");
+      dense_gemm_plus_times(c, dt, Ad, Bd, C->vals, extent(p, p.M), extent(p, p.N), extent(p, p.K), accumulate, s);
+      return;
+    }
+    fail(SRTC_ERR_UNSUPPORTED, "dense A with sparse B: swap the operands");
+  });
+}
+
+srtc_status srtc_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const srtc_tensor *A, srtc_tensor *X,
+                          int64_t max_iters, int32_t steps_per_check, int64_t *iters_out, void *stream) {
+  return guard(ctx, [&] {
+    check_tensor(A, "A");
+    check_tensor(X, "X");
+    if (A->format != SRTC_CSR || A->order != 2 || A->split != 1) fail(SRTC_ERR_FORMAT, "A must be a CSR matrix");
+    if (X->format != SRTC_DENSE || X->order < 1 || X->order > 2) fail(SRTC_ERR_FORMAT, "X must be a dense n or n x s array");
+    if (sr == SRTC_PLUS_TIMES) fail(SRTC_ERR_UNSUPPORTED, "fixpoint needs an idempotent semiring");
+    if (A->dtype != X->dtype) fail(SRTC_ERR_DTYPE, "A and X value types differ");
+    const int dt = A->dtype;
+    const IdVal id = make_id(sr, dt, add_id);
+    const int64_t n = A->dims[0];
+    if (A->dims[1] != n || X->dims[0] != n) fail(SRTC_ERR_DIM, "A must be n x n and X n x s");
+    const int64_t sw = X->order == 2 ? X->dims[1] : 1;
+    if (max_iters <= 0) max_iters = n;
+    int k = std::max(2, (int)steps_per_check);
+    if (k % 2) k++;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    Ctx *c = &ctx->c;
+    CsrView av = csr_view(A);
+    SpmmPlan pl;
+    pl.build(c, av, sw, s);
+    const size_t bytes = tensor_value_bytes(X);
+    Buf xb(c, bytes);
+    Buf flags(c, sizeof(int32_t) * (size_t)k);
+    void *xa = X->vals;
+    void *bufs[2] = {xa, xb.p};
+    auto step = [&](int t, int parity, hipStream_t st) {
+      fill_i32(flags.as<int32_t>() + t, 1, 0, st);
+      spmm_with_plan(pl, sr, dt, id, av, bufs[parity], sw, bufs[parity ^ 1], 1, 0, flags.as<int32_t>() + t,
+                     nullptr, nullptr, nullptr, st);
+    };
+    // capture k steps (k even: the iterate returns to X)
+    hipStream_t cap;
+    SRTC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct Cleanup {
+      hipStream_t *cap;
+      hipGraph_t *g;
+      hipGraphExec_t *e;
+      ~Cleanup() {
+        if (*e) (void)hipGraphExecDestroy(*e);
+        if (*g) (void)hipGraphDestroy(*g);
+        (void)hipStreamDestroy(*cap);
+      }
+    } cleanup{&cap, &graph, &exec};
+    SRTC_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    for (int t = 0; t < k; t++) step(t, t & 1, cap);
+    SRTC_HIP(hipStreamEndCapture(cap, &graph));
+    SRTC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    std::vector<int32_t> hf(k);
+    int64_t r = 0;
+    while (r < max_iters) {
+      int nsteps;
+      if (r + k <= max_iters) {
+        SRTC_HIP(hipGraphLaunch(exec, s));
+        nsteps = k;
+      } else {
+        nsteps = (int)(max_iters - r);
+        for (int t = 0; t < nsteps; t++) step(t, t & 1, s);
+        if (nsteps & 1) SRTC_HIP(hipMemcpyAsync(xa, xb.p, bytes, hipMemcpyDeviceToDevice, s));
+      }
+      read_to_host(c, hf.data(), flags.p, sizeof(int32_t) * (size_t)nsteps, s);
+      for (int t = 0; t < nsteps; t++) {
+        if (hf[t] == 0) {
+          if (iters_out) *iters_out = r + t + 1;
+          return;
+        }
+      }
+      r += nsteps;
+    }
+    if (iters_out) *iters_out = r;
+    fail(SRTC_ERR_NOT_CONVERGED, "still changing after max_iters steps");
+  });
+}
+
+srtc_status srtc_bfs_levels(srtc_ctx *ctx, const srtc_tensor *A, const int64_t *sources, int32_t nsrc, int32_t *levels,
+                            int32_t *depth_out, void *stream) {
+  return guard(ctx, [&] {
+    check_tensor(A, "A");
+    if (A->format != SRTC_CSR || A->order != 2 || A->split != 1) fail(SRTC_ERR_FORMAT, "A must be a CSR matrix");
+    if (nsrc < 1 || nsrc > 64) fail(SRTC_ERR_ARG, "1..64 sources");
+    if (!sources || !levels) fail(SRTC_ERR_ARG, "null sources/levels");
+    const int64_t n = A->dims[0];
+    if (A->dims[1] != n) fail(SRTC_ERR_DIM, "A must be square");
+    for (int t = 0; t < nsrc; t++)
+      if (sources[t] < 0 || sources[t] >= n) fail(SRTC_ERR_ARG, "source out of range");
+    for (int t = 0; t < nsrc; t++)
+      for (int u = t + 1; u < nsrc; u++)
+        if (sources[t] == sources[u]) fail(SRTC_ERR_ARG, "repeated source");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    Ctx *c = &ctx->c;
+    CsrView av = csr_view(A);
+    Buf fa(c, 8 * (size_t)n), fb(c, 8 * (size_t)n), vis(c, 8 * (size_t)n), src(c, 8 * 64), chg(c, 64);
+    fill_i64((int64_t *)fa.p, n, 0, s);
+    fill_i64((int64_t *)vis.p, n, 0, s);
+    fill_i32(levels, n * nsrc, -1, s);
+    int64_t *hs = (int64_t *)c->host_scratch(8 * 64);
+    memcpy(hs, sources, 8 * (size_t)nsrc);
+    SRTC_HIP(hipMemcpyAsync(src.p, hs, 8 * (size_t)nsrc, hipMemcpyHostToDevice, s));
+    bfs_init<<<1, 64, 0, s>>>(src.as<int64_t>(), nsrc, fa.as<uint64_t>(), vis.as<uint64_t>(), levels);
+    SRTC_LAUNCH_CHECK("bfs_init");
+    uint64_t *cur = fa.as<uint64_t>(), *nxt = fb.as<uint64_t>();
+    int32_t depth = 0;
+    for (int level = 1; level <= n; level++) {
+      fill_i32(chg.as<int32_t>(), 1, 0, s);
+      bfs_step(av, cur, vis.as<uint64_t>(), nxt, levels, nsrc, level, chg.as<int32_t>(), s);
+      int32_t h = 0;
+      read_to_host(c, &h, chg.p, sizeof(int32_t), s);
+      if (!h) break;
+      depth = level;
+      std::swap(cur, nxt);
+    }
+    if (depth_out) *depth_out = depth;
+  });
+}
+
+int64_t srtc_mlp_num_params(void) {
+  const int64_t K = SRTC_NUM_SCHEDULES;
+  return 64 * 32 + 64 + 64 * 64 + 64 + K * 64 + K;
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+// Host-side internal interfaces between the C-ABI layer and the kernels.
+#pragma once
+
+#include <map>
+#include <new>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace srtc {
+
+struct Mlp;  // selector network (mlp.hip)
+
+struct Ctx {
+  int device = 0;
+  srtc_alloc_fn alloc = nullptr;
+  srtc_free_fn free_fn = nullptr;
+  void *user = nullptr;
+  std::string err = "no error";
+  int num_cus = 256;
+  size_t lds_per_block = 65536;
+  // autotune cache: feature fingerprint -> schedule
+  std::map<std::string, int> tune_cache;
+  Mlp *mlp = nullptr;
+  // pinned host scratch for small device->host reads
+  void *pinned = nullptr;
+  size_t pinned_bytes = 0;
+  // stream of the call in progress (scratch memory is ordered on it)
+  hipStream_t stream = nullptr;
+
+  void *raw_alloc(size_t bytes, int kind);
+  void raw_free(void *p, int kind);
+  void *host_scratch(size_t bytes);
+};
+
+// A device CSR matrix view (not owning).
+struct CsrView {
+  int64_t m = 0, n = 0, nnz = 0;
+  const int64_t *rowptr = nullptr;
+  const int32_t *col = nullptr;
+  const void *val = nullptr;
+};
+
+// An owned CSR result (kind: OUTPUT for results handed to the caller,
+// SCRATCH for intermediates such as folded operands).
+struct CsrOut {
+  int64_t m = 0, n = 0, nnz = 0;
+  int kind = OUTPUT;
+  Buf rowptr, col, val;
+};
+
+// ---------------------------------------------------------------- prims --
+// out[i] = sum_{j<i} in[i]; out has n+1 entries (out[n] = total).  In = int32
+// or int64.  Returns nothing; total stays on device.
+void excl_scan_i64(Ctx *c, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+void excl_scan_i32(Ctx *c, const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+void fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
+void fill_bytes_value(void *p, int64_t n, int dtype, IdVal v, hipStream_t s);
+int64_t read_i64(Ctx *c, const int64_t *dev, hipStream_t s);
+void read_to_host(Ctx *c, void *host, const void *dev, size_t bytes, hipStream_t s);
+
+// ----------------------------------------------------------------- fold --
+// Keys (row*ncols + col, < 2^63) with values -> CSR, duplicates combined in
+// input order, identity entries dropped.  Synchronizes once.
+void fold_keys_to_csr(Ctx *c, int sr, int dt, IdVal id, const int64_t *keys, const void *vals,
+                      int64_t nnz, int64_t nrows, int64_t ncols, CsrOut *out, hipStream_t s);
+// Mode remap of linearized keys: out[t] = rowkey*ncols + colkey where the
+// row (col) key linearizes the listed source modes.
+void remap_keys(Ctx *c, const int64_t *keys, int64_t nnz, int order, const int64_t *dims,
+                int nrow_modes, const int *row_modes, int ncol_modes, const int *col_modes,
+                int64_t *out, hipStream_t s);
+// Expand a CSR matrix to linearized keys row*ncols+col.
+void csr_to_keys(const CsrView &a, int64_t *keys, hipStream_t s);
+// Stable LSD radix sort of 64-bit keys carrying a 32-bit payload (exposed
+// for tests through the fold).
+void radix_sort_pairs(Ctx *c, int64_t *keys, uint32_t *payload, int64_t n, int bits,
+                      hipStream_t s);
+
+// --------------------------------------------------------------- spgemm --
+struct Schedule {
+  // symbolic: rows with products <= sym_hash_max use an LDS hash, others a
+  // bitmap
+  int64_t sym_hash_max;
+  // numeric bins by exact row nnz: <= t_tiny (64-slot hash), <= t_small
+  // (512-slot hash), <= t_mid (4096-slot hash), <= t_big (8192-slot hash),
+  // above: dense LDS windows
+  int64_t t_tiny, t_small, t_mid, t_big;
+  int small_bitmap;  // 512-slot bin extracts through a bitmap (1) or a sort (0)
+  int dense_bs;      // dense-window block size (256 or 512)
+  int dense_wide;    // dense window of 16K (1) or 8K (0) 8-byte accumulators
+};
+const Schedule &schedule(int id);
+
+struct SpgemmStats {
+  int64_t products = 0;
+  int64_t nnz = 0;
+  int64_t dense_rows = 0;
+  int compacted = 0;
+};
+
+// C = A (x) B, output CSR with ascending columns (sorted=1) allocated from
+// the context.  Synchronizes once.
+void spgemm(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B, int sched,
+            int sorted, CsrOut *out, SpgemmStats *st, hipStream_t s);
+// Row product counts w_i (int64, m entries).
+void row_products(const CsrView &A, const CsrView &B, int64_t *w, hipStream_t s);
+// C = X (+) Y for two CSR matrices of the same shape (sorted rows); the
+// union of patterns, identity results dropped.  Synchronizes once.
+void ewise_add(Ctx *c, int sr, int dt, IdVal id, const CsrView &X, const CsrView &Y, CsrOut *out,
+               hipStream_t s);
+
+// ----------------------------------------------------------------- spmm --
+// Y[i,:] = [X0[i,:] (+)] (+)_k A_ik (x) X[k,:]; dense row-major width s.
+// accumulate: Y's previous contents join the sum.  changed (optional, device
+// int) is set to 1 if any Y entry differs from X0 (self-term form).
+void spmm(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const void *X, int64_t s_width,
+          void *Y, int accumulate, hipStream_t s);
+void bf_step(int sr, int dt, IdVal id, const CsrView &A, const void *X, void *Y, int64_t s_width,
+             int32_t *changed, const int32_t *row_inst, const uint8_t *inst_active,
+             int32_t *inst_changed, hipStream_t s);
+void bfs_step(const CsrView &A, const uint64_t *front, uint64_t *visited, uint64_t *next,
+              int32_t *levels, int nsrc, int level, int32_t *changed, hipStream_t s);
+
+// --------------------------------------------------------------- dense --
+void dense_gemm_plus_times(Ctx *c, int dt, const void *A, const void *B, void *C, int64_t M,
+                           int64_t N, int64_t K, int accumulate, hipStream_t s);
+void dense_permute(const void *src, void *dst, int esize, int order, const int64_t *dims,
+                   const int *perm, hipStream_t s);
+
+// ------------------------------------------------------------- features --
+void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B, float *out,
+                     hipStream_t s);
+
+// The caller's additive identity checked against the semiring, or the
+// default identity (Section 3.1).
+IdVal make_id_public(int sr, int dt, const void *add_id);
+// Key of the autotune cache for a feature vector.
+std::string tune_key(int sr, int dt, const float *features);
+}  // namespace srtc
+
+struct srtc_ctx {
+  srtc::Ctx c;
+};
+
+namespace srtc {
+template <class F> srtc_status guard(srtc_ctx *ctx, F &&f) {
+  try {
+    if (!ctx) return SRTC_ERR_ARG;
+    ctx->c.stream = nullptr;
+    SRTC_HIP(hipSetDevice(ctx->c.device));
+    f();
+    return SRTC_OK;
+  } catch (const Error &e) {
+    ctx->c.err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc &) {
+    ctx->c.err = "host allocation failed";
+    return SRTC_ERR_OOM;
+  } catch (...) {
+    ctx->c.err = "internal error";
+    return SRTC_ERR_DEVICE;
+  }
+}
+}  // namespace srtc

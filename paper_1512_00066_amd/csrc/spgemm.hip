@@ -1,0 +1,946 @@
+// Sparse x sparse semiring contraction C = A (x) B (row-wise, two phases).
+//
+//   C_ij = (+)_{k : (i,k) in A, (k,j) in B} A_ik (x) B_kj
+// (the loop-nest meaning of an indexed contraction, Section 3.3.1; sparse x
+// sparse is the extension left open in Sections 1 and 7).
+//
+// Pipeline (all rows of A are independent):
+//   1. row analysis   w_i = sum_{k in A_i} nnz(B_k)   (products per row)
+//   2. binning        rows grouped by w_i, then by the exact nnz_i
+//   3. symbolic       nnz_i per row: LDS hash of column keys (light rows) or
+//                     an LDS bitmap over the columns (heavy rows)
+//   4. scan           rowptr of C; the single host sync sizes C
+//   5. numeric        per bin: LDS hash + in-LDS bitonic sort (tiny rows),
+//                     LDS hash + bitmap-ranked extraction (medium rows), or
+//                     dense LDS accumulator windows over the columns (heavy
+//                     rows, whose outputs are a sizeable fraction of n)
+//   6. compaction     only if some result equalled the additive identity
+//                     (dropped), the rows are packed again.
+// Every per-bin kernel is persistent: a grid sized to the machine pulls rows
+// from an atomic work counter.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace srtc {
+
+namespace {
+
+constexpr int32_t EMPTY = 0x7fffffff;  // empty hash slot (sorts last)
+constexpr int LDS_BYTES = 160 * 1024;
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t j, int lg) {
+  return ((uint32_t)j * 0x9E3779B1u) >> (32 - lg);
+}
+
+// ------------------------------------------------------------- analysis --
+__global__ void row_products_kernel(const int64_t *__restrict__ rpA, const int32_t *__restrict__ cA,
+                                    const int64_t *__restrict__ rpB, int64_t m, int64_t *__restrict__ w) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  for (int64_t i = wid; i < m; i += nw) {
+    int64_t acc = 0;
+    for (int64_t p = rpA[i] + lane_id(); p < rpA[i + 1]; p += WAVE) {
+      const int32_t k = cA[p];
+      acc += rpB[k + 1] - rpB[k];
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) w[i] = acc;
+  }
+}
+
+constexpr int NBIN = 6;  // bin 0 = empty rows (skipped)
+struct Thresholds {
+  int64_t t[NBIN - 1];  // bin b (1..) takes v with t[b-2] < v <= t[b-1]; last bin above
+};
+
+// info layout: [0..NBIN) counts, [NBIN..2NBIN) starts, [2NBIN..3NBIN) cursors,
+// [3NBIN..4NBIN) work counters, [4NBIN] sum of values
+constexpr int INFO = 4 * NBIN + 2;
+
+__device__ __forceinline__ int bin_of(int64_t v, const Thresholds &th) {
+  if (v <= 0) return 0;
+#pragma unroll
+  for (int b = 0; b < NBIN - 2; b++)
+    if (v <= th.t[b]) return b + 1;
+  return NBIN - 1;
+}
+
+__global__ void bin_count(const int64_t *v, int64_t m, Thresholds th, int64_t *info) {
+  __shared__ int32_t cnt[NBIN];
+  __shared__ unsigned long long sum;
+  if (threadIdx.x < NBIN) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) sum = 0;
+  __syncthreads();
+  unsigned long long local = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = v[i];
+    atomicAdd(&cnt[bin_of(x, th)], 1);
+    local += (unsigned long long)x;
+  }
+  local = wave_sum(local);
+  if (lane_id() == 0) atomicAdd(&sum, local);
+  __syncthreads();
+  if (threadIdx.x < NBIN) atomicAdd((unsigned long long *)&info[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+  if (threadIdx.x == 0) atomicAdd((unsigned long long *)&info[4 * NBIN], sum);
+}
+
+__global__ void bin_offsets(int64_t *info) {
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int b = 0; b < NBIN; b++) {
+      info[NBIN + b] = run;
+      info[2 * NBIN + b] = 0;
+      info[3 * NBIN + b] = 0;
+      run += info[b];
+    }
+  }
+}
+
+__global__ void bin_scatter(const int64_t *v, int64_t m, Thresholds th, int64_t *info, int32_t *lists,
+                            const int32_t *row_map) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int b = bin_of(v[i], th);
+    if (b == 0) continue;
+    const int64_t p = atomicAdd((unsigned long long *)&info[2 * NBIN + b], 1ull);
+    lists[info[NBIN + b] + p] = row_map ? row_map[i] : (int32_t)i;
+  }
+}
+
+__global__ void gather_i64(const int64_t *src, const int32_t *idx, int64_t n, int64_t *dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[idx[i]];
+}
+
+// ------------------------------------------------------ product walking --
+template <int BS, class V> struct Chunk {
+  int32_t off[BS];
+  int64_t start[BS];
+  V a[BS];
+  int32_t tmp[BS / WAVE + 1];
+};
+
+// Visit every product of row i (optionally restricted to column window w of
+// the window table) as f(j, a_ik, b_kj).  A entries are taken BS at a time;
+// their B segments are laid end to end by a block scan and every thread
+// walks that flattened range with a binary search for its segment, so the
+// work per thread is balanced whatever the segment lengths.
+template <int BS, bool VALS, class V, class F>
+__device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, const int32_t *__restrict__ cA,
+                                             const V *__restrict__ vA, const int64_t *__restrict__ rpB,
+                                             const int32_t *__restrict__ cB, const V *__restrict__ vB,
+                                             int64_t i, const int32_t *__restrict__ woff, int nwin, int w,
+                                             Chunk<BS, V> &L, F &&f) {
+  const int t = threadIdx.x;
+  const int64_t pa = rpA[i], pe = rpA[i + 1];
+  for (int64_t p0 = pa; p0 < pe; p0 += BS) {
+    const int cnt = (int)min((int64_t)BS, pe - p0);
+    int32_t len = 0;
+    int64_t st = 0;
+    V a{};
+    if (t < cnt) {
+      const int32_t k = cA[p0 + t];
+      st = rpB[k];
+      if (woff) {
+        const int32_t *wk = woff + (int64_t)k * (nwin + 1) + w;
+        const int32_t o0 = wk[0], o1 = wk[1];
+        st += o0;
+        len = o1 - o0;
+      } else {
+        len = (int32_t)(rpB[k + 1] - st);
+      }
+      if (VALS) a = vA[p0 + t];
+    }
+    int32_t total;
+    const int32_t off = block_excl_scan<BS>(len, L.tmp, &total);
+    L.off[t] = off;
+    L.start[t] = st;
+    if (VALS) L.a[t] = a;
+    __syncthreads();
+    for (int32_t q = t; q < total; q += BS) {
+      int lo = 0, hi = cnt - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.off[mid] <= q) lo = mid; else hi = mid - 1;
+      }
+      const int64_t pos = L.start[lo] + (q - L.off[lo]);
+      if (VALS) f(cB[pos], L.a[lo], vB[pos]);
+      else f(cB[pos], V{}, V{});
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int64_t next_row(int64_t *ctr) {
+  __shared__ int64_t r;
+  if (threadIdx.x == 0) r = (int64_t)atomicAdd((unsigned long long *)ctr, 1ull);
+  __syncthreads();
+  const int64_t v = r;
+  __syncthreads();
+  return v;
+}
+
+template <int BS, class T> __device__ __forceinline__ T block_sum(T v, T *tmp) {
+  T tot;
+  block_excl_scan<BS>(v, tmp, &tot);
+  return tot;
+}
+
+// ------------------------------------------------------------- symbolic --
+template <int BS, int TBL>
+__global__ void __launch_bounds__(BS) sym_hash(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
+                                               int bin, const int64_t *__restrict__ rpA,
+                                               const int32_t *__restrict__ cA, const int64_t *__restrict__ rpB,
+                                               const int32_t *__restrict__ cB, int64_t *__restrict__ nnz_row,
+                                               int64_t *ctr) {
+  constexpr int LG = __builtin_ctz(TBL);
+  __shared__ int32_t keys[TBL];
+  __shared__ Chunk<BS, uint8_t> L;
+  __shared__ int64_t red[BS / WAVE + 1];
+  const int64_t count = info[bin];
+  const int32_t *rows = list + info[NBIN + bin];
+  for (;;) {
+    const int64_t r = next_row(ctr);
+    if (r >= count) break;
+    const int64_t i = rows[r];
+    for (int s = threadIdx.x; s < TBL; s += BS) keys[s] = EMPTY;
+    __syncthreads();
+    int64_t mine = 0;
+    for_products<BS, false, uint8_t>(rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr, i,
+                                     nullptr, 0, 0, L, [&](int32_t j, uint8_t, uint8_t) {
+      uint32_t h = hash_slot(j, LG);
+      for (;;) {
+        const int32_t k = keys[h];
+        if (k == j) break;
+        if (k == EMPTY) {
+          const int32_t old = atomicCAS(&keys[h], EMPTY, j);
+          if (old == EMPTY) { mine++; break; }
+          if (old == j) break;
+        }
+        h = (h + 1) & (TBL - 1);
+      }
+    });
+    const int64_t tot = block_sum<BS>(mine, red);
+    if (threadIdx.x == 0) nnz_row[i] = tot;
+  }
+}
+
+// bitmap over a window of `wbits` columns (dynamic LDS); rows wider than
+// the window are walked once per window.
+template <int BS>
+__global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
+                                                 int bin, const int64_t *__restrict__ rpA,
+                                                 const int32_t *__restrict__ cA, const int64_t *__restrict__ rpB,
+                                                 const int32_t *__restrict__ cB, int64_t ncols, int32_t wwords,
+                                                 int64_t *__restrict__ nnz_row, int64_t *ctr) {
+  extern __shared__ uint32_t bits[];
+  __shared__ Chunk<BS, uint8_t> L;
+  __shared__ int64_t red[BS / WAVE + 1];
+  const int64_t count = info[bin];
+  const int32_t *rows = list + info[NBIN + bin];
+  const int64_t wcols = (int64_t)wwords * 32;
+  for (;;) {
+    const int64_t r = next_row(ctr);
+    if (r >= count) break;
+    const int64_t i = rows[r];
+    int64_t mine = 0;
+    for (int64_t w0 = 0; w0 < ncols; w0 += wcols) {
+      for (int s = threadIdx.x; s < wwords; s += BS) bits[s] = 0;
+      __syncthreads();
+      for_products<BS, false, uint8_t>(rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr, i,
+                                       nullptr, 0, 0, L, [&](int32_t j, uint8_t, uint8_t) {
+        const int64_t jj = (int64_t)j - w0;
+        if (jj >= 0 && jj < wcols) atomicOr(&bits[jj >> 5], 1u << (jj & 31));
+      });
+      for (int s = threadIdx.x; s < wwords; s += BS) mine += __popc(bits[s]);
+      __syncthreads();
+    }
+    const int64_t tot = block_sum<BS>(mine, red);
+    if (threadIdx.x == 0) nnz_row[i] = tot;
+  }
+}
+
+// -------------------------------------------------------------- numeric --
+// Output bookkeeping: row_kept[i] = entries written; any_short is raised if
+// some result equalled the identity and was dropped.
+
+// EXTRACT: 0 = bitonic sort of the table, 1 = bitmap-ranked (sorted), 2 = table order
+template <class SR, int BS, int TBL, int EXTRACT>
+__global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
+                                               int bin, const int64_t *__restrict__ rpA,
+                                               const int32_t *__restrict__ cA,
+                                               const typename SR::val_t *__restrict__ vA,
+                                               const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB,
+                                               const typename SR::val_t *__restrict__ vB, int64_t ncols,
+                                               int32_t wwords, const int64_t *__restrict__ rpC,
+                                               int32_t *__restrict__ cC, typename SR::val_t *__restrict__ vC,
+                                               typename SR::acc_t id, int64_t *__restrict__ row_kept,
+                                               int32_t *any_short, int64_t *ctr) {
+  using V = typename SR::val_t;
+  using A = typename SR::acc_t;
+  constexpr int LG = __builtin_ctz(TBL);
+  constexpr int NV = SR::HAS_VALS ? TBL : 1;
+  __shared__ int32_t keys[TBL];
+  __shared__ A vals[NV];
+  __shared__ Chunk<BS, V> L;
+  __shared__ int64_t red[BS / WAVE + 1];
+  extern __shared__ uint32_t bits[];
+  const int64_t count = info[bin];
+  const int32_t *rows = list + info[NBIN + bin];
+  for (;;) {
+    const int64_t r = next_row(ctr);
+    if (r >= count) break;
+    const int64_t i = rows[r];
+    for (int s = threadIdx.x; s < TBL; s += BS) {
+      keys[s] = EMPTY;
+      if (SR::HAS_VALS) vals[s] = id;
+    }
+    __syncthreads();
+    for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nullptr, 0, 0, L, [&](int32_t j, V a, V b) {
+      if (SR::HAS_VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
+      uint32_t h = hash_slot(j, LG);
+      for (;;) {
+        const int32_t k = keys[h];
+        if (k == j) break;
+        if (k == EMPTY) {
+          const int32_t old = atomicCAS(&keys[h], EMPTY, j);
+          if (old == EMPTY || old == j) break;
+        }
+        h = (h + 1) & (TBL - 1);
+      }
+      if (SR::HAS_VALS) SR::lds_add(&vals[h], SR::mul(a, b));
+    });
+    __syncthreads();
+    const int64_t base = rpC[i];
+    int64_t written = 0;
+    if (EXTRACT == 0 || EXTRACT == 2) {
+      if (EXTRACT == 0) {
+        // bitonic sort of (key, value) over the whole table; EMPTY sorts last
+        for (int k = 2; k <= TBL; k <<= 1) {
+          for (int jst = k >> 1; jst > 0; jst >>= 1) {
+            for (int q = threadIdx.x; q < TBL / 2; q += BS) {
+              const int lo = (q / jst) * 2 * jst + (q % jst);
+              const int hi = lo + jst;
+              const bool up = (lo & k) == 0;
+              const int32_t ka = keys[lo], kb = keys[hi];
+              if ((ka > kb) == up) {
+                keys[lo] = kb;
+                keys[hi] = ka;
+                if (SR::HAS_VALS) { const A t = vals[lo]; vals[lo] = vals[hi]; vals[hi] = t; }
+              }
+            }
+            __syncthreads();
+          }
+        }
+      }
+      // compact in table order
+      for (int c0 = 0; c0 < TBL; c0 += BS) {
+        const int s = c0 + threadIdx.x;
+        const int32_t kk = keys[s];
+        const A v = SR::HAS_VALS ? vals[s] : (A)1;
+        const int keep = (kk != EMPTY && !SR::acc_absent(v, id)) ? 1 : 0;
+        int64_t tot;
+        const int64_t pre = block_excl_scan<BS>((int64_t)keep, red, &tot);
+        if (keep) {
+          cC[base + written + pre] = kk;
+          vC[base + written + pre] = SR::out(v);
+        }
+        written += tot;
+      }
+    } else {
+      // bitmap ranks: walk the columns in order through a bitmap window
+      const int64_t wcols = (int64_t)wwords * 32;
+      const int per = (wwords + BS - 1) / BS;  // words per thread (contiguous)
+      for (int64_t w0 = 0; w0 < ncols; w0 += wcols) {
+        for (int s = threadIdx.x; s < wwords; s += BS) bits[s] = 0;
+        __syncthreads();
+        for (int s = threadIdx.x; s < TBL; s += BS) {
+          const int32_t kk = keys[s];
+          if (kk != EMPTY) {
+            const int64_t jj = (int64_t)kk - w0;
+            if (jj >= 0 && jj < wcols) atomicOr(&bits[jj >> 5], 1u << (jj & 31));
+          }
+        }
+        __syncthreads();
+        // pass 1: kept entries per thread
+        int64_t mine = 0;
+        const int u0 = threadIdx.x * per;
+        for (int u = u0; u < u0 + per && u < wwords; u++) {
+          uint32_t wd = bits[u];
+          while (wd) {
+            const int b = __ffs(wd) - 1;
+            wd &= wd - 1;
+            const int32_t j = (int32_t)(w0 + u * 32 + b);
+            if (SR::HAS_VALS) {
+              uint32_t h = hash_slot(j, LG);
+              while (keys[h] != j) h = (h + 1) & (TBL - 1);
+              if (SR::acc_absent(vals[h], id)) continue;
+            }
+            mine++;
+          }
+        }
+        int64_t tot;
+        int64_t pos = base + written + block_excl_scan<BS>(mine, red, &tot);
+        for (int u = u0; u < u0 + per && u < wwords; u++) {
+          uint32_t wd = bits[u];
+          while (wd) {
+            const int b = __ffs(wd) - 1;
+            wd &= wd - 1;
+            const int32_t j = (int32_t)(w0 + u * 32 + b);
+            A v = (A)1;
+            if (SR::HAS_VALS) {
+              uint32_t h = hash_slot(j, LG);
+              while (keys[h] != j) h = (h + 1) & (TBL - 1);
+              v = vals[h];
+              if (SR::acc_absent(v, id)) continue;
+            }
+            cC[pos] = j;
+            vC[pos] = SR::out(v);
+            pos++;
+          }
+        }
+        written += tot;
+        __syncthreads();
+      }
+    }
+    if (threadIdx.x == 0) {
+      row_kept[i] = written;
+      if (written != rpC[i + 1] - base) atomicOr(any_short, 1);
+    }
+    __syncthreads();
+  }
+}
+
+// Dense accumulator windows: W consecutive columns per window held in LDS
+// (values + presence bits).  The window table gives, for every row k of B,
+// where each window starts in B_k (B rows have ascending columns), so each
+// product is visited exactly once over all windows.
+template <class SR, int BS, int W>
+__global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
+                                                int bin, const int64_t *__restrict__ rpA,
+                                                const int32_t *__restrict__ cA,
+                                                const typename SR::val_t *__restrict__ vA,
+                                                const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB,
+                                                const typename SR::val_t *__restrict__ vB, int64_t ncols,
+                                                const int32_t *__restrict__ woff, int nwin,
+                                                const int64_t *__restrict__ rpC, int32_t *__restrict__ cC,
+                                                typename SR::val_t *__restrict__ vC, typename SR::acc_t id,
+                                                int64_t *__restrict__ row_kept, int32_t *any_short,
+                                                int64_t *ctr) {
+  using V = typename SR::val_t;
+  using A = typename SR::acc_t;
+  constexpr int NWORD = W / 32;
+  constexpr int PER = (NWORD + BS - 1) / BS;
+  constexpr int NV = SR::HAS_VALS ? W : 1;
+  __shared__ A vals[NV];
+  __shared__ uint32_t bits[NWORD];
+  __shared__ Chunk<BS, V> L;
+  __shared__ int64_t red[BS / WAVE + 1];
+  for (int s = threadIdx.x; s < NV; s += BS) vals[s] = id;
+  for (int s = threadIdx.x; s < NWORD; s += BS) bits[s] = 0;
+  __syncthreads();
+  const int64_t count = info[bin];
+  const int32_t *rows = list + info[NBIN + bin];
+  for (;;) {
+    const int64_t r = next_row(ctr);
+    if (r >= count) break;
+    const int64_t i = rows[r];
+    const int64_t base = rpC[i];
+    int64_t written = 0;
+    for (int w = 0; w < nwin; w++) {
+      const int64_t w0 = (int64_t)w * W;
+      for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin, w, L,
+                                        [&](int32_t j, V a, V b) {
+        if (SR::HAS_VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
+        const int64_t jl = (int64_t)j - w0;
+        if (jl < 0 || jl >= W) return;  // B rows must list columns in ascending order
+        const int jj = (int)jl;
+        if (SR::HAS_VALS) SR::lds_add(&vals[jj], SR::mul(a, b));
+        atomicOr(&bits[jj >> 5], 1u << (jj & 31));
+      });
+      // extraction in column order; resets the touched slots
+      int64_t mine = 0;
+      const int u0 = threadIdx.x * PER;
+#pragma unroll
+      for (int q = 0; q < PER; q++) {
+        const int u = u0 + q;
+        if (u >= NWORD) break;
+        uint32_t wd = bits[u];
+        if (SR::HAS_VALS) {
+          uint32_t t2 = wd;
+          while (t2) {
+            const int b = __ffs(t2) - 1;
+            t2 &= t2 - 1;
+            if (SR::acc_absent(vals[u * 32 + b], id)) wd &= ~(1u << b);
+          }
+        }
+        mine += __popc(wd);
+      }
+      int64_t tot;
+      int64_t pos = base + written + block_excl_scan<BS>(mine, red, &tot);
+#pragma unroll
+      for (int q = 0; q < PER; q++) {
+        const int u = u0 + q;
+        if (u >= NWORD) break;
+        uint32_t wd = bits[u];
+        bits[u] = 0;
+        while (wd) {
+          const int b = __ffs(wd) - 1;
+          wd &= wd - 1;
+          const int s = u * 32 + b;
+          A v = (A)1;
+          if (SR::HAS_VALS) {
+            v = vals[s];
+            vals[s] = id;
+            if (SR::acc_absent(v, id)) continue;
+          }
+          cC[pos] = (int32_t)(w0 + s);
+          vC[pos] = SR::out(v);
+          pos++;
+        }
+      }
+      written += tot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      row_kept[i] = written;
+      if (written != rpC[i + 1] - base) atomicOr(any_short, 1);
+    }
+  }
+}
+
+// Window table: woff[k*(nwin+1) + w] = first position in B_k with column
+// >= w*W (relative to rowptr[k]); woff[k*(nwin+1)+nwin] = nnz(B_k).
+__global__ void build_woff(const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB, int64_t nrows,
+                           int nwin, int64_t W, int32_t *__restrict__ woff) {
+  const int64_t total = nrows * (nwin + 1);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = t / (nwin + 1);
+    const int w = (int)(t % (nwin + 1));
+    const int64_t a = rpB[k], b = rpB[k + 1];
+    int64_t res;
+    if (w == nwin) res = b - a;
+    else {
+      const int64_t target = (int64_t)w * W;
+      int64_t lo = a, hi = b;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cB[mid] < target) lo = mid + 1; else hi = mid;
+      }
+      res = lo - a;
+    }
+    woff[t] = (int32_t)res;
+  }
+}
+
+// Pack rows whose kept count fell short of the symbolic count.
+template <class V>
+__global__ void compact_rows(const int64_t *rp_old, const int64_t *rp_new, int64_t m, const int32_t *c_old,
+                             const V *v_old, int32_t *c_new, V *v_new) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  for (int64_t i = wid; i < m; i += nw) {
+    const int64_t a = rp_old[i], n = rp_new[i + 1] - rp_new[i], o = rp_new[i];
+    for (int64_t q = lane_id(); q < n; q += WAVE) {
+      c_new[o + q] = c_old[a + q];
+      v_new[o + q] = v_old[a + q];
+    }
+  }
+}
+
+inline unsigned gridn(int64_t n, int bs = 256, int64_t cap = 65536) {
+  int64_t g = (n + bs - 1) / bs;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// Schedules: symbolic hash ceiling, numeric bin edges, extraction and dense
+// window shape.  Index = schedule id.
+const Schedule kSchedules[SRTC_NUM_SCHEDULES] = {
+    // sym_hash_max, t_tiny, t_small, t_mid, t_big, small_bitmap, dense_bs, dense_wide
+    {2048, 32, 256, 2048, 4096, 0, 256, 0},   // 0 balanced
+    {2048, 32, 256, 2048, 4096, 1, 256, 0},   // 1 small bin ranked by bitmap
+    {2048, 32, 256, 256, 256, 1, 256, 0},     // 2 dense windows from 257 outputs
+    {8192, 32, 256, 2048, 4096, 0, 512, 1},   // 3 hash-heavy, wide dense windows
+    {0, 0, 0, 0, 0, 0, 256, 0},               // 4 dense windows for every row
+    {2048, 32, 256, 2048, 4096, 0, 512, 0},   // 5 as 0 with 512-thread dense blocks
+    {2048, 32, 256, 2048, 4096, 0, 256, 1},   // 6 as 0 with wide dense windows
+    {256, 32, 256, 1024, 1024, 1, 256, 0},    // 7 bitmap symbolic above 256 products
+};
+
+struct Launch {
+  Ctx *c;
+  hipStream_t s;
+  int blocks_per_cu(int lds_bytes, int bs) const {
+    int by_lds = lds_bytes > 0 ? LDS_BYTES / lds_bytes : 64;
+    int by_waves = 32 / std::max(1, bs / WAVE);  // 8 waves/SIMD x 4 SIMDs
+    return std::max(1, std::min(by_lds, by_waves));
+  }
+  unsigned grid(int64_t rows, int lds_bytes, int bs) const {
+    int64_t cap = (int64_t)c->num_cus * blocks_per_cu(lds_bytes, bs);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(rows, cap));
+  }
+};
+
+template <int BS, int TBL>
+void launch_sym_hash(const Launch &L, int64_t rows, const int32_t *list, const int64_t *info, int bin,
+                     const CsrView &A, const CsrView &B, int64_t *nnz_row, int64_t *ctr) {
+  if (rows == 0) return;
+  const int lds = TBL * 4 + sizeof(Chunk<BS, uint8_t>) + 64;
+  sym_hash<BS, TBL><<<L.grid(rows, lds, BS), BS, 0, L.s>>>(list, info, bin, A.rowptr, A.col, B.rowptr, B.col,
+                                                           nnz_row, ctr);
+  SRTC_LAUNCH_CHECK("sym_hash");
+}
+
+int32_t bitmap_words(int64_t ncols, int bs, int64_t budget_bytes) {
+  int64_t want = (ncols + 31) / 32;
+  int64_t cap = budget_bytes / 4;
+  cap -= cap % bs;
+  if (cap < bs) cap = bs;
+  int64_t wv = std::min(want, cap);
+  wv = ((wv + bs - 1) / bs) * bs;  // whole words per thread
+  return (int32_t)wv;
+}
+
+// Symbolic pass over `nsel` rows whose product counts are wsel (row ids in
+// row_map, or 0..nsel-1): nnz_row[row] for each.  Returns the product total.
+// Synchronizes once (bin sizes).
+int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, const CsrView &Bm, const int64_t *wsel,
+                     const int32_t *row_map, int64_t nsel, int64_t *info1, int32_t *list, int64_t *nnz_row) {
+  hipStream_t s = L.s;
+  Ctx *c = L.c;
+  const int64_t n = Bm.n;
+  Thresholds th1{};
+  {
+    // bins: 1: <=32 (64-slot hash), 2: <=256 (512), 3: <=2048 (4096),
+    // 4: <=8192 (16384), 5: bitmap.  Edges above sym_hash_max collapse so
+    // those rows fall through to the bitmap.
+    const int64_t edges[4] = {32, 256, 2048, 8192};
+    int64_t prev = 0;
+    for (int b = 0; b < 4; b++) {
+      th1.t[b] = edges[b] <= S.sym_hash_max ? edges[b] : prev;
+      prev = th1.t[b];
+    }
+  }
+  bin_count<<<gridn(nsel, 256, 2048), 256, 0, s>>>(wsel, nsel, th1, info1);
+  SRTC_LAUNCH_CHECK("bin_count");
+  bin_offsets<<<1, 64, 0, s>>>(info1);
+  bin_scatter<<<gridn(nsel, 256, 4096), 256, 0, s>>>(wsel, nsel, th1, info1, list, row_map);
+  SRTC_LAUNCH_CHECK("bin_scatter");
+  int64_t hinfo[INFO];
+  read_to_host(c, hinfo, info1, sizeof(hinfo), s);
+  int64_t *ctr1 = info1 + 3 * NBIN;
+  launch_sym_hash<64, 64>(L, hinfo[1], list, info1, 1, Am, Bm, nnz_row, ctr1 + 1);
+  launch_sym_hash<64, 512>(L, hinfo[2], list, info1, 2, Am, Bm, nnz_row, ctr1 + 2);
+  launch_sym_hash<256, 4096>(L, hinfo[3], list, info1, 3, Am, Bm, nnz_row, ctr1 + 3);
+  launch_sym_hash<512, 16384>(L, hinfo[4], list, info1, 4, Am, Bm, nnz_row, ctr1 + 4);
+  if (hinfo[5] > 0) {
+    constexpr int BS = 256;
+    const int stat = (int)sizeof(Chunk<BS, uint8_t>) + 64;
+    const int32_t ww = bitmap_words(n, BS, LDS_BYTES - stat - 1024);
+    auto kern = sym_bitmap<BS>;
+    if (ww * 4 > 64 * 1024)
+      SRTC_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, ww * 4));
+    kern<<<L.grid(hinfo[5], stat + ww * 4, BS), BS, (size_t)ww * 4, s>>>(list, info1, 5, Am.rowptr, Am.col,
+                                                                      Bm.rowptr, Bm.col, n, ww, nnz_row, ctr1 + 5);
+    SRTC_LAUNCH_CHECK("sym_bitmap");
+  }
+  return hinfo[4 * NBIN];
+}
+
+template <class SR> struct NumLaunch {
+  using V = typename SR::val_t;
+  using A = typename SR::acc_t;
+  template <int BS, int TBL, int EX>
+  static void hash(const Launch &L, int64_t rows, const int32_t *list, const int64_t *info, int bin,
+                   const CsrView &Am, const CsrView &Bm, const int64_t *rpC, int32_t *cC, V *vC, A id,
+                   int64_t *kept, int32_t *any_short, int64_t *ctr) {
+    if (rows == 0) return;
+    constexpr int NV = SR::HAS_VALS ? TBL : 1;
+    const int stat = TBL * 4 + NV * (int)sizeof(A) + (int)sizeof(Chunk<BS, V>) + 64;
+    int32_t ww = 0;
+    size_t dyn = 0;
+    if (EX == 1) {
+      ww = bitmap_words(Bm.n, BS, LDS_BYTES - stat - 1024);
+      dyn = (size_t)ww * 4;
+    }
+    auto kern = num_hash<SR, BS, TBL, EX>;
+    if (dyn > 64 * 1024) SRTC_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    kern<<<L.grid(rows, stat + (int)dyn, BS), BS, dyn, L.s>>>(
+        list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, ww,
+        rpC, cC, vC, id, kept, any_short, ctr);
+    SRTC_LAUNCH_CHECK("num_hash");
+  }
+  template <int BS, int W>
+  static void dense(const Launch &L, int64_t rows, const int32_t *list, const int64_t *info, int bin,
+                    const CsrView &Am, const CsrView &Bm, const int32_t *woff, int nwin, const int64_t *rpC,
+                    int32_t *cC, V *vC, A id, int64_t *kept, int32_t *any_short, int64_t *ctr) {
+    if (rows == 0) return;
+    constexpr int NV = SR::HAS_VALS ? W : 1;
+    const int stat = NV * (int)sizeof(A) + W / 8 + (int)sizeof(Chunk<BS, V>) + 64;
+    num_dense<SR, BS, W><<<L.grid(rows, stat, BS), BS, 0, L.s>>>(
+        list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, woff,
+        nwin, rpC, cC, vC, id, kept, any_short, ctr);
+    SRTC_LAUNCH_CHECK("num_dense");
+  }
+};
+
+// Dense window width (columns) for a semiring and schedule.
+template <class SR> int64_t dense_width(bool wide) {
+  if (!SR::HAS_VALS) return wide ? (1 << 20) : (1 << 18);
+  return (wide ? 16384 : 8192) * (8 / (int)sizeof(typename SR::acc_t));
+}
+
+template <class SR>
+void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int sched, int sorted, CsrOut *out,
+                  SpgemmStats *st, hipStream_t s) {
+  using V = typename SR::val_t;
+  using A = typename SR::acc_t;
+  const A id = id_as<SR>(idv);
+  const Schedule &S = schedule(sched);
+  const int64_t m = Am.m, n = Bm.n;
+  Launch L{c, s};
+  out->m = m;
+  out->n = n;
+  out->rowptr = Buf(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
+  const size_t es = sizeof(V);
+  if (m == 0 || Am.nnz == 0 || Bm.nnz == 0) {
+    fill_i64(out->rowptr.as<int64_t>(), m + 1, 0, s);
+    out->nnz = 0;
+    out->col = Buf(c, 4, out->kind);
+    out->val = Buf(c, es, out->kind);
+    if (st) *st = SpgemmStats{};
+    return;
+  }
+  // 1-3. products per row, symbolic bins, symbolic pass
+  Buf w(c, sizeof(int64_t) * (size_t)m);
+  row_products(Am, Bm, w.as<int64_t>(), s);
+  Buf info(c, sizeof(int64_t) * INFO * 2);
+  int64_t *info1 = info.as<int64_t>(), *info2 = info1 + INFO;
+  fill_i64(info1, INFO * 2, 0, s);
+  Buf list(c, sizeof(int32_t) * (size_t)m);
+  Buf nnz_row(c, sizeof(int64_t) * (size_t)m);
+  fill_i64(nnz_row.as<int64_t>(), m, 0, s);
+  const int64_t products = run_symbolic(L, S, Am, Bm, w.as<int64_t>(), nullptr, m, info1, list.as<int32_t>(),
+                                        nnz_row.as<int64_t>());
+  if (st) st->products = products;
+  // 4. rowptr, numeric bins (by exact nnz)
+  excl_scan_i64(c, nnz_row.as<int64_t>(), out->rowptr.as<int64_t>(), m, s);
+  Thresholds th2{};
+  th2.t[0] = S.t_tiny;
+  th2.t[1] = std::max(S.t_small, th2.t[0]);
+  th2.t[2] = std::max(S.t_mid, th2.t[1]);
+  th2.t[3] = std::max(S.t_big, th2.t[2]);
+  bin_count<<<gridn(m, 256, 2048), 256, 0, s>>>(nnz_row.as<int64_t>(), m, th2, info2);
+  SRTC_LAUNCH_CHECK("bin_count");
+  bin_offsets<<<1, 64, 0, s>>>(info2);
+  bin_scatter<<<gridn(m, 256, 4096), 256, 0, s>>>(nnz_row.as<int64_t>(), m, th2, info2, list.as<int32_t>(), nullptr);
+  SRTC_LAUNCH_CHECK("bin_scatter");
+  int64_t hinfo2[INFO];
+  read_to_host(c, hinfo2, info2, sizeof(hinfo2), s);
+  const int64_t total = hinfo2[4 * NBIN];
+  if (st) { st->nnz = total; st->dense_rows = hinfo2[5]; }
+  // 5. numeric
+  Buf col(c, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), out->kind);
+  Buf val(c, es * (size_t)std::max<int64_t>(total, 1), out->kind);
+  Buf kept(c, sizeof(int64_t) * (size_t)m);
+  Buf flag(c, 64);
+  fill_i32(flag.as<int32_t>(), 1, 0, s);
+  int64_t *ctr2 = info2 + 3 * NBIN;
+  const int64_t *rpC = out->rowptr.as<int64_t>();
+  int32_t *cC = col.as<int32_t>();
+  V *vC = val.as<V>();
+  int32_t *lst = list.as<int32_t>();
+  int64_t *kp = kept.as<int64_t>();
+  int32_t *fl = flag.as<int32_t>();
+  using NL = NumLaunch<SR>;
+  if (!sorted) {
+    NL::template hash<64, 64, 2>(L, hinfo2[1], lst, info2, 1, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 1);
+    NL::template hash<128, 512, 2>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
+  } else {
+    NL::template hash<64, 64, 0>(L, hinfo2[1], lst, info2, 1, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 1);
+    if (S.small_bitmap)
+      NL::template hash<128, 512, 1>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
+    else
+      NL::template hash<128, 512, 0>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
+  }
+  if (sorted) {
+    NL::template hash<256, 4096, 1>(L, hinfo2[3], lst, info2, 3, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 3);
+    NL::template hash<512, 8192, 1>(L, hinfo2[4], lst, info2, 4, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 4);
+  } else {
+    NL::template hash<256, 4096, 2>(L, hinfo2[3], lst, info2, 3, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 3);
+    NL::template hash<512, 8192, 2>(L, hinfo2[4], lst, info2, 4, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 4);
+  }
+  if (hinfo2[5] > 0) {
+    const int64_t W = dense_width<SR>(S.dense_wide != 0);
+    const int nwin = (int)((n + W - 1) / W);
+    Buf woff;
+    if (nwin > 1) {
+      woff = Buf(c, sizeof(int32_t) * (size_t)(Bm.m * (nwin + 1)));
+      build_woff<<<gridn(Bm.m * (nwin + 1)), 256, 0, s>>>(Bm.rowptr, Bm.col, Bm.m, nwin, W, woff.as<int32_t>());
+      SRTC_LAUNCH_CHECK("build_woff");
+    }
+    const int32_t *wo = woff.as<int32_t>();
+    if (S.dense_wide) {
+      if (S.dense_bs == 512) NL::template dense<512, (int)(SR::HAS_VALS ? 16384 * 8 / sizeof(A) : (1 << 20))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      else NL::template dense<256, (int)(SR::HAS_VALS ? 16384 * 8 / sizeof(A) : (1 << 20))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+    } else {
+      if (S.dense_bs == 512) NL::template dense<512, (int)(SR::HAS_VALS ? 8192 * 8 / sizeof(A) : (1 << 18))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      else NL::template dense<256, (int)(SR::HAS_VALS ? 8192 * 8 / sizeof(A) : (1 << 18))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+    }
+  }
+  // 6. compaction when identity results were dropped
+  int32_t short_flag = 0;
+  read_to_host(c, &short_flag, fl, sizeof(int32_t), s);
+  if (short_flag) {
+    Buf rp2(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
+    excl_scan_i64(c, kp, rp2.as<int64_t>(), m, s);
+    const int64_t t2 = read_i64(c, rp2.as<int64_t>() + m, s);
+    Buf col2(c, sizeof(int32_t) * (size_t)std::max<int64_t>(t2, 1), out->kind);
+    Buf val2(c, es * (size_t)std::max<int64_t>(t2, 1), out->kind);
+    compact_rows<V><<<gridn(m * WAVE, 256, 16384), 256, 0, s>>>(rpC, rp2.as<int64_t>(), m, cC, vC,
+                                                                 col2.as<int32_t>(), val2.as<V>());
+    SRTC_LAUNCH_CHECK("compact_rows");
+    out->rowptr = std::move(rp2);
+    col = std::move(col2);
+    val = std::move(val2);
+    if (st) { st->nnz = t2; st->compacted = 1; }
+    out->nnz = t2;
+  } else {
+    out->nnz = total;
+  }
+  out->col = std::move(col);
+  out->val = std::move(val);
+}
+
+// Row statistics for the schedule features: log2 histograms of row lengths
+// of A and of row product counts, maxima, sums, empty rows.
+__global__ void feat_stats_kernel(const int64_t *__restrict__ rpA, const int64_t *__restrict__ w, int64_t m,
+                                  unsigned long long *__restrict__ hist, unsigned long long *__restrict__ mx,
+                                  double *__restrict__ sums) {
+  __shared__ unsigned long long h[21];
+  __shared__ unsigned long long lmx[2];
+  __shared__ double ls[2];
+  if (threadIdx.x < 21) h[threadIdx.x] = 0;
+  if (threadIdx.x < 2) { lmx[threadIdx.x] = 0; ls[threadIdx.x] = 0.0; }
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t nz = rpA[i + 1] - rpA[i];
+    const int64_t wi = w[i];
+    const int bn = nz == 0 ? 0 : min(9, 64 - __clzll((unsigned long long)nz));          // ceil-ish log2(nz+1)
+    const int bw = wi == 0 ? 0 : min(9, (64 - __clzll((unsigned long long)wi) + 1) / 2);  // base-4 bins
+    atomicAdd(&h[bn], 1ull);
+    atomicAdd(&h[10 + bw], 1ull);
+    if (wi == 0) atomicAdd(&h[20], 1ull);
+    atomicMax(&lmx[0], (unsigned long long)wi);
+    atomicMax(&lmx[1], (unsigned long long)nz);
+    atomicAdd(&ls[0], (double)wi);
+    atomicAdd(&ls[1], (double)wi * (double)wi);
+  }
+  __syncthreads();
+  if (threadIdx.x < 21) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x < 2) {
+    atomicMax(&mx[threadIdx.x], lmx[threadIdx.x]);
+    atomicAdd(&sums[threadIdx.x], ls[threadIdx.x]);
+  }
+}
+
+}  // namespace
+
+const Schedule &schedule(int id) {
+  if (id < 0 || id >= SRTC_NUM_SCHEDULES) fail(SRTC_ERR_ARG, "schedule id out of range");
+  return kSchedules[id];
+}
+
+void row_products(const CsrView &A, const CsrView &B, int64_t *w, hipStream_t s) {
+  if (A.m == 0) return;
+  row_products_kernel<<<gridn(A.m * WAVE, 256, 16384), 256, 0, s>>>(A.rowptr, A.col, B.rowptr, A.m, w);
+  SRTC_LAUNCH_CHECK("row_products");
+}
+
+void spgemm(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B, int sched, int sorted,
+            CsrOut *out, SpgemmStats *st, hipStream_t s) {
+  if (A.n != B.m) fail(SRTC_ERR_DIM, "spgemm: inner dimensions differ");
+  if (B.n >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "spgemm: more than 2^31-2 columns");
+  SRTC_DISPATCH_SR(sr, dt, spgemm_typed, c, id, A, B, sched, sorted, out, st, s);
+}
+
+}  // namespace srtc
+
+namespace srtc {
+
+// Features of an SpGEMM problem (32 scale-free numbers; the selector's
+// input).  Compression ratio: products / outputs over a stratified sample of
+// up to 512 rows, counted exactly by the symbolic kernels.
+void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B, float *out, hipStream_t s) {
+  for (int q = 0; q < SRTC_NUM_FEATURES; q++) out[q] = 0.f;
+  const int64_t m = A.m;
+  if (A.n != B.m) fail(SRTC_ERR_DIM, "features: inner dimensions differ");
+  Launch L{c, s};
+  Buf w(c, sizeof(int64_t) * (size_t)std::max<int64_t>(m, 1));
+  if (m > 0) row_products(A, B, w.as<int64_t>(), s);
+  Buf st(c, 8 * 32);
+  fill_i64(st.as<int64_t>(), 32, 0, s);
+  unsigned long long *hist = (unsigned long long *)st.p;
+  unsigned long long *mx = hist + 21;
+  double *sums = (double *)(hist + 24);
+  if (m > 0) {
+    feat_stats_kernel<<<gridn(m, 256, 1024), 256, 0, s>>>(A.rowptr, w.as<int64_t>(), m, hist, mx, sums);
+    SRTC_LAUNCH_CHECK("feat_stats_kernel");
+  }
+  // sampled compression ratio
+  const int64_t ns = std::min<int64_t>(512, m);
+  double cr = 1.0;
+  if (ns > 0 && A.nnz > 0 && B.nnz > 0) {
+    std::vector<int32_t> hrows(ns);
+    for (int64_t t = 0; t < ns; t++) hrows[t] = (int32_t)((t * m) / ns);
+    Buf rows(c, sizeof(int32_t) * (size_t)ns), wsel(c, sizeof(int64_t) * (size_t)ns), nsel(c, sizeof(int64_t) * (size_t)ns);
+    void *pin = c->host_scratch(sizeof(int32_t) * (size_t)ns);
+    memcpy(pin, hrows.data(), sizeof(int32_t) * (size_t)ns);
+    SRTC_HIP(hipMemcpyAsync(rows.p, pin, sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, s));
+    gather_i64<<<gridn(ns), 256, 0, s>>>(w.as<int64_t>(), rows.as<int32_t>(), ns, wsel.as<int64_t>());
+    Buf info(c, sizeof(int64_t) * INFO);
+    fill_i64(info.as<int64_t>(), INFO, 0, s);
+    Buf list(c, sizeof(int32_t) * (size_t)ns);
+    Buf nnz_row(c, sizeof(int64_t) * (size_t)m);
+    fill_i64(nnz_row.as<int64_t>(), m, 0, s);
+    run_symbolic(L, schedule(0), A, B, wsel.as<int64_t>(), rows.as<int32_t>(), ns, info.as<int64_t>(),
+                 list.as<int32_t>(), nnz_row.as<int64_t>());
+    gather_i64<<<gridn(ns), 256, 0, s>>>(nnz_row.as<int64_t>(), rows.as<int32_t>(), ns, nsel.as<int64_t>());
+    std::vector<int64_t> hw(ns), hn(ns);
+    read_to_host(c, hw.data(), wsel.p, sizeof(int64_t) * (size_t)ns, s);
+    read_to_host(c, hn.data(), nsel.p, sizeof(int64_t) * (size_t)ns, s);
+    double sw = 0, sn = 0;
+    for (int64_t t = 0; t < ns; t++) { sw += (double)hw[t]; sn += (double)hn[t]; }
+    if (sn > 0) cr = sw / sn;
+  }
+  uint64_t hs[32];
+  read_to_host(c, hs, st.p, sizeof(hs), s);
+  double dsum[2];
+  memcpy(dsum, &hs[24], sizeof(dsum));
+  const double mm = (double)std::max<int64_t>(m, 1);
+  for (int b = 0; b < 10; b++) out[b] = (float)(hs[b] / mm);
+  for (int b = 0; b < 10; b++) out[10 + b] = (float)(hs[10 + b] / mm);
+  const double sw = dsum[0];
+  const double mean = sw / mm;
+  const double var = std::max(0.0, dsum[1] / mm - mean * mean);
+  out[20] = (float)std::log2((double)m + 1);
+  out[21] = (float)std::log2((double)B.n + 1);
+  out[22] = (float)std::log2((double)A.nnz + 1);
+  out[23] = (float)std::log2(sw + 1);
+  out[24] = (float)std::log2(cr);
+  out[25] = (float)std::log2((double)hs[21] + 1);
+  out[26] = (float)std::log2((double)hs[22] + 1);
+  out[27] = (float)(mean > 0 ? std::sqrt(var) / mean : 0.0);
+  out[28] = (float)(hs[20] / mm);
+  out[29] = (float)sr / 3.0f;
+  out[30] = (float)dtype_size(dt) / 8.0f;
+  out[31] = (float)std::log2((double)B.nnz / (double)std::max<int64_t>(B.m, 1) + 1);
+}
+
+}  // namespace srtc

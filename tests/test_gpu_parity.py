@@ -1,0 +1,421 @@
+"""Parity of the HIP library with the CPU oracle (GPU only).
+
+Every input comes from the seeded generators; the library folds it with its
+own kernels and the oracle with its own code, then the results are compared
+element by element: bit-exact for (min,+), (or,and), (max,x); within the
+stated relative bounds for (+,x) (1e-12 fp64, 1e-5 fp32 against fp64)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1512_00066_amd as srtc
+from gen import synth
+from gpu_common import EXACT, PAIRS, RTOL, TORCH, check_csr, gpu_fold, pair_inputs, say, values
+
+pytestmark = pytest.mark.gpu
+INF = oracle.INT_INF
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return srtc.Context(0)
+
+
+# ------------------------------------------------------------------- fold --
+@pytest.mark.parametrize("semiring,dtype", PAIRS)
+def test_fold_duplicates_and_identities(ctx, semiring, dtype):
+    say("fold", semiring, dtype)
+    src, dst = synth.rmat_edges(12, 8, 0.57, 0.19, 0.19, seed=101)   # ~32k pairs, duplicates
+    v = values(semiring, dtype, src.size, 101)
+    # sprinkle explicit identity entries (absent by definition)
+    idv = oracle.default_add_id(semiring, dtype)
+    v = v.copy()
+    v[::97] = idv
+    n = 1 << 12
+    G = gpu_fold(ctx, semiring, dtype, dst, src, v, n, n)
+    O = oracle.fold(semiring, dtype, dst, src, v, n, n)
+    # fold combines duplicates in input order on both sides: bit-exact
+    rp, col, val = G.to_host()
+    assert np.array_equal(rp, O.rowptr) and np.array_equal(col, O.col)
+    assert np.array_equal(val, O.val)
+
+
+def test_fold_edge_cases(ctx):
+    say("fold edge cases")
+    e = gpu_fold(ctx, "min_plus", "i32", [], [], np.zeros(0, np.int32), 5, 7)
+    assert e.nnz == 0 and e.rowptr.cpu().tolist() == [0] * 6
+    one = gpu_fold(ctx, "min_plus", "i32", [4], [6], np.array([3], np.int32), 5, 7)
+    assert one.rowptr.cpu().tolist() == [0, 0, 0, 0, 0, 1] and one.col.cpu().tolist() == [6]
+    # all entries identity -> empty
+    z = gpu_fold(ctx, "plus_times", "f64", [0, 1], [1, 0], np.zeros(2), 2, 2)
+    assert z.nnz == 0
+
+
+def test_fold_transpose_and_tensor_modes(ctx):
+    say("fold transpose / tensor modes")
+    src, dst = synth.er_edges(3000, 5, seed=55)
+    v = values("plus_times", "f64", src.size, 55)
+    G = gpu_fold(ctx, "plus_times", "f64", dst, src, v, 3000, 3000)
+    T = ctx.fold("plus_times", G, "ij", "j", "i")              # transpose of a CSR
+    O = oracle.fold("plus_times", "f64", src, dst, v, 3000, 3000)
+    rp, col, val = T.to_host()
+    assert np.array_equal(rp, O.rowptr) and np.array_equal(col, O.col) and np.array_equal(val, O.val)
+    dims = (37, 41, 29)
+    keys = synth.bernoulli_keys(dims, 0.05, seed=9)
+    tv = synth.uniform_f32(synth.stream_key(9, 1), keys.size)
+    coo = srtc.COO(torch.as_tensor(keys, device="cuda"), torch.as_tensor(tv, device="cuda"), dims)
+    F = ctx.fold("plus_times", coo, "ijk", "ki", "j")
+    OF = oracle.fold_tensor("plus_times", "f32", keys, tv, dims, "ijk", "ki", "j")
+    rp, col, val = F.to_host()
+    assert np.array_equal(rp, OF.rowptr) and np.array_equal(col, OF.col) and np.array_equal(val, OF.val)
+
+
+# ----------------------------------------------------------------- spgemm --
+CASES = {
+    "er500": lambda: (synth.er_edges(500, 6, seed=3), 500),
+    "rmat11": lambda: (synth.rmat_edges(11, 8, 0.57, 0.19, 0.19, seed=7), 1 << 11),
+    "rmat15w": lambda: (synth.rmat_edges(15, 4, 0.57, 0.19, 0.19, seed=7), 1 << 15),  # several windows
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("semiring,dtype", PAIRS)
+def test_spgemm_parity(ctx, semiring, dtype, case):
+    (src, dst), n = CASES[case]()
+    say("spgemm", semiring, dtype, case)
+    G, O = pair_inputs(ctx, semiring, dtype, src, dst, n, 11)
+    exp = oracle.spgemm(semiring, dtype, O, O)
+    scheds = range(srtc.NUM_SCHEDULES) if (semiring, dtype) in EXACT and case != "rmat15w" else (0, 2, 4)
+    for sch in scheds:
+        say("  schedule", sch)
+        C = ctx.contract(semiring, "ik", G, "kj", G, "ij", schedule=sch)
+        check_csr(C, exp, semiring, dtype)
+
+
+def test_spgemm_heavy_rows_all_schedules(ctx):
+    # R-MAT 14, edge factor 16: >1000 rows above 4096 outputs (dense windows)
+    src, dst = synth.rmat_edges(14, 16, 0.57, 0.19, 0.19, seed=7)
+    n = 1 << 14
+    for semiring, dtype in (("min_plus", "i32"), ("plus_times", "f64")):
+        G, O = pair_inputs(ctx, semiring, dtype, src, dst, n, 12)
+        exp = oracle.spgemm(semiring, dtype, O, O)
+        for sch in range(srtc.NUM_SCHEDULES):
+            say("heavy", semiring, dtype, "schedule", sch)
+            check_csr(ctx.contract(semiring, "ik", G, "kj", G, "ij", schedule=sch), exp, semiring, dtype)
+
+
+def test_spgemm_star_and_identity(ctx):
+    say("star / identity")
+    L = 3000
+    hub = np.zeros(L, np.int64)
+    leaves = np.arange(1, L + 1)
+    rows = np.concatenate([hub, leaves])
+    cols = np.concatenate([leaves, hub])
+    G = gpu_fold(ctx, "plus_times", "f64", rows, cols, np.ones(2 * L), L + 1, L + 1)
+    C = ctx.contract("plus_times", "ik", G, "kj", G, "ij", schedule=0)
+    rp, col, val = C.to_host()
+    assert C.nnz == L * L + 1 and col[0] == 0 and val[0] == L and np.all(val[1:] == 1.0)
+    # identity (x) A == A, bit-exact even for fp (one term per entry)
+    src, dst = synth.er_edges(700, 7, seed=21)
+    A, _ = pair_inputs(ctx, "plus_times", "f32", src, dst, 700, 21)
+    I = gpu_fold(ctx, "plus_times", "f32", np.arange(700), np.arange(700), np.ones(700, np.float32), 700, 700)
+    for X in (ctx.contract("plus_times", "ik", I, "kj", A, "ij"), ctx.contract("plus_times", "ik", A, "kj", I, "ij")):
+        for a, b in zip(X.to_host(), A.to_host()):
+            assert np.array_equal(a, b)
+
+
+def test_spgemm_empty_and_rectangular(ctx):
+    say("empty / rectangular")
+    E = gpu_fold(ctx, "min_plus", "i32", [], [], np.zeros(0, np.int32), 40, 30)
+    B = gpu_fold(ctx, "min_plus", "i32", [0, 5, 29], [1, 2, 3], np.array([1, 2, 3], np.int32), 30, 50)
+    C = ctx.contract("min_plus", "ik", E, "kj", B, "ij")
+    assert C.nnz == 0 and C.shape == (40, 50)
+    key = synth.stream_key(31, 0)
+    r = synth.randint(key, 900, 0, 59)
+    c = synth.randint(synth.stream_key(31, 1), 900, 0, 16)
+    v = values("min_plus", "i32", 900, 31)
+    A = gpu_fold(ctx, "min_plus", "i32", r, c, v, 60, 17)
+    OA = oracle.fold("min_plus", "i32", r, c, v, 60, 17)
+    r2 = synth.randint(synth.stream_key(31, 2), 300, 0, 16)
+    c2 = synth.randint(synth.stream_key(31, 3), 300, 0, 99)
+    v2 = values("min_plus", "i32", 300, 32)
+    B = gpu_fold(ctx, "min_plus", "i32", r2, c2, v2, 17, 100)
+    OB = oracle.fold("min_plus", "i32", r2, c2, v2, 17, 100)
+    check_csr(ctx.contract("min_plus", "ik", A, "kj", B, "ij"), oracle.spgemm("min_plus", "i32", OA, OB),
+              "min_plus", "i32")
+
+
+def test_spgemm_drops_identity_results(ctx):
+    # (+,x): a row whose two products cancel to exactly 0 is dropped
+    say("identity results dropped")
+    A = gpu_fold(ctx, "plus_times", "f64", [0, 0, 1], [0, 1, 1], np.array([1.0, 1.0, 2.0]), 2, 2)
+    B = gpu_fold(ctx, "plus_times", "f64", [0, 1], [0, 0], np.array([3.0, -3.0]), 2, 1)
+    for sch in range(srtc.NUM_SCHEDULES):
+        C = ctx.contract("plus_times", "ik", A, "kj", B, "ij", schedule=sch)
+        rp, col, val = C.to_host()
+        assert rp.tolist() == [0, 0, 1] and col.tolist() == [0] and val.tolist() == [-6.0]
+
+
+def test_spgemm_accumulate_path_doubling(ctx):
+    # APSP of the 64-vertex instance: (I (+) A)^n by ceil(log2 n) rounds of
+    # P (+)= P (x) P, against Floyd-Warshall
+    say("path doubling")
+    n = 64
+    src, dst = synth.er_edges(n, 8, synth.SEED_CFG0)
+    w = synth.edge_values("i32", src.size, synth.SEED_CFG0, lo=1, hi=100)
+    rows = np.concatenate([dst, np.arange(n)])
+    cols = np.concatenate([src, np.arange(n)])
+    vals = np.concatenate([w, np.zeros(n, np.int32)]).astype(np.int32)
+    P = gpu_fold(ctx, "min_plus", "i32", rows, cols, vals, n, n)
+    l = 1
+    while l < n:
+        Q = srtc.CSR(P.rowptr.clone(), P.col.clone(), P.val.clone(), P.dims, 1)
+        P = ctx.contract("min_plus", "ik", Q, "kj", Q, "ij", C=P, accumulate=True)
+        l <<= 1
+    D = np.full((n, n), INF, dtype=np.int64)
+    np.minimum.at(D, (dst, src), w.astype(np.int64))
+    np.fill_diagonal(D, 0)
+    FW = oracle.floyd_warshall(D)
+    rp, col, val = P.to_host()
+    got = np.full((n, n), INF, dtype=np.int64)
+    for i in range(n):
+        got[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    assert np.array_equal(got, FW)
+
+
+# ------------------------------------------------------------ cfg0 (ER 4096) --
+def test_er4096_tropical_square_and_bellman_ford(ctx):
+    say("ER 4096 (min,+)")
+    n = 4096
+    src, dst = synth.er_edges(n, 8, synth.SEED_CFG0)
+    w = synth.edge_values("i32", src.size, synth.SEED_CFG0, lo=1, hi=100)
+    G = gpu_fold(ctx, "min_plus", "i32", dst, src, w, n, n)
+    O = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+    for sch in range(srtc.NUM_SCHEDULES):
+        check_csr(ctx.contract("min_plus", "ik", G, "kj", G, "ij", schedule=sch), oracle.spgemm("min_plus", "i32", O, O),
+                  "min_plus", "i32")
+    # one Bellman-Ford relaxation step from vertex 0: P1 = P0 (+) A (x) P0
+    P0 = np.full((n, 1), INF, np.int32)
+    P0[0] = 0
+    X = torch.as_tensor(P0, device="cuda")
+    Y = X.clone()
+    ctx.contract("min_plus", "ij", G, "jk", X, "ik", C=Y, accumulate=True)
+    exp, _ = oracle.spmm("min_plus", "i32", O, P0, self_term=True)
+    assert np.array_equal(Y.cpu().numpy(), exp)
+    # the fixpoint: iterates and count as the oracle, distances as Dijkstra
+    X = torch.as_tensor(P0, device="cuda")
+    iters = ctx.fixpoint("min_plus", G, X, steps_per_check=4)
+    Pexp, it_exp, conv = oracle.bellman_ford("min_plus", "i32", O, P0)
+    assert conv and iters == it_exp
+    assert np.array_equal(X.cpu().numpy(), Pexp)
+    Dj = oracle.dijkstra(O, [0])
+    assert np.array_equal(X.cpu().numpy().astype(np.int64), Dj)
+
+
+# ------------------------------------------------------------------ SpMM --
+@pytest.mark.parametrize("semiring,dtype", PAIRS)
+@pytest.mark.parametrize("width", [1, 8, 64, 100])
+def test_spmm_parity(ctx, semiring, dtype, width):
+    say("spmm", semiring, dtype, width)
+    src, dst = synth.rmat_edges(12, 16, 0.57, 0.19, 0.19, seed=77)   # rows up to ~1k nonzeros (split items)
+    n = 1 << 12
+    G, O = pair_inputs(ctx, semiring, dtype, src, dst, n, 77)
+    key = synth.stream_key(77, 5)
+    X = values(semiring, dtype, n * width, 78).reshape(n, width)
+    absent = synth.uniform_f64(key, n * width).reshape(n, width) < 0.3
+    X = np.where(absent, np.asarray(oracle.default_add_id(semiring, dtype), dtype=X.dtype), X)
+    Xd = torch.as_tensor(np.ascontiguousarray(X), device="cuda")
+    Y = torch.empty_like(Xd)
+    ctx.contract(semiring, "ik", G, "kj", Xd, "ij", C=Y)
+    exp, _ = oracle.spmm(semiring, dtype, O, X)
+    got = Y.cpu().numpy()
+    if (semiring, dtype) in RTOL:
+        err = np.abs(got.astype(np.float64) - exp)
+        assert np.all(err <= RTOL[(semiring, dtype)] * np.abs(exp))
+    else:
+        assert np.array_equal(got, exp)
+
+
+def test_tensor_fold_contraction(ctx):
+    # T["ijk"] * M["kl"] -> C["ijl"] with T sparse COO (folded on the fly)
+    for dims, p, L in (((40, 30, 50), 0.02, 16), ((512, 512, 512), 1e-3, 64)):
+        say("tensor contraction", dims)
+        keys = synth.bernoulli_keys(dims, p, seed=synth.SEED_CFG1, tag=1)
+        tv = synth.uniform_f32(synth.stream_key(synth.SEED_CFG1, 11), keys.size)
+        M = synth.uniform_f32(synth.stream_key(synth.SEED_CFG1, 12), dims[2] * L).reshape(dims[2], L)
+        T = srtc.COO(torch.as_tensor(keys, device="cuda"), torch.as_tensor(tv, device="cuda"), dims)
+        C = torch.empty((dims[0], dims[1], L), dtype=torch.float32, device="cuda")
+        ctx.contract("plus_times", "ijk", T, "kl", torch.as_tensor(M, device="cuda"), "ijl", C=C)
+        F = oracle.fold_tensor("plus_times", "f32", keys, tv, dims, "ijk", "ij", "k")
+        exp, _ = oracle.spmm("plus_times", "f32", F, M)
+        got = C.cpu().numpy().reshape(dims[0] * dims[1], L).astype(np.float64)
+        assert np.all(np.abs(got - exp) <= 1e-5 * np.abs(exp))
+
+
+# ------------------------------------------------------- fixpoints / BFS --
+def test_multi_source_bellman_ford_and_bfs(ctx):
+    say("multi-source BF / BFS")
+    scale = 14
+    n = 1 << scale
+    src, dst = synth.rmat_edges(scale, 16, 0.57, 0.19, 0.19, seed=synth.SEED_CFG2)
+    w = synth.edge_values("i32", src.size, synth.SEED_CFG2, lo=1, hi=255)
+    G = gpu_fold(ctx, "min_plus", "i32", dst, src, w, n, n)
+    O = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+    sources = synth.pick_sources(n, src, 64, synth.SEED_CFG2)
+    P0 = np.full((n, 64), INF, np.int32)
+    P0[sources, np.arange(64)] = 0
+    X = torch.as_tensor(P0, device="cuda")
+    it = ctx.fixpoint("min_plus", G, X, steps_per_check=4)
+    Pexp, it_exp, conv = oracle.bellman_ford("min_plus", "i32", O, P0)
+    assert conv and it == it_exp
+    assert np.array_equal(X.cpu().numpy(), Pexp)
+    assert np.array_equal(Pexp.astype(np.int64), oracle.dijkstra(O, sources))
+    lev, depth = ctx.bfs_levels(G, sources)
+    exp = oracle.bfs_levels(O, sources)
+    assert np.array_equal(lev.cpu().numpy(), exp) and depth == exp.max()
+
+
+def test_fixpoint_not_converged_and_cap(ctx):
+    say("negative cycle / cap")
+    # 0 -> 1 -> 2 -> 0 with total weight -3: never settles
+    A = gpu_fold(ctx, "min_plus", "i32", [1, 2, 0], [0, 1, 2], np.array([1, 1, -5], np.int32), 3, 3)
+    X = torch.as_tensor(np.array([[0], [INF], [INF]], np.int32), device="cuda")
+    with pytest.raises(srtc.NotConverged) as e:
+        ctx.fixpoint("min_plus", A, X)
+    assert e.value.iters == 3
+    # path graph with a cap below its n steps
+    n = 50
+    P = gpu_fold(ctx, "min_plus", "i32", np.arange(1, n), np.arange(n - 1), np.ones(n - 1, np.int32), n, n)
+    X = torch.full((n, 1), INF, dtype=torch.int32, device="cuda")
+    X[0] = 0
+    with pytest.raises(srtc.NotConverged):
+        ctx.fixpoint("min_plus", P, X, max_iters=7, steps_per_check=4)
+    O = oracle.fold("min_plus", "i32", np.arange(1, n), np.arange(n - 1), np.ones(n - 1, np.int32), n, n)
+    X0 = np.full((n, 1), INF, np.int32)
+    X0[0] = 0
+    exp, _, _ = oracle.bellman_ford("min_plus", "i32", O, X0, max_iters=7)
+    assert np.array_equal(X.cpu().numpy(), exp)
+    X = torch.full((n, 1), INF, dtype=torch.int32, device="cuda")
+    X[0] = 0
+    assert ctx.fixpoint("min_plus", P, X, steps_per_check=6) == n
+
+
+# ------------------------------------------------------------- MFMA tile --
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dense_mfma(ctx, dtype):
+    say("dense mfma", dtype)
+    for (M, N, K) in ((16, 16, 4), (100, 70, 300), (257, 129, 1000)):
+        a = synth.uniform_f64(synth.stream_key(5, M), M * K).reshape(M, K)
+        b = synth.uniform_f64(synth.stream_key(6, N), K * N).reshape(K, N)
+        if dtype == "f32":
+            a, b = a.astype(np.float32), b.astype(np.float32)
+        C = torch.zeros((M, N), dtype=TORCH[dtype], device="cuda")
+        ctx.contract("plus_times", "ik", torch.as_tensor(a, device="cuda"), "kj", torch.as_tensor(b, device="cuda"),
+                     "ij", C=C)
+        ref = a.astype(np.float64) @ b.astype(np.float64)   # non-negative terms
+        tol = 1e-12 if dtype == "f64" else 1e-5
+        assert np.all(np.abs(C.cpu().numpy().astype(np.float64) - ref) <= tol * ref)
+
+
+# ----------------------------------------------------------------- batch --
+def test_batch_contract_and_fixpoint(ctx):
+    say("batch")
+    ns = [1, 200, 1500, 64, 3000, 0 + 1, 900]
+    As, Os, srcs = [], [], []
+    for b, n in enumerate(ns):
+        src, dst = synth.er_edges(n, 6, seed=1000 + b)
+        w = synth.edge_values("i32", src.size, 1000 + b, lo=1, hi=100)
+        As.append(gpu_fold(ctx, "min_plus", "i32", dst, src, w, n, n))
+        Os.append(oracle.fold("min_plus", "i32", dst, src, w, n, n))
+        srcs.append(src)
+    Cs = ctx.batch_contract("min_plus", As, As)
+    for C, O in zip(Cs, Os):
+        check_csr(C, oracle.spgemm("min_plus", "i32", O, O), "min_plus", "i32")
+    Xs, P0s = [], []
+    for b, n in enumerate(ns):
+        P0 = np.full((n, 8), INF, np.int32)
+        s = synth.pick_sources(n, srcs[b], 8, 2000 + b)
+        P0[s, np.arange(s.size)] = 0
+        P0s.append(P0)
+        Xs.append(torch.as_tensor(P0, device="cuda"))
+    iters = ctx.batch_fixpoint("min_plus", As, Xs, steps_per_check=4)
+    for X, O, P0, it in zip(Xs, Os, P0s, iters):
+        exp, it_exp, conv = oracle.bellman_ford("min_plus", "i32", O, P0)
+        assert conv and it == it_exp
+        assert np.array_equal(X.cpu().numpy(), exp)
+
+
+# -------------------------------------------------------------------- MLP --
+def test_mlp_gradients_match_oracle(ctx):
+    say("mlp gradients")
+    from oracle import mlp
+    K = srtc.NUM_SCHEDULES
+    P = mlp.num_params(K)
+    assert P == srtc.mlp_num_params()
+    key = synth.stream_key(44, 0)
+    p = (synth.uniform_f64(key, P) - 0.5) * 0.4
+    X = synth.uniform_f64(synth.stream_key(44, 1), 50 * 32).reshape(50, 32) * 2 - 1
+    T = synth.uniform_f64(synth.stream_key(44, 2), 50 * K).reshape(50, K)
+    p32, X32, T32 = p.astype(np.float32), X.astype(np.float32), T.astype(np.float32)
+    loss, g = ctx.mlp_loss_grad(torch.as_tensor(p32, device="cuda"), torch.as_tensor(X32, device="cuda"),
+                                torch.as_tensor(T32, device="cuda"))
+    lref, gref = mlp.loss_grad(p32.astype(np.float64), X32.astype(np.float64), T32.astype(np.float64), K)
+    gg = g.cpu().numpy().astype(np.float64)
+    assert abs(loss.item() - lref) <= 1e-4 * abs(lref)
+    assert np.linalg.norm(gg - gref) <= 1e-4 * np.linalg.norm(gref)
+    Y = ctx.mlp_forward(torch.as_tensor(p32, device="cuda"), torch.as_tensor(X32, device="cuda")).cpu().numpy()
+    yref, _ = mlp.forward(p32.astype(np.float64), X32.astype(np.float64), K)
+    assert np.abs(Y - yref).max() <= 1e-4 * max(1.0, np.abs(yref).max())
+    z = np.zeros(P, np.float32)
+    z[-K:] = np.arange(K)
+    Yz = ctx.mlp_forward(torch.as_tensor(z, device="cuda"), torch.as_tensor(X32, device="cuda")).cpu().numpy()
+    assert np.array_equal(Yz, np.tile(np.arange(K, dtype=np.float32), (50, 1)))
+
+
+def test_selector_overfits_tiny_set(ctx, tmp_path):
+    say("selector overfit")
+    c2 = srtc.Context(0)
+    X = synth.uniform_f32(synth.stream_key(45, 0), 16 * 32).reshape(16, 32)
+    best = synth.randint(synth.stream_key(45, 1), 16, 0, srtc.NUM_SCHEDULES - 1)
+    T = np.ones((16, srtc.NUM_SCHEDULES), np.float32)
+    T[np.arange(16), best] = -1.0
+    loss = c2.selector_train(X, T, epochs=1500, batch=16, lr=3e-3, seed=1)
+    assert loss < 1e-3
+    picks = [c2.select(X[i]) for i in range(16)]
+    assert picks == best.tolist()
+    path = str(tmp_path / "sel.bin")
+    c2.selector_save(path)
+    c3 = srtc.Context(0)
+    c3.selector_load(path)
+    assert [c3.select(X[i]) for i in range(16)] == picks
+
+
+# ----------------------------------------------------------------- errors --
+def test_error_statuses(ctx):
+    say("error statuses")
+    A = gpu_fold(ctx, "min_plus", "i32", [0], [1], np.array([1], np.int32), 3, 4)
+    B = gpu_fold(ctx, "min_plus", "i32", [0], [1], np.array([1], np.int32), 4, 5)
+    cases = [
+        (dict(ia="ik", ib="kj", ic="ii"), -2),           # repeated index
+        (dict(ia="ik", ib="kj", ic="ixj"), -2),           # length / index only in output
+        (dict(ia="ik", ib="lj", ic="ij"), -2),            # index only in one operand (reduction)
+        (dict(ia="ik", ib="jk", ic="ij"), -3),            # extents of k differ
+        (dict(ia="ik", ib="kj", ic="ji"), -9),            # output interleaves... column before row
+    ]
+    for kw, st in cases:
+        with pytest.raises(srtc.SrtcError) as e:
+            ctx.contract("min_plus", kw["ia"], A, kw["ib"], B, kw["ic"])
+        assert e.value.status == st, kw
+    F = gpu_fold(ctx, "plus_times", "f32", [0], [1], np.array([1], np.float32), 3, 4)
+    with pytest.raises(srtc.SrtcError) as e:
+        ctx.contract("min_plus", "ik", F, "kj", B, "ij")  # mixed value types
+    assert e.value.status == -4
+    with pytest.raises(srtc.SrtcError) as e:
+        ctx.contract("or_and", "ik", A, "kj", B, "ij")    # int32 not defined for (or,and)
+    assert e.value.status == -4
+    X = torch.zeros((4, 5), dtype=torch.int32, device="cuda")
+    with pytest.raises(srtc.SrtcError) as e:
+        ctx.contract("min_plus", "ik", A, "kj", X, "ij", C=X[:3])   # C is a view of B
+    assert e.value.status == -6

@@ -364,3 +364,25 @@ def test_spmm_matches_brute_force(semiring, dtype):
         np.testing.assert_allclose(Y, exp, rtol=1e-14)
     else:
         assert np.array_equal(Y.astype(np.float64), exp.astype(np.float64))
+
+
+def test_mlp_oracle_gradient_matches_finite_differences():
+    from oracle import mlp
+    K = 8
+    rng = np.random.default_rng(3)
+    p = rng.normal(0, 0.3, mlp.num_params(K))
+    X = rng.normal(0, 1, (7, 32))
+    T = rng.normal(0, 1, (7, K))
+    loss, g = mlp.loss_grad(p, X, T, K)
+    idx = rng.choice(p.size, 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = h
+        fd = (mlp.loss_grad(p + e, X, T, K)[0] - mlp.loss_grad(p - e, X, T, K)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9
+    # a network with zero weights outputs its last bias exactly
+    z = np.zeros(mlp.num_params(K))
+    z[-K:] = np.arange(K)
+    y, _ = mlp.forward(z, X, K)
+    assert np.array_equal(y, np.tile(np.arange(K, dtype=float), (7, 1)))
