@@ -24,11 +24,13 @@
  *     Work is enqueued on it; calls that must know an output size
  *     synchronize that stream once (documented per call).
  *   - Inputs are borrowed: they must stay valid until the stream work ends.
- *   - Every device buffer the library needs (outputs and scratch) comes from
- *     the context's allocator callback; outputs become the caller's, scratch
- *     is returned through the free callback before the call returns (the
- *     allocator must therefore be stream-ordered, e.g. a caching allocator
- *     bound to `stream`, or a synchronous one).
+ *   - Device memory comes from the context's allocator callback (outputs,
+ *     which become the caller's, and scratch, returned through the free
+ *     callback before the call ends).  The allocator must be stream-ordered
+ *     (a caching allocator bound to `stream`, as torch's is) or synchronous.
+ *     Without a callback, outputs come from hipMalloc and scratch from a
+ *     per-context cache of hipMalloc blocks kept until srtc_ctx_destroy.
+ *   - Environment: SRTC_TRACE=1 prints each phase of every call to stderr.
  *   - No call aborts and no C++ exception crosses the ABI: failures return a
  *     negative srtc_status and srtc_last_error() describes the last one.
  *   - An operand entry equal to the additive identity is absent; output
@@ -145,6 +147,20 @@ srtc_status srtc_ctx_destroy(srtc_ctx *ctx);
 /* Message for the last failed call on this context (never NULL). */
 const char *srtc_last_error(const srtc_ctx *ctx);
 const char *srtc_status_string(srtc_status st);
+
+/* ------------------------------------------------------------ profile -- */
+
+/* Per-kernel profile (for measuring a kernel against its roofline).  While
+ * enabled, every kernel launch outside graph capture is bracketed by HIP
+ * events recorded on the stream it runs on, and the launch's algorithmic
+ * byte count (what the operation must read and write, not what the cache
+ * hierarchy moves) is added to its entry.  Enabling clears the table. */
+srtc_status srtc_profile_enable(srtc_ctx *ctx, int32_t on);
+/* Entry idx (0-based; SRTC_ERR_ARG past the end): kernel name (copied into
+ * name[name_len], host), launches, total milliseconds and total algorithmic
+ * bytes.  Waits for the recorded events. */
+srtc_status srtc_profile_query(srtc_ctx *ctx, int32_t idx, char *name, int32_t name_len, int64_t *launches,
+                               double *total_ms, double *total_bytes);
 
 /* ---------------------------------------------------------------- fold -- */
 

@@ -6,7 +6,9 @@
 // to the kernels.  No exception crosses the ABI.
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <limits>
 #include <new>
 #include <string>
@@ -18,15 +20,53 @@
 namespace srtc {
 
 // ------------------------------------------------------------- memory --
+// Device memory.  With an allocator callback every buffer (output or
+// scratch) comes from it -- a caching, stream-ordered allocator such as
+// torch's is expected.  Without one, outputs come from hipMalloc and scratch
+// from a per-context cache of hipMalloc blocks (power-of-two size classes),
+// reused in the order of the context's stream; a call on a different stream
+// first waits for the previous one.
+static int size_class(size_t bytes) {
+  int c = 8;  // 256 bytes minimum
+  while (((size_t)1 << c) < bytes) c++;
+  return c;
+}
+
+void Ctx::release_cache() {
+  if (block_class.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto &kv : block_class) (void)hipFree(kv.first);
+  block_class.clear();
+  for (auto &v : free_blocks) v.clear();
+}
+
 void *Ctx::raw_alloc(size_t bytes, int kind) {
   if (bytes == 0) bytes = 1;
   void *p = nullptr;
-  if (kind == OUTPUT && alloc) {
+  if (alloc) {
     p = alloc(user, bytes);
   } else if (kind == OUTPUT) {
-    if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      release_cache();
+      if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    }
   } else {
-    if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
+    if (cache_stream != stream) {
+      // blocks freed on the previous stream may still be in use there
+      SRTC_HIP(hipStreamSynchronize(cache_stream));
+      cache_stream = stream;
+    }
+    const int c = size_class(bytes);
+    if (!free_blocks[c].empty()) {
+      p = free_blocks[c].back();
+      free_blocks[c].pop_back();
+    } else {
+      if (hipMalloc(&p, (size_t)1 << c) != hipSuccess) {
+        release_cache();
+        if (hipMalloc(&p, (size_t)1 << c) != hipSuccess) p = nullptr;
+      }
+      if (p) block_class[p] = c;
+    }
   }
   if (!p) fail(SRTC_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   return p;
@@ -34,12 +74,25 @@ void *Ctx::raw_alloc(size_t bytes, int kind) {
 
 void Ctx::raw_free(void *p, int kind) {
   if (!p) return;
-  if (kind == OUTPUT) {
-    if (free_fn) free_fn(user, p);
-    else (void)hipFree(p);
+  if (free_fn) {
+    free_fn(user, p);
+  } else if (kind == OUTPUT) {
+    (void)hipFree(p);
   } else {
-    (void)hipFreeAsync(p, stream);
+    auto it = block_class.find(p);
+    if (it != block_class.end()) free_blocks[it->second].push_back(p);
   }
+}
+
+void Ctx::tracef(const char *fmt, ...) {
+  if (!trace) return;
+  va_list ap;
+  va_start(ap, fmt);
+  fprintf(stderr, "[srtc] ");
+  vfprintf(stderr, fmt, ap);
+  fprintf(stderr, "\n");
+  fflush(stderr);
+  va_end(ap);
 }
 
 void *Ctx::host_scratch(size_t bytes) {
@@ -51,6 +104,56 @@ void *Ctx::host_scratch(size_t bytes) {
     pinned_bytes = nb;
   }
   return pinned;
+}
+
+// ------------------------------------------------------------ profile --
+static hipEvent_t take_event(Ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  SRTC_HIP(hipEventCreate(&e));
+  return e;
+}
+
+ProfScope::ProfScope(Ctx *ctx, const char *name, double algorithmic_bytes, hipStream_t stream)
+    : c(ctx), bytes(algorithmic_bytes), s(stream) {
+  if (!c || !c->profiling) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  for (size_t q = 0; q < c->prof.size(); q++)
+    if (c->prof[q].name == name) slot = (int)q;
+  if (slot < 0) {
+    c->prof.push_back(Ctx::ProfAgg{name});
+    slot = (int)c->prof.size() - 1;
+  }
+  e0 = take_event(c);
+  e1 = take_event(c);
+  SRTC_HIP(hipEventRecord(e0, s));
+}
+
+ProfScope::~ProfScope() {
+  if (slot < 0) return;
+  if (hipEventRecord(e1, s) == hipSuccess) c->prof_pending.push_back(Ctx::ProfPending{slot, e0, e1, bytes});
+  if (c->prof_pending.size() > 4096) {
+    try { c->prof_resolve(); } catch (...) {}
+  }
+}
+
+void Ctx::prof_resolve() {
+  for (auto &p : prof_pending) {
+    SRTC_HIP(hipEventSynchronize(p.e1));
+    float ms = 0.f;
+    SRTC_HIP(hipEventElapsedTime(&ms, p.e0, p.e1));
+    prof[p.slot].launches++;
+    prof[p.slot].ms += ms;
+    prof[p.slot].bytes += p.bytes;
+    event_pool.push_back(p.e0);
+    event_pool.push_back(p.e1);
+  }
+  prof_pending.clear();
 }
 
 Buf::Buf(Ctx *c, size_t n, int k) : ctx(c), p(nullptr), bytes(n), kind(k) { p = c->raw_alloc(n, k); }
@@ -360,18 +463,41 @@ srtc_status srtc_ctx_create(int device, srtc_alloc_fn alloc, srtc_free_fn free_f
     c->c.num_cus = prop.multiProcessorCount;
     c->c.lds_per_block = prop.sharedMemPerBlock;
   }
-  // keep freed scratch in the device's stream-ordered pool
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
+  const char *tr = getenv("SRTC_TRACE");
+  c->c.trace = tr && *tr && *tr != '0';
   *out = c;
   return SRTC_OK;
 }
 
+srtc_status srtc_profile_enable(srtc_ctx *ctx, int32_t on) {
+  return guard(ctx, [&] {
+    ctx->c.prof_resolve();
+    ctx->c.prof.clear();
+    ctx->c.profiling = on != 0;
+  });
+}
+
+srtc_status srtc_profile_query(srtc_ctx *ctx, int32_t idx, char *name, int32_t name_len, int64_t *launches,
+                               double *total_ms, double *total_bytes) {
+  return guard(ctx, [&] {
+    ctx->c.prof_resolve();
+    if (idx < 0 || idx >= (int32_t)ctx->c.prof.size()) fail(SRTC_ERR_ARG, "no such profile entry");
+    const Ctx::ProfAgg &a = ctx->c.prof[idx];
+    if (name && name_len > 0) {
+      strncpy(name, a.name.c_str(), (size_t)name_len - 1);
+      name[name_len - 1] = 0;
+    }
+    if (launches) *launches = a.launches;
+    if (total_ms) *total_ms = a.ms;
+    if (total_bytes) *total_bytes = a.bytes;
+  });
+}
+
 srtc_status srtc_ctx_destroy(srtc_ctx *ctx) {
   if (!ctx) return SRTC_ERR_ARG;
+  try { ctx->c.prof_resolve(); } catch (...) {}
+  for (auto e : ctx->c.event_pool) (void)hipEventDestroy(e);
+  ctx->c.release_cache();
   if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
   mlp_destroy(ctx->c.mlp);
   delete ctx;
@@ -397,6 +523,7 @@ srtc_status srtc_fold(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const
     const IdVal id = make_id(sr, src->dtype, add_id);
     hipStream_t s = (hipStream_t)stream;
     ctx->c.stream = s;
+    ctx->c.tracef("srtc_fold %s -> (%s)(%s), %lld entries", idx.c_str(), r.c_str(), cl.c_str(), (long long)src->nnz);
     Folded f;
     fold_sparse(&ctx->c, sr, id, src, idx, r, cl, &f, s, true);
     int64_t dims[SRTC_MAX_ORDER];
@@ -423,6 +550,7 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
     hipStream_t s = (hipStream_t)stream;
     ctx->c.stream = s;
     Ctx *c = &ctx->c;
+    c->tracef("srtc_contract %s,%s->%s semiring %d dtype %d", a.c_str(), b.c_str(), cidx.c_str(), (int)sr, dt);
     const std::string crow = rows_of_c(cidx, p);  // batch + M letters in C order
     std::string acol = p.batch, brow = p.batch, bcol = p.batch;
     acol += p.K;
@@ -502,7 +630,12 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
       const void *Ad = dense_in_order(A, a, p.M + p.K, &ta);
       const void *Bd = dense_in_order(B, b, p.K + p.N, &tb);
       if (crow != p.M) fail(SRTC_ERR_UNSUPPORTED, "dense output row order");
-      dense_gemm_plus_times(c, dt, Ad, Bd, C->vals, extent(p, p.M), extent(p, p.N), extent(p, p.K), accumulate, s);
+      {
+        const double es = (double)dtype_size(dt);
+        const double M_ = (double)extent(p, p.M), N_ = (double)extent(p, p.N), K_ = (double)extent(p, p.K);
+        ProfScope ps(c, "dense.gemm_mfma", es * (M_ * K_ + K_ * N_ + M_ * N_ * (accumulate ? 2 : 1)), s);
+        dense_gemm_plus_times(c, dt, Ad, Bd, C->vals, extent(p, p.M), extent(p, p.N), extent(p, p.K), accumulate, s);
+      }
       return;
     }
     fail(SRTC_ERR_UNSUPPORTED, "dense A with sparse B: swap the operands");
@@ -557,6 +690,7 @@ srtc_status srtc_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, c
         (void)hipStreamDestroy(*cap);
       }
     } cleanup{&cap, &graph, &exec};
+    c->tracef("srtc_fixpoint n=%lld s=%lld, capturing %d steps", (long long)n, (long long)sw, k);
     SRTC_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     for (int t = 0; t < k; t++) step(t, t & 1, cap);
     SRTC_HIP(hipStreamEndCapture(cap, &graph));
@@ -618,7 +752,10 @@ srtc_status srtc_bfs_levels(srtc_ctx *ctx, const srtc_tensor *A, const int64_t *
     int32_t depth = 0;
     for (int level = 1; level <= n; level++) {
       fill_i32(chg.as<int32_t>(), 1, 0, s);
-      bfs_step(av, cur, vis.as<uint64_t>(), nxt, levels, nsrc, level, chg.as<int32_t>(), s);
+      {
+        ProfScope ps(c, "bfs.step", 4.0 * av.nnz + 8.0 * (n + 1) + 24.0 * n, s);
+        bfs_step(av, cur, vis.as<uint64_t>(), nxt, levels, nsrc, level, chg.as<int32_t>(), s);
+      }
       int32_t h = 0;
       read_to_host(c, &h, chg.p, sizeof(int32_t), s);
       if (!h) break;

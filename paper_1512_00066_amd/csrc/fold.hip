@@ -277,11 +277,17 @@ void radix_sort_pairs(Ctx *c, int64_t *keys, uint32_t *payload, int64_t n, int b
   const int passes = (bits + 7) / 8;
   for (int ps = 0; ps < passes; ps++) {
     const int shift = ps * 8;
-    radix_hist<<<(unsigned)ntiles, RS_BS, 0, s>>>(ka, n, shift, hist.as<int32_t>(), ntiles);
-    SRTC_LAUNCH_CHECK("radix_hist");
+    {
+      ProfScope ps(c, "fold.radix_hist", 8.0 * n + 4.0 * RS_DIG * ntiles, s);
+      radix_hist<<<(unsigned)ntiles, RS_BS, 0, s>>>(ka, n, shift, hist.as<int32_t>(), ntiles);
+      SRTC_LAUNCH_CHECK("radix_hist");
+    }
     excl_scan_i32(c, hist.as<int32_t>(), offs.as<int64_t>(), RS_DIG * ntiles, s);
-    radix_scatter<<<(unsigned)ntiles, RS_BS, 0, s>>>(ka, pa, kb, pb, n, shift, offs.as<int64_t>(), ntiles);
-    SRTC_LAUNCH_CHECK("radix_scatter");
+    {
+      ProfScope ps(c, "fold.radix_scatter", 24.0 * n + 8.0 * RS_DIG * ntiles, s);
+      radix_scatter<<<(unsigned)ntiles, RS_BS, 0, s>>>(ka, pa, kb, pb, n, shift, offs.as<int64_t>(), ntiles);
+      SRTC_LAUNCH_CHECK("radix_scatter");
+    }
     std::swap(ka, kb);
     std::swap(pa, pb);
   }
@@ -313,6 +319,7 @@ void fold_keys_to_csr(Ctx *c, int sr, int dt, IdVal id, const int64_t *keys_in, 
   const unsigned __int128 span = (unsigned __int128)nrows * (unsigned __int128)ncols;
   int bits = 0;
   while (bits < 63 && ((unsigned __int128)1 << bits) < span) bits++;
+  c->tracef("fold: %lld keys, %lld x %lld, %d key bits", (long long)nnz, (long long)nrows, (long long)ncols, bits);
   radix_sort_pairs(c, keys.as<int64_t>(), perm.as<uint32_t>(), nnz, bits, s);
   // segments of equal keys
   Buf flag(c, sizeof(int32_t) * (size_t)nnz), segid(c, sizeof(int64_t) * (size_t)(nnz + 1));
@@ -330,6 +337,7 @@ void fold_keys_to_csr(Ctx *c, int sr, int dt, IdVal id, const int64_t *keys_in, 
   Buf pos(c, sizeof(int64_t) * (size_t)(nnz + 1));
   excl_scan_i32(c, keep.as<int32_t>(), pos.as<int64_t>(), nnz, s);
   const int64_t total = read_i64(c, pos.as<int64_t>() + nnz, s);
+  c->tracef("fold: %lld entries after combining duplicates", (long long)total);
   out->nnz = total;
   out->col = Buf(c, sizeof(int32_t) * (size_t)(total > 0 ? total : 1), out->kind);
   out->val = Buf(c, es * (size_t)(total > 0 ? total : 1), out->kind);

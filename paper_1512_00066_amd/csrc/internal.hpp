@@ -27,12 +27,49 @@ struct Ctx {
   // pinned host scratch for small device->host reads
   void *pinned = nullptr;
   size_t pinned_bytes = 0;
-  // stream of the call in progress (scratch memory is ordered on it)
+  // stream of the call in progress (kernels and scratch reuse follow it)
   hipStream_t stream = nullptr;
+  // scratch cache used when no allocator callback is given: freed scratch
+  // blocks are kept by power-of-two size class and reused in stream order
+  std::map<void *, int> block_class;
+  std::vector<std::vector<void *>> free_blocks = std::vector<std::vector<void *>>(64);
+  hipStream_t cache_stream = nullptr;
+  bool trace = false;
+  void release_cache();
+  void tracef(const char *fmt, ...);
+  // per-kernel profile: HIP events around each launch on its stream, with
+  // the launch's algorithmic bytes; resolved when queried
+  struct ProfPending {
+    int slot;
+    hipEvent_t e0, e1;
+    double bytes;
+  };
+  struct ProfAgg {
+    std::string name;
+    int64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
+  };
+  bool profiling = false;
+  std::vector<ProfPending> prof_pending;
+  std::vector<ProfAgg> prof;
+  std::vector<hipEvent_t> event_pool;
+  void prof_resolve();
 
   void *raw_alloc(size_t bytes, int kind);
   void raw_free(void *p, int kind);
   void *host_scratch(size_t bytes);
+};
+
+// Records the enclosed launches as one profiled kernel (no-op unless
+// profiling is on, or while the stream is being captured into a graph).
+struct ProfScope {
+  Ctx *c = nullptr;
+  int slot = -1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double bytes = 0;
+  hipStream_t s = nullptr;
+  ProfScope(Ctx *ctx, const char *name, double algorithmic_bytes, hipStream_t stream);
+  ~ProfScope();
 };
 
 // A device CSR matrix view (not owning).
@@ -146,10 +183,16 @@ struct srtc_ctx {
 };
 
 namespace srtc {
+// The context's stream is saved and restored, so an entry point called from
+// inside another keeps the outer call's stream for its scratch memory.
 template <class F> srtc_status guard(srtc_ctx *ctx, F &&f) {
+  if (!ctx) return SRTC_ERR_ARG;
+  struct Restore {
+    Ctx *c;
+    hipStream_t s;
+    ~Restore() { c->stream = s; }
+  } restore{&ctx->c, ctx->c.stream};
   try {
-    if (!ctx) return SRTC_ERR_ARG;
-    ctx->c.stream = nullptr;
     SRTC_HIP(hipSetDevice(ctx->c.device));
     f();
     return SRTC_OK;

@@ -303,7 +303,7 @@ srtc_status srtc_select(srtc_ctx *ctx, const float *features, int32_t *schedule_
     if (!c->mlp) fail(SRTC_ERR_UNSUPPORTED, "no selector network loaded");
     float xn[IN];
     normalize(c->mlp, features, xn, 1);
-    hipStream_t s = nullptr;
+    hipStream_t s = c->stream;  // the caller's stream when nested in a contraction
     Buf P(c, 4ull * NPARAM), Xd(c, 4ull * IN), Yd(c, 4ull * K);
     SRTC_HIP(hipMemcpyAsync(P.p, c->mlp->params.data(), 4ull * NPARAM, hipMemcpyHostToDevice, s));
     SRTC_HIP(hipMemcpyAsync(Xd.p, xn, 4ull * IN, hipMemcpyHostToDevice, s));

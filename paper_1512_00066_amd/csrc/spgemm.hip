@@ -57,8 +57,11 @@ struct Thresholds {
 };
 
 // info layout: [0..NBIN) counts, [NBIN..2NBIN) starts, [2NBIN..3NBIN) cursors,
-// [3NBIN..4NBIN) work counters, [4NBIN] sum of values
-constexpr int INFO = 4 * NBIN + 2;
+// [3NBIN..4NBIN) work counters, [4NBIN] sum of values, [SUMV..SUMV+NBIN)
+// per-bin sums of values, [SUMA..SUMA+NBIN) per-bin sums of A row lengths
+constexpr int SUMV = 4 * NBIN + 1;
+constexpr int SUMA = 5 * NBIN + 1;
+constexpr int INFO = 6 * NBIN + 2;
 
 __device__ __forceinline__ int bin_of(int64_t v, const Thresholds &th) {
   if (v <= 0) return 0;
@@ -68,23 +71,33 @@ __device__ __forceinline__ int bin_of(int64_t v, const Thresholds &th) {
   return NBIN - 1;
 }
 
-__global__ void bin_count(const int64_t *v, int64_t m, Thresholds th, int64_t *info) {
+__global__ void bin_count(const int64_t *v, int64_t m, Thresholds th, int64_t *info, const int64_t *rpA,
+                          const int32_t *row_map) {
   __shared__ int32_t cnt[NBIN];
+  __shared__ unsigned long long sv[NBIN], sa[NBIN];
   __shared__ unsigned long long sum;
-  if (threadIdx.x < NBIN) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < NBIN) { cnt[threadIdx.x] = 0; sv[threadIdx.x] = 0; sa[threadIdx.x] = 0; }
   if (threadIdx.x == 0) sum = 0;
   __syncthreads();
   unsigned long long local = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = v[i];
-    atomicAdd(&cnt[bin_of(x, th)], 1);
+    const int b = bin_of(x, th);
+    const int64_t r = row_map ? row_map[i] : i;
+    atomicAdd(&cnt[b], 1);
+    atomicAdd(&sv[b], (unsigned long long)x);
+    atomicAdd(&sa[b], (unsigned long long)(rpA[r + 1] - rpA[r]));
     local += (unsigned long long)x;
   }
   local = wave_sum(local);
   if (lane_id() == 0) atomicAdd(&sum, local);
   __syncthreads();
-  if (threadIdx.x < NBIN) atomicAdd((unsigned long long *)&info[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+  if (threadIdx.x < NBIN) {
+    atomicAdd((unsigned long long *)&info[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+    atomicAdd((unsigned long long *)&info[SUMV + threadIdx.x], sv[threadIdx.x]);
+    atomicAdd((unsigned long long *)&info[SUMA + threadIdx.x], sa[threadIdx.x]);
+  }
   if (threadIdx.x == 0) atomicAdd((unsigned long long *)&info[4 * NBIN], sum);
 }
 
@@ -197,7 +210,7 @@ __global__ void __launch_bounds__(BS) sym_hash(const int32_t *__restrict__ list,
                                                int bin, const int64_t *__restrict__ rpA,
                                                const int32_t *__restrict__ cA, const int64_t *__restrict__ rpB,
                                                const int32_t *__restrict__ cB, int64_t *__restrict__ nnz_row,
-                                               int64_t *ctr) {
+                                               int64_t *ctr, int64_t *err) {
   constexpr int LG = __builtin_ctz(TBL);
   __shared__ int32_t keys[TBL];
   __shared__ Chunk<BS, uint8_t> L;
@@ -214,7 +227,10 @@ __global__ void __launch_bounds__(BS) sym_hash(const int32_t *__restrict__ list,
     for_products<BS, false, uint8_t>(rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr, i,
                                      nullptr, 0, 0, L, [&](int32_t j, uint8_t, uint8_t) {
       uint32_t h = hash_slot(j, LG);
-      for (;;) {
+      // the table is sized to at least twice the row's products; the probe
+      // bound only guards against a broken invariant
+      for (int probes = 0;; probes++) {
+        if (probes >= TBL) { atomicAdd((unsigned long long *)err, 1ull); break; }
         const int32_t k = keys[h];
         if (k == j) break;
         if (k == EMPTY) {
@@ -304,15 +320,18 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
     for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nullptr, 0, 0, L, [&](int32_t j, V a, V b) {
       if (SR::HAS_VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
       uint32_t h = hash_slot(j, LG);
-      for (;;) {
+      // the table holds at least twice the row's (symbolic) outputs
+      bool placed = false;
+      for (int probes = 0; probes < TBL; probes++) {
         const int32_t k = keys[h];
-        if (k == j) break;
+        if (k == j) { placed = true; break; }
         if (k == EMPTY) {
           const int32_t old = atomicCAS(&keys[h], EMPTY, j);
-          if (old == EMPTY || old == j) break;
+          if (old == EMPTY || old == j) { placed = true; break; }
         }
         h = (h + 1) & (TBL - 1);
       }
+      if (!placed) { atomicOr(any_short + 1, 1); return; }
       if (SR::HAS_VALS) SR::lds_add(&vals[h], SR::mul(a, b));
     });
     __syncthreads();
@@ -378,7 +397,7 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
             const int32_t j = (int32_t)(w0 + u * 32 + b);
             if (SR::HAS_VALS) {
               uint32_t h = hash_slot(j, LG);
-              while (keys[h] != j) h = (h + 1) & (TBL - 1);
+              for (int probes = 0; keys[h] != j && probes < TBL; probes++) h = (h + 1) & (TBL - 1);
               if (SR::acc_absent(vals[h], id)) continue;
             }
             mine++;
@@ -395,7 +414,7 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
             A v = (A)1;
             if (SR::HAS_VALS) {
               uint32_t h = hash_slot(j, LG);
-              while (keys[h] != j) h = (h + 1) & (TBL - 1);
+              for (int probes = 0; keys[h] != j && probes < TBL; probes++) h = (h + 1) & (TBL - 1);
               v = vals[h];
               if (SR::acc_absent(v, id)) continue;
             }
@@ -589,11 +608,11 @@ struct Launch {
 
 template <int BS, int TBL>
 void launch_sym_hash(const Launch &L, int64_t rows, const int32_t *list, const int64_t *info, int bin,
-                     const CsrView &A, const CsrView &B, int64_t *nnz_row, int64_t *ctr) {
+                     const CsrView &A, const CsrView &B, int64_t *nnz_row, int64_t *ctr, int64_t *err) {
   if (rows == 0) return;
   const int lds = TBL * 4 + sizeof(Chunk<BS, uint8_t>) + 64;
   sym_hash<BS, TBL><<<L.grid(rows, lds, BS), BS, 0, L.s>>>(list, info, bin, A.rowptr, A.col, B.rowptr, B.col,
-                                                           nnz_row, ctr);
+                                                           nnz_row, ctr, err);
   SRTC_LAUNCH_CHECK("sym_hash");
 }
 
@@ -611,7 +630,8 @@ int32_t bitmap_words(int64_t ncols, int bs, int64_t budget_bytes) {
 // row_map, or 0..nsel-1): nnz_row[row] for each.  Returns the product total.
 // Synchronizes once (bin sizes).
 int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, const CsrView &Bm, const int64_t *wsel,
-                     const int32_t *row_map, int64_t nsel, int64_t *info1, int32_t *list, int64_t *nnz_row) {
+                     const int32_t *row_map, int64_t nsel, int64_t *info1, int32_t *list, int64_t *nnz_row,
+                     int64_t *err) {
   hipStream_t s = L.s;
   Ctx *c = L.c;
   const int64_t n = Bm.n;
@@ -627,7 +647,7 @@ int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, cons
       prev = th1.t[b];
     }
   }
-  bin_count<<<gridn(nsel, 256, 2048), 256, 0, s>>>(wsel, nsel, th1, info1);
+  bin_count<<<gridn(nsel, 256, 2048), 256, 0, s>>>(wsel, nsel, th1, info1, Am.rowptr, row_map);
   SRTC_LAUNCH_CHECK("bin_count");
   bin_offsets<<<1, 64, 0, s>>>(info1);
   bin_scatter<<<gridn(nsel, 256, 4096), 256, 0, s>>>(wsel, nsel, th1, info1, list, row_map);
@@ -635,11 +655,24 @@ int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, cons
   int64_t hinfo[INFO];
   read_to_host(c, hinfo, info1, sizeof(hinfo), s);
   int64_t *ctr1 = info1 + 3 * NBIN;
-  launch_sym_hash<64, 64>(L, hinfo[1], list, info1, 1, Am, Bm, nnz_row, ctr1 + 1);
-  launch_sym_hash<64, 512>(L, hinfo[2], list, info1, 2, Am, Bm, nnz_row, ctr1 + 2);
-  launch_sym_hash<256, 4096>(L, hinfo[3], list, info1, 3, Am, Bm, nnz_row, ctr1 + 3);
-  launch_sym_hash<512, 16384>(L, hinfo[4], list, info1, 4, Am, Bm, nnz_row, ctr1 + 4);
+  // algorithmic bytes of a symbolic bin: its A rows (pointers + columns),
+  // B's columns once, one count per row
+  auto sym_bytes = [&](int b) {
+    return 16.0 * hinfo[b] + 4.0 * hinfo[SUMA + b] + 4.0 * Bm.nnz + 8.0 * (Bm.m + 1) + 8.0 * hinfo[b];
+  };
+  static const char *kSymName[NBIN] = {"", "spgemm.symbolic.hash64", "spgemm.symbolic.hash512",
+                                       "spgemm.symbolic.hash4096", "spgemm.symbolic.hash16384",
+                                       "spgemm.symbolic.bitmap"};
+  for (int b = 1; b < NBIN - 1; b++) {
+    if (hinfo[b] == 0) continue;
+    ProfScope ps(c, kSymName[b], sym_bytes(b), s);
+    if (b == 1) launch_sym_hash<64, 64>(L, hinfo[1], list, info1, 1, Am, Bm, nnz_row, ctr1 + 1, err);
+    if (b == 2) launch_sym_hash<64, 512>(L, hinfo[2], list, info1, 2, Am, Bm, nnz_row, ctr1 + 2, err);
+    if (b == 3) launch_sym_hash<256, 4096>(L, hinfo[3], list, info1, 3, Am, Bm, nnz_row, ctr1 + 3, err);
+    if (b == 4) launch_sym_hash<512, 16384>(L, hinfo[4], list, info1, 4, Am, Bm, nnz_row, ctr1 + 4, err);
+  }
   if (hinfo[5] > 0) {
+    ProfScope ps(c, kSymName[5], sym_bytes(5), s);
     constexpr int BS = 256;
     const int stat = (int)sizeof(Chunk<BS, uint8_t>) + 64;
     const int32_t ww = bitmap_words(n, BS, LDS_BYTES - stat - 1024);
@@ -719,15 +752,21 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
   }
   // 1-3. products per row, symbolic bins, symbolic pass
   Buf w(c, sizeof(int64_t) * (size_t)m);
-  row_products(Am, Bm, w.as<int64_t>(), s);
+  {
+    ProfScope ps(c, "spgemm.row_products", 16.0 * (m + 1) + 4.0 * Am.nnz + 8.0 * (Bm.m + 1), s);
+    row_products(Am, Bm, w.as<int64_t>(), s);
+  }
   Buf info(c, sizeof(int64_t) * INFO * 2);
   int64_t *info1 = info.as<int64_t>(), *info2 = info1 + INFO;
   fill_i64(info1, INFO * 2, 0, s);
   Buf list(c, sizeof(int32_t) * (size_t)m);
   Buf nnz_row(c, sizeof(int64_t) * (size_t)m);
   fill_i64(nnz_row.as<int64_t>(), m, 0, s);
+  c->tracef("spgemm: %lld x %lld (nnz %lld) times %lld x %lld (nnz %lld), schedule %d", (long long)m,
+            (long long)Am.n, (long long)Am.nnz, (long long)Bm.m, (long long)n, (long long)Bm.nnz, sched);
   const int64_t products = run_symbolic(L, S, Am, Bm, w.as<int64_t>(), nullptr, m, info1, list.as<int32_t>(),
-                                        nnz_row.as<int64_t>());
+                                        nnz_row.as<int64_t>(), info2 + INFO - 1);
+  c->tracef("spgemm: symbolic launched, %lld products", (long long)products);
   if (st) st->products = products;
   // 4. rowptr, numeric bins (by exact nnz)
   excl_scan_i64(c, nnz_row.as<int64_t>(), out->rowptr.as<int64_t>(), m, s);
@@ -736,21 +775,24 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
   th2.t[1] = std::max(S.t_small, th2.t[0]);
   th2.t[2] = std::max(S.t_mid, th2.t[1]);
   th2.t[3] = std::max(S.t_big, th2.t[2]);
-  bin_count<<<gridn(m, 256, 2048), 256, 0, s>>>(nnz_row.as<int64_t>(), m, th2, info2);
+  bin_count<<<gridn(m, 256, 2048), 256, 0, s>>>(nnz_row.as<int64_t>(), m, th2, info2, Am.rowptr, nullptr);
   SRTC_LAUNCH_CHECK("bin_count");
   bin_offsets<<<1, 64, 0, s>>>(info2);
   bin_scatter<<<gridn(m, 256, 4096), 256, 0, s>>>(nnz_row.as<int64_t>(), m, th2, info2, list.as<int32_t>(), nullptr);
   SRTC_LAUNCH_CHECK("bin_scatter");
   int64_t hinfo2[INFO];
   read_to_host(c, hinfo2, info2, sizeof(hinfo2), s);
+  if (hinfo2[INFO - 1]) fail(SRTC_ERR_DEVICE, "spgemm: symbolic hash table overflow (internal invariant)");
   const int64_t total = hinfo2[4 * NBIN];
+  c->tracef("spgemm: nnz(C) = %lld; numeric bins %lld %lld %lld %lld %lld", (long long)total, (long long)hinfo2[1],
+            (long long)hinfo2[2], (long long)hinfo2[3], (long long)hinfo2[4], (long long)hinfo2[5]);
   if (st) { st->nnz = total; st->dense_rows = hinfo2[5]; }
   // 5. numeric
   Buf col(c, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), out->kind);
   Buf val(c, es * (size_t)std::max<int64_t>(total, 1), out->kind);
   Buf kept(c, sizeof(int64_t) * (size_t)m);
   Buf flag(c, 64);
-  fill_i32(flag.as<int32_t>(), 1, 0, s);
+  fill_i32(flag.as<int32_t>(), 2, 0, s);
   int64_t *ctr2 = info2 + 3 * NBIN;
   const int64_t *rpC = out->rowptr.as<int64_t>();
   int32_t *cC = col.as<int32_t>();
@@ -759,33 +801,46 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
   int64_t *kp = kept.as<int64_t>();
   int32_t *fl = flag.as<int32_t>();
   using NL = NumLaunch<SR>;
-  if (!sorted) {
-    NL::template hash<64, 64, 2>(L, hinfo2[1], lst, info2, 1, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 1);
-    NL::template hash<128, 512, 2>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
-  } else {
-    NL::template hash<64, 64, 0>(L, hinfo2[1], lst, info2, 1, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 1);
-    if (S.small_bitmap)
-      NL::template hash<128, 512, 1>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
-    else
-      NL::template hash<128, 512, 0>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
-  }
-  if (sorted) {
-    NL::template hash<256, 4096, 1>(L, hinfo2[3], lst, info2, 3, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 3);
-    NL::template hash<512, 8192, 1>(L, hinfo2[4], lst, info2, 4, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 4);
-  } else {
-    NL::template hash<256, 4096, 2>(L, hinfo2[3], lst, info2, 3, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 3);
-    NL::template hash<512, 8192, 2>(L, hinfo2[4], lst, info2, 4, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 4);
+  // algorithmic bytes of a numeric bin: its C entries written, its A rows
+  // read, B read once
+  const double vb = (double)sizeof(V);
+  auto num_bytes = [&](int b) {
+    return (4.0 + vb) * hinfo2[SUMV + b] + (4.0 + vb) * hinfo2[SUMA + b] + 24.0 * hinfo2[b] +
+           (4.0 + vb) * Bm.nnz + 8.0 * (Bm.m + 1);
+  };
+  static const char *kNumName[NBIN] = {"", "spgemm.numeric.hash64", "spgemm.numeric.hash512",
+                                       "spgemm.numeric.hash4096", "spgemm.numeric.hash8192",
+                                       "spgemm.numeric.dense"};
+  for (int b = 1; b < NBIN - 1; b++) {
+    if (hinfo2[b] == 0) continue;
+    ProfScope ps(c, kNumName[b], num_bytes(b), s);
+    if (b == 1) {
+      if (sorted) NL::template hash<64, 64, 0>(L, hinfo2[1], lst, info2, 1, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 1);
+      else NL::template hash<64, 64, 2>(L, hinfo2[1], lst, info2, 1, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 1);
+    } else if (b == 2) {
+      if (!sorted) NL::template hash<128, 512, 2>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
+      else if (S.small_bitmap) NL::template hash<128, 512, 1>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
+      else NL::template hash<128, 512, 0>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
+    } else if (b == 3) {
+      if (sorted) NL::template hash<256, 4096, 1>(L, hinfo2[3], lst, info2, 3, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 3);
+      else NL::template hash<256, 4096, 2>(L, hinfo2[3], lst, info2, 3, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 3);
+    } else {
+      if (sorted) NL::template hash<512, 8192, 1>(L, hinfo2[4], lst, info2, 4, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 4);
+      else NL::template hash<512, 8192, 2>(L, hinfo2[4], lst, info2, 4, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 4);
+    }
   }
   if (hinfo2[5] > 0) {
     const int64_t W = dense_width<SR>(S.dense_wide != 0);
     const int nwin = (int)((n + W - 1) / W);
     Buf woff;
     if (nwin > 1) {
+      ProfScope ps(c, "spgemm.window_table", 8.0 * (Bm.m + 1) + 4.0 * Bm.nnz + 4.0 * Bm.m * (nwin + 1), s);
       woff = Buf(c, sizeof(int32_t) * (size_t)(Bm.m * (nwin + 1)));
       build_woff<<<gridn(Bm.m * (nwin + 1)), 256, 0, s>>>(Bm.rowptr, Bm.col, Bm.m, nwin, W, woff.as<int32_t>());
       SRTC_LAUNCH_CHECK("build_woff");
     }
     const int32_t *wo = woff.as<int32_t>();
+    ProfScope ps(c, kNumName[5], num_bytes(5) + (nwin > 1 ? 8.0 * hinfo2[SUMA + 5] * nwin : 0.0), s);
     if (S.dense_wide) {
       if (S.dense_bs == 512) NL::template dense<512, (int)(SR::HAS_VALS ? 16384 * 8 / sizeof(A) : (1 << 20))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
       else NL::template dense<256, (int)(SR::HAS_VALS ? 16384 * 8 / sizeof(A) : (1 << 20))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
@@ -795,8 +850,11 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
     }
   }
   // 6. compaction when identity results were dropped
-  int32_t short_flag = 0;
-  read_to_host(c, &short_flag, fl, sizeof(int32_t), s);
+  int32_t flags_h[2] = {0, 0};
+  read_to_host(c, flags_h, fl, sizeof(flags_h), s);
+  c->tracef("spgemm: numeric done (short %d, error %d)", flags_h[0], flags_h[1]);
+  if (flags_h[1]) fail(SRTC_ERR_DEVICE, "spgemm: numeric hash table overflow (internal invariant)");
+  const int32_t short_flag = flags_h[0];
   if (short_flag) {
     Buf rp2(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
     excl_scan_i64(c, kp, rp2.as<int64_t>(), m, s);
@@ -910,7 +968,7 @@ void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B,
     Buf nnz_row(c, sizeof(int64_t) * (size_t)m);
     fill_i64(nnz_row.as<int64_t>(), m, 0, s);
     run_symbolic(L, schedule(0), A, B, wsel.as<int64_t>(), rows.as<int32_t>(), ns, info.as<int64_t>(),
-                 list.as<int32_t>(), nnz_row.as<int64_t>());
+                 list.as<int32_t>(), nnz_row.as<int64_t>(), info.as<int64_t>() + INFO - 1);
     gather_i64<<<gridn(ns), 256, 0, s>>>(nnz_row.as<int64_t>(), rows.as<int32_t>(), ns, nsel.as<int64_t>());
     std::vector<int64_t> hw(ns), hn(ns);
     read_to_host(c, hw.data(), wsel.p, sizeof(int64_t) * (size_t)ns, s);

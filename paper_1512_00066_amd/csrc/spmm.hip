@@ -278,6 +278,7 @@ __global__ void __launch_bounds__(256) bfs_step_kernel(const int64_t *__restrict
 }  // namespace
 
 void SpmmPlan::build(Ctx *c, const CsrView &A, int64_t s_width, hipStream_t st) {
+  ctx = c;
   int g = 1;
   while (g < s_width && g < WAVE) g <<= 1;
   G = g;
@@ -320,6 +321,12 @@ void spmm_with_plan(const SpmmPlan &pl, int sr, int dt, IdVal id, const CsrView 
                     int64_t s_width, void *Y, int mode, int accumulate, int32_t *changed, const int32_t *row_inst,
                     const uint8_t *inst_active, int32_t *inst_changed, hipStream_t st) {
   SpmmCall q{&pl, &A, X, s_width, Y, id, mode, accumulate, changed, row_inst, inst_active, inst_changed, st};
+  // algorithmic bytes: A once, X once, Y written (and read for the self
+  // term / accumulation)
+  const double es = (double)dtype_size(dt);
+  const double xy = es * (double)s_width * (double)(A.m + A.n);
+  ProfScope ps(pl.ctx, mode == 1 ? "spmm.fixpoint_step" : "spmm.product",
+               (4.0 + es) * A.nnz + 8.0 * (A.m + 1) + xy + (mode == 1 || accumulate ? es * s_width * A.m : 0.0), st);
   SRTC_DISPATCH_SR(sr, dt, spmm_dispatch, q);
 }
 

@@ -7,6 +7,7 @@
 namespace srtc {
 
 struct SpmmPlan {
+  Ctx *ctx = nullptr;
   int G = 64;          // lanes per item (power of two covering the width)
   int64_t T = 256;     // nonzeros per item
   int64_t max_items = 0;
