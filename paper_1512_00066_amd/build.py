@@ -34,6 +34,17 @@ def _compile(src):
     return obj, err
 
 
+def device_asm(src, out):
+    """gfx950 assembly of one source, built with the library's own flags
+    (device code only); returns the path written."""
+    flags = [f for f in FLAGS if f != "-fPIC"]
+    cmd = [HIPCC, *flags, "-x", "hip", "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc -S failed on {src}:\n{r.stderr}")
+    return out
+
+
 def build(jobs=None, verbose=False):
     """Compile every source and link libsrtc.so; always rebuilds."""
     os.makedirs(OBJ, exist_ok=True)

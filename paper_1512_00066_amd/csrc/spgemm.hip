@@ -189,6 +189,14 @@ __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, co
   }
 }
 
+// Rows of a bin are handed out one at a time from a global counter: thread 0
+// takes the next index and the block reads it back through LDS.  Callers
+// fetch the first row before their loop and the next one at the end of the
+// body, so the loop test is on a block-uniform value and no thread-dependent
+// branch leads into the loop header.  (With the fetch at the top of an
+// endless loop, the compiler was free to route threads other than 0 from the
+// end of the body straight past the fetch; the generated code then kept
+// those lanes in an inner loop over the same row that they never left.)
 __device__ __forceinline__ int64_t next_row(int64_t *ctr) {
   __shared__ int64_t r;
   if (threadIdx.x == 0) r = (int64_t)atomicAdd((unsigned long long *)ctr, 1ull);
@@ -217,9 +225,7 @@ __global__ void __launch_bounds__(BS) sym_hash(const int32_t *__restrict__ list,
   __shared__ int64_t red[BS / WAVE + 1];
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
-  for (;;) {
-    const int64_t r = next_row(ctr);
-    if (r >= count) break;
+  for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
     const int64_t i = rows[r];
     for (int s = threadIdx.x; s < TBL; s += BS) keys[s] = EMPTY;
     __syncthreads();
@@ -260,9 +266,7 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
   const int64_t wcols = (int64_t)wwords * 32;
-  for (;;) {
-    const int64_t r = next_row(ctr);
-    if (r >= count) break;
+  for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
     const int64_t i = rows[r];
     int64_t mine = 0;
     for (int64_t w0 = 0; w0 < ncols; w0 += wcols) {
@@ -308,9 +312,7 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
   extern __shared__ uint32_t bits[];
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
-  for (;;) {
-    const int64_t r = next_row(ctr);
-    if (r >= count) break;
+  for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
     const int64_t i = rows[r];
     for (int s = threadIdx.x; s < TBL; s += BS) {
       keys[s] = EMPTY;
@@ -465,9 +467,7 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
   __syncthreads();
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
-  for (;;) {
-    const int64_t r = next_row(ctr);
-    if (r >= count) break;
+  for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
     const int64_t i = rows[r];
     const int64_t base = rpC[i];
     int64_t written = 0;
