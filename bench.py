@@ -146,7 +146,10 @@ def run_rmat18(args):
     log(f"nnz(A)={A64.nnz} products={products} nnz(T)={t_nnz} ops/step={ops_step:.4e}")
 
     sched = {}
-    if args.schedule >= 0:
+    if args.schedules:
+        a, b = (int(x) for x in args.schedules.split(","))
+        sched = {"f64": a, "f32": b}
+    elif args.schedule >= 0:
         sched = {"f64": args.schedule, "f32": args.schedule}
     elif not args.no_autotune:
         A32 = ctx.fold("plus_times", coo32, "ij", "i", "j")
@@ -222,6 +225,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18", choices=["rmat18"])
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
+    ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

@@ -98,7 +98,9 @@ __global__ void __launch_bounds__(256) gemm_mfma(const T *__restrict__ A, const 
       }
     }
   }
-  // output layout of a 16x16 MFMA tile: lane l holds rows 4*(l/16)+q, col l%16
+  // output layout of a 16x16 MFMA tile, lane l, column l%16, accumulator q:
+  //   fp32 (16x16x4 f32): row 4*(l/16) + q
+  //   fp64 (16x16x4 f64): row 4*q + l/16
 #pragma unroll
   for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -108,7 +110,7 @@ __global__ void __launch_bounds__(256) gemm_mfma(const T *__restrict__ A, const 
         double v;
         if constexpr (sizeof(T) == 8) v = accd[a][b][q];
         else v = acc64[a][b][q] + (double)acc32[a][b][q];
-        const int64_t gm = m0 + wm + a * 16 + 4 * (l / 16) + q;
+        const int64_t gm = m0 + wm + a * 16 + (sizeof(T) == 8 ? 4 * q + l / 16 : 4 * (l / 16) + q);
         const int64_t gn = n0 + wn + b * 16 + (l % 16);
         if (gm < M && gn < N) {
           if (accumulate) v += (double)C[gm * N + gn];

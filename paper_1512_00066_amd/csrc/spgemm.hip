@@ -22,6 +22,9 @@
 #include <cmath>
 #include <vector>
 
+#include <string>
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace srtc {
@@ -811,9 +814,13 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
   static const char *kNumName[NBIN] = {"", "spgemm.numeric.hash64", "spgemm.numeric.hash512",
                                        "spgemm.numeric.hash4096", "spgemm.numeric.hash8192",
                                        "spgemm.numeric.dense"};
+  // profile names carry the value type, so each names one kernel instance
+  const char *vt = std::is_same<V, double>::value ? ".f64" : std::is_same<V, float>::value ? ".f32"
+                   : std::is_same<V, int32_t>::value ? ".i32" : ".u8";
+  auto pname = [&](int b) { return std::string(kNumName[b]) + vt; };
   for (int b = 1; b < NBIN - 1; b++) {
     if (hinfo2[b] == 0) continue;
-    ProfScope ps(c, kNumName[b], num_bytes(b), s);
+    ProfScope ps(c, pname(b).c_str(), num_bytes(b), s);
     if (b == 1) {
       if (sorted) NL::template hash<64, 64, 0>(L, hinfo2[1], lst, info2, 1, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 1);
       else NL::template hash<64, 64, 2>(L, hinfo2[1], lst, info2, 1, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 1);
@@ -840,7 +847,7 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
       SRTC_LAUNCH_CHECK("build_woff");
     }
     const int32_t *wo = woff.as<int32_t>();
-    ProfScope ps(c, kNumName[5], num_bytes(5) + (nwin > 1 ? 8.0 * hinfo2[SUMA + 5] * nwin : 0.0), s);
+    ProfScope ps(c, pname(5).c_str(), num_bytes(5) + (nwin > 1 ? 8.0 * hinfo2[SUMA + 5] * nwin : 0.0), s);
     if (S.dense_wide) {
       if (S.dense_bs == 512) NL::template dense<512, (int)(SR::HAS_VALS ? 16384 * 8 / sizeof(A) : (1 << 20))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
       else NL::template dense<256, (int)(SR::HAS_VALS ? 16384 * 8 / sizeof(A) : (1 << 20))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
