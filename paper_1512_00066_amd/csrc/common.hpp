@@ -61,43 +61,76 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-template <class T> __device__ __forceinline__ T wave_incl_scan(T v) {
-#pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    T o = __shfl_up(v, d, WAVE);
-    if (lane_id() >= d) v += o;
+// DPP lane moves (GFX9 data-parallel primitives): lanes whose source is
+// outside the pattern, or whose row is masked off, read 0.  Values of 8 bytes
+// move as two 32-bit halves.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xf, false);
+}
+template <int CTRL, int ROWMASK, class T>
+__device__ __forceinline__ T dpp_move(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "dpp_move on 4- or 8-byte values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp32<CTRL, ROWMASK>(__builtin_bit_cast(uint32_t, v)));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint64_t hi = dpp32<CTRL, ROWMASK>((uint32_t)(u >> 32));
+    const uint64_t lo = dpp32<CTRL, ROWMASK>((uint32_t)u);
+    return __builtin_bit_cast(T, (hi << 32) | lo);
   }
+}
+
+// Inclusive sum over the 64 lanes: shifts of 1, 2, 4, 8 within each row of
+// 16 lanes, then lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31
+// into rows 2 and 3.
+template <class T> __device__ __forceinline__ T wave_incl_scan(T v) {
+  v += dpp_move<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xa>(v);  // row_bcast:15
+  v += dpp_move<0x143, 0xc>(v);  // row_bcast:31
   return v;
 }
 
-template <class T> __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int d = WAVE / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
-  return v;
+template <class T> __device__ __forceinline__ T lane63(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    return __builtin_bit_cast(T, (hi << 32) | lo);
+  }
 }
+
+// Sum over the 64 lanes (every lane gets it); all lanes must be active.
+template <class T> __device__ __forceinline__ T wave_sum(T v) { return lane63(wave_incl_scan(v)); }
 
 // Block-wide exclusive scan for BS threads (BS a multiple of 64, <= 1024).
 // `tmp` is LDS of at least BS/64 + 1 elements.  Returns the exclusive prefix
-// and writes the block total to *total (every thread sees it).
-template <int BS, class T>
+// and writes the block total to *total (every thread sees it).  With
+// SYNC_AFTER false the caller must pass a barrier before tmp is written
+// again (by any later scan on the same tmp).
+template <int BS, class T, bool SYNC_AFTER = true>
 __device__ __forceinline__ T block_excl_scan(T v, T *tmp, T *total) {
   static_assert(BS % WAVE == 0 && BS <= 1024, "block size");
   constexpr int NW = BS / WAVE;
   const int w = threadIdx.x / WAVE;
-  T inc = wave_incl_scan(v);
+  const T inc = wave_incl_scan(v);
   if (lane_id() == WAVE - 1) tmp[w] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    T run = 0;
+  T before = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < NW; i++) { T t = tmp[i]; tmp[i] = run; run += t; }
-    tmp[NW] = run;
+  for (int q = 0; q < NW; q++) {
+    const T x = tmp[q];
+    if (q < w) before += x;
+    tot += x;
   }
-  __syncthreads();
-  T res = tmp[w] + inc - v;
-  *total = tmp[NW];
-  __syncthreads();
-  return res;
+  *total = tot;
+  if (SYNC_AFTER) __syncthreads();
+  return before + inc - v;
 }
 
 // ------------------------------------------------------------- semirings --

@@ -116,14 +116,38 @@ __global__ void bin_offsets(int64_t *info) {
   }
 }
 
+// Rows go to their bin's list; each wave takes one slot range per bin with a
+// single atomic and places its rows by ballot rank.
 __global__ void bin_scatter(const int64_t *v, int64_t m, Thresholds th, int64_t *info, int32_t *lists,
                             const int32_t *row_map) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int b = bin_of(v[i], th);
-    if (b == 0) continue;
-    const int64_t p = atomicAdd((unsigned long long *)&info[2 * NBIN + b], 1ull);
-    lists[info[NBIN + b] + p] = row_map ? row_map[i] : (int32_t)i;
+  const uint64_t lt = lanemask_lt();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < m; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    const int b = i < m ? bin_of(v[i], th) : 0;
+#pragma unroll
+    for (int bb = 1; bb < NBIN; bb++) {
+      const uint64_t mk = __ballot(b == bb);
+      if (mk == 0) continue;
+      const int leader = __ffsll((unsigned long long)mk) - 1;
+      long long p = 0;
+      if (lane_id() == leader)
+        p = (long long)atomicAdd((unsigned long long *)&info[2 * NBIN + bb], (unsigned long long)__popcll(mk));
+      p = __shfl(p, leader, WAVE);
+      if (b == bb) lists[info[NBIN + bb] + p + __popcll(mk & lt)] = row_map ? row_map[i] : (int32_t)i;
+    }
+  }
+}
+
+// Sort key putting heavy rows first: descending in a 16-bit code of the
+// row's product count (exponent and three mantissa bits).
+__global__ void heavy_first_keys(const int32_t *__restrict__ rows, const int64_t *__restrict__ w, int64_t n,
+                                 int64_t *__restrict__ keys) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = (uint64_t)max((int64_t)1, w[rows[q]]);
+    const int e = 63 - __clzll(x);
+    const uint64_t mant = e >= 3 ? (x >> (e - 3)) & 7 : (x << (3 - e)) & 7;
+    keys[q] = 0xFFFF - (int64_t)(e * 8 + mant);
   }
 }
 
@@ -141,11 +165,92 @@ template <int BS, class V> struct Chunk {
   int32_t tmp[BS / WAVE + 1];
 };
 
+// Walking the products laid out by a chunk: L.off holds the exclusive scan of
+// the cnt segment lengths (total products), L.start each segment's first
+// position in B, L.a the A value.  Thread t takes products t, t+BS, ...; a
+// batch is U of them handled together (an interleaved binary search for the
+// owning segments, then all B loads), so a lane keeps U independent memory
+// requests in flight instead of one.  Gathering a batch and consuming it are
+// separate steps, so a caller can issue the loads early and use them later.
+template <int U, class V> struct Batch {
+  int32_t j[U];
+  V a[U], b[U];
+};
+
+template <int BS, int U, bool VALS, class V>
+__device__ __forceinline__ void gather_batch(const int32_t *__restrict__ cB, const V *__restrict__ vB, int cnt,
+                                             int32_t total, const Chunk<BS, V> &L, int32_t q0, Batch<U, V> &g) {
+  const int top = cnt > 1 ? 1 << (31 - __clz(cnt - 1)) : 0;  // largest power of two <= cnt-1
+  int lo[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) lo[u] = 0;
+  // largest lo with off[lo] <= q (off is non-decreasing, off[0] = 0)
+  for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int c = lo[u] + step;
+      if (c < cnt && L.off[c] <= q0 + u * BS) lo[u] = c;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int32_t q = q0 + u * BS;
+    g.j[u] = 0;
+    g.a[u] = V{};
+    g.b[u] = V{};
+    if (q < total) {
+      const int64_t pos = L.start[lo[u]] + (q - L.off[lo[u]]);
+      g.j[u] = cB[pos];
+      if (VALS) {
+        g.a[u] = L.a[lo[u]];
+        g.b[u] = vB[pos];
+      }
+    }
+  }
+}
+
+template <int BS, int U, class V, class F>
+__device__ __forceinline__ void consume_batch(const Batch<U, V> &g, int32_t q0, int32_t total, F &&f) {
+#pragma unroll
+  for (int u = 0; u < U; u++)
+    if (q0 + u * BS < total) f(g.j[u], g.a[u], g.b[u]);
+}
+
+// All products of a laid-out chunk from product index q_start on (the
+// thread's own first product by default).
+template <int BS, int U, bool VALS, class V, class F>
+__device__ __forceinline__ void walk_chunk(const int32_t *__restrict__ cB, const V *__restrict__ vB, int cnt,
+                                           int32_t total, const Chunk<BS, V> &L, F &&f, int32_t q_start = -1) {
+  for (int32_t q0 = q_start < 0 ? (int32_t)threadIdx.x : q_start; q0 < total; q0 += BS * U) {
+    Batch<U, V> g;
+    gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, q0, g);
+    consume_batch<BS, U, V>(g, q0, total, f);
+  }
+}
+
+constexpr int WALK_U = 4;
+
+// Lay out one chunk's segments: thread t < cnt owns a segment of `len`
+// products starting at B position `st` with A value `a`.  Returns the total;
+// L is ready to walk when this returns.
+template <int BS, bool VALS, class V>
+__device__ __forceinline__ int32_t layout_chunk(int32_t len, int64_t st, V a, Chunk<BS, V> &L) {
+  const int t = threadIdx.x;
+  int32_t total;
+  // the barrier below also orders these reads of L.tmp before its next use
+  const int32_t off = block_excl_scan<BS, int32_t, false>(len, L.tmp, &total);
+  L.off[t] = off;
+  L.start[t] = st;
+  if (VALS) L.a[t] = a;
+  __syncthreads();
+  return total;
+}
+
 // Visit every product of row i (optionally restricted to column window w of
 // the window table) as f(j, a_ik, b_kj).  A entries are taken BS at a time;
-// their B segments are laid end to end by a block scan and every thread
-// walks that flattened range with a binary search for its segment, so the
-// work per thread is balanced whatever the segment lengths.
+// their B segments are laid end to end by a block scan and the threads walk
+// that flattened range, so the work per thread is balanced whatever the
+// segment lengths.
 template <int BS, bool VALS, class V, class F>
 __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, const int32_t *__restrict__ cA,
                                              const V *__restrict__ vA, const int64_t *__restrict__ rpB,
@@ -172,22 +277,8 @@ __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, co
       }
       if (VALS) a = vA[p0 + t];
     }
-    int32_t total;
-    const int32_t off = block_excl_scan<BS>(len, L.tmp, &total);
-    L.off[t] = off;
-    L.start[t] = st;
-    if (VALS) L.a[t] = a;
-    __syncthreads();
-    for (int32_t q = t; q < total; q += BS) {
-      int lo = 0, hi = cnt - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L.off[mid] <= q) lo = mid; else hi = mid - 1;
-      }
-      const int64_t pos = L.start[lo] + (q - L.off[lo]);
-      if (VALS) f(cB[pos], L.a[lo], vB[pos]);
-      else f(cB[pos], V{}, V{});
-    }
+    const int32_t total = layout_chunk<BS, VALS, V>(len, st, a, L);
+    walk_chunk<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, f);
     __syncthreads();
   }
 }
@@ -440,10 +531,56 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
   }
 }
 
+// Extraction of one dense window of a value semiring: every slot that does
+// not hold the identity is written out in column order, and all slots are
+// reset.  Wave wv owns the slot range [wv*SPW, (wv+1)*SPW) and walks it 64
+// slots at a time; a ballot gives each kept slot its place.  Returns the
+// number of entries written (the same on every thread).
+template <class SR, int BS, int W>
+__device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, typename SR::acc_t id, int64_t w0,
+                                                  int64_t pos0, int32_t *__restrict__ cC,
+                                                  typename SR::val_t *__restrict__ vC, int64_t *red) {
+  constexpr int NW = BS / WAVE, SPW = W / NW;
+  static_assert(W % (NW * WAVE) == 0, "window split");
+  const int wv = threadIdx.x / WAVE, l = lane_id();
+  int cntw = 0;
+  for (int g = 0; g < SPW; g += WAVE)
+    cntw += __popcll(__ballot(!SR::acc_absent(vals[wv * SPW + g + l], id)));
+  if (l == 0) red[wv] = cntw;
+  __syncthreads();
+  int64_t before = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < NW; q++) {
+    const int64_t x = red[q];
+    if (q < wv) before += x;
+    tot += x;
+  }
+  int64_t pos = pos0 + before;
+  const uint64_t lt = lanemask_lt();
+  for (int g = 0; g < SPW; g += WAVE) {
+    const int s = wv * SPW + g + l;
+    const typename SR::acc_t v = vals[s];
+    const bool keep = !SR::acc_absent(v, id);
+    const uint64_t m = __ballot(keep);
+    if (keep) {
+      const int64_t o = pos + __popcll(m & lt);
+      cC[o] = (int32_t)(w0 + s);
+      vC[o] = SR::out(v);
+    }
+    pos += __popcll(m);
+    vals[s] = id;
+  }
+  __syncthreads();
+  return tot;
+}
+
 // Dense accumulator windows: W consecutive columns per window held in LDS
-// (values + presence bits).  The window table gives, for every row k of B,
-// where each window starts in B_k (B rows have ascending columns), so each
-// product is visited exactly once over all windows.
+// (values for value semirings, presence bits for the boolean one).  The
+// window table gives, for every row k of B, where each window starts in B_k
+// (B rows have ascending columns), so each product is visited exactly once
+// over all windows.  A rows of at most BS entries keep their entries in
+// registers across the windows and fetch the next window's table entry one
+// window ahead; longer A rows are re-read in chunks for every window.
 template <class SR, int BS, int W>
 __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
                                                 int bin, const int64_t *__restrict__ rpA,
@@ -458,78 +595,113 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
                                                 int64_t *ctr) {
   using V = typename SR::val_t;
   using A = typename SR::acc_t;
-  constexpr int NWORD = W / 32;
+  constexpr bool VALS = SR::HAS_VALS;
+  constexpr int NWORD = VALS ? 1 : W / 32;
   constexpr int PER = (NWORD + BS - 1) / BS;
-  constexpr int NV = SR::HAS_VALS ? W : 1;
+  constexpr int NV = VALS ? W : 1;
   __shared__ A vals[NV];
   __shared__ uint32_t bits[NWORD];
   __shared__ Chunk<BS, V> L;
   __shared__ int64_t red[BS / WAVE + 1];
-  for (int s = threadIdx.x; s < NV; s += BS) vals[s] = id;
-  for (int s = threadIdx.x; s < NWORD; s += BS) bits[s] = 0;
+  const int t = threadIdx.x;
+  for (int s = t; s < NV; s += BS) vals[s] = id;
+  for (int s = t; s < NWORD; s += BS) bits[s] = 0;
   __syncthreads();
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
   for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
     const int64_t i = rows[r];
     const int64_t base = rpC[i];
+    const int64_t pa = rpA[i], pe = rpA[i + 1];
     int64_t written = 0;
-    for (int w = 0; w < nwin; w++) {
-      const int64_t w0 = (int64_t)w * W;
-      for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin, w, L,
-                                        [&](int32_t j, V a, V b) {
-        if (SR::HAS_VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
+    // one window: accumulate (already walked), then write out and reset
+    auto finish = [&](int64_t w0) {
+      if constexpr (VALS) {
+        written += extract_window<SR, BS, W>(vals, id, w0, base + written, cC, vC, red);
+      } else {
+        int64_t mine = 0;
+        const int u0 = t * PER;
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+          const int u = u0 + q;
+          if (u < NWORD) mine += __popc(bits[u]);
+        }
+        int64_t tot;
+        int64_t pos = base + written + block_excl_scan<BS>(mine, red, &tot);
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+          const int u = u0 + q;
+          if (u >= NWORD) break;
+          uint32_t wd = bits[u];
+          bits[u] = 0;
+          while (wd) {
+            const int b = __ffs(wd) - 1;
+            wd &= wd - 1;
+            cC[pos] = (int32_t)(w0 + u * 32 + b);
+            vC[pos] = SR::out((A)1);
+            pos++;
+          }
+        }
+        written += tot;
+        __syncthreads();
+      }
+    };
+    auto adder = [&](int64_t w0) {
+      return [&, w0](int32_t j, V a, V b) {
+        if (VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
         const int64_t jl = (int64_t)j - w0;
         if (jl < 0 || jl >= W) return;  // B rows must list columns in ascending order
         const int jj = (int)jl;
-        if (SR::HAS_VALS) SR::lds_add(&vals[jj], SR::mul(a, b));
-        atomicOr(&bits[jj >> 5], 1u << (jj & 31));
-      });
-      // extraction in column order; resets the touched slots
-      int64_t mine = 0;
-      const int u0 = threadIdx.x * PER;
-#pragma unroll
-      for (int q = 0; q < PER; q++) {
-        const int u = u0 + q;
-        if (u >= NWORD) break;
-        uint32_t wd = bits[u];
-        if (SR::HAS_VALS) {
-          uint32_t t2 = wd;
-          while (t2) {
-            const int b = __ffs(t2) - 1;
-            t2 &= t2 - 1;
-            if (SR::acc_absent(vals[u * 32 + b], id)) wd &= ~(1u << b);
-          }
-        }
-        mine += __popc(wd);
-      }
-      int64_t tot;
-      int64_t pos = base + written + block_excl_scan<BS>(mine, red, &tot);
-#pragma unroll
-      for (int q = 0; q < PER; q++) {
-        const int u = u0 + q;
-        if (u >= NWORD) break;
-        uint32_t wd = bits[u];
-        bits[u] = 0;
-        while (wd) {
-          const int b = __ffs(wd) - 1;
-          wd &= wd - 1;
-          const int s = u * 32 + b;
-          A v = (A)1;
-          if (SR::HAS_VALS) {
-            v = vals[s];
-            vals[s] = id;
-            if (SR::acc_absent(v, id)) continue;
-          }
-          cC[pos] = (int32_t)(w0 + s);
-          vC[pos] = SR::out(v);
-          pos++;
+        if constexpr (VALS) SR::lds_add(&vals[jj], SR::mul(a, b));
+        else atomicOr(&bits[jj >> 5], 1u << (jj & 31));
+      };
+    };
+    if (pe - pa <= BS) {
+      // Window pipeline: while window w is written out, the layout of window
+      // w+1 is already done and its first batch of B loads is in flight.
+      const int cnt = (int)(pe - pa);
+      int32_t k = 0, o_cur = 0, o_nxt = 0;
+      int64_t rb = 0;
+      V av{};
+      const int32_t *wk = nullptr;
+      if (t < cnt) {
+        k = cA[pa + t];
+        rb = rpB[k];
+        if (VALS) av = vA[pa + t];
+        if (nwin > 1) {
+          wk = woff + (int64_t)k * (nwin + 1);
+          o_cur = wk[0];
+          o_nxt = wk[1];
+        } else {
+          o_nxt = (int32_t)(rpB[k + 1] - rb);
         }
       }
-      written += tot;
-      __syncthreads();
+      int32_t total = layout_chunk<BS, VALS, V>(o_nxt - o_cur, rb + o_cur, av, L);
+      Batch<WALK_U, V> g;
+      gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, t, g);
+      for (int w = 0; w < nwin; w++) {
+        const int32_t o_after = (wk && w + 2 <= nwin) ? wk[w + 2] : 0;
+        const int64_t w0 = (int64_t)w * W;
+        consume_batch<BS, WALK_U, V>(g, t, total, adder(w0));
+        if (total > BS * WALK_U) walk_chunk<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, adder(w0), t + BS * WALK_U);
+        __syncthreads();  // window w accumulated; L free
+        int32_t total_n = 0;
+        if (w + 1 < nwin) {
+          total_n = layout_chunk<BS, VALS, V>(o_after - o_nxt, rb + o_nxt, av, L);
+          gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total_n, L, t, g);
+        }
+        finish(w0);
+        total = total_n;
+        o_nxt = o_after;
+      }
+    } else {
+      for (int w = 0; w < nwin; w++) {
+        const int64_t w0 = (int64_t)w * W;
+        for_products<BS, VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin, w, L, adder(w0));
+        finish(w0);
+      }
     }
-    if (threadIdx.x == 0) {
+    if (t == 0) {
       row_kept[i] = written;
       if (written != rpC[i + 1] - base) atomicOr(any_short, 1);
     }
@@ -579,6 +751,16 @@ __global__ void compact_rows(const int64_t *rp_old, const int64_t *rp_new, int64
 inline unsigned gridn(int64_t n, int bs = 256, int64_t cap = 65536) {
   int64_t g = (n + bs - 1) / bs;
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// Order the rows of one bin heaviest first (by their product counts), so the
+// longest rows of a persistent launch start early instead of forming its tail.
+void heavy_first(Ctx *c, int32_t *seg, int64_t nb, const int64_t *w, hipStream_t s) {
+  if (nb < 2) return;
+  Buf keys(c, sizeof(int64_t) * (size_t)nb);
+  heavy_first_keys<<<gridn(nb), 256, 0, s>>>(seg, w, nb, keys.as<int64_t>());
+  SRTC_LAUNCH_CHECK("heavy_first_keys");
+  radix_sort_pairs(c, keys.as<int64_t>(), reinterpret_cast<uint32_t *>(seg), nb, 16, s);
 }
 
 // Schedules: symbolic hash ceiling, numeric bin edges, extraction and dense
@@ -657,6 +839,7 @@ int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, cons
   SRTC_LAUNCH_CHECK("bin_scatter");
   int64_t hinfo[INFO];
   read_to_host(c, hinfo, info1, sizeof(hinfo), s);
+  if (!row_map) heavy_first(c, list + hinfo[NBIN + 5], hinfo[5], wsel, s);
   int64_t *ctr1 = info1 + 3 * NBIN;
   // algorithmic bytes of a symbolic bin: its A rows (pointers + columns),
   // B's columns once, one count per row
@@ -718,7 +901,7 @@ template <class SR> struct NumLaunch {
                     int32_t *cC, V *vC, A id, int64_t *kept, int32_t *any_short, int64_t *ctr) {
     if (rows == 0) return;
     constexpr int NV = SR::HAS_VALS ? W : 1;
-    const int stat = NV * (int)sizeof(A) + W / 8 + (int)sizeof(Chunk<BS, V>) + 64;
+    const int stat = NV * (int)sizeof(A) + (SR::HAS_VALS ? 4 : W / 8) + (int)sizeof(Chunk<BS, V>) + 64;
     num_dense<SR, BS, W><<<L.grid(rows, stat, BS), BS, 0, L.s>>>(
         list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, woff,
         nwin, rpC, cC, vC, id, kept, any_short, ctr);
@@ -786,6 +969,7 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
   int64_t hinfo2[INFO];
   read_to_host(c, hinfo2, info2, sizeof(hinfo2), s);
   if (hinfo2[INFO - 1]) fail(SRTC_ERR_DEVICE, "spgemm: symbolic hash table overflow (internal invariant)");
+  heavy_first(c, list.as<int32_t>() + hinfo2[NBIN + 5], hinfo2[5], w.as<int64_t>(), s);
   const int64_t total = hinfo2[4 * NBIN];
   c->tracef("spgemm: nnz(C) = %lld; numeric bins %lld %lld %lld %lld %lld", (long long)total, (long long)hinfo2[1],
             (long long)hinfo2[2], (long long)hinfo2[3], (long long)hinfo2[4], (long long)hinfo2[5]);
@@ -794,6 +978,7 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
   Buf col(c, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), out->kind);
   Buf val(c, es * (size_t)std::max<int64_t>(total, 1), out->kind);
   Buf kept(c, sizeof(int64_t) * (size_t)m);
+  fill_i64(kept.as<int64_t>(), m, 0, s);  // rows in no bin (no outputs) keep 0
   Buf flag(c, 64);
   fill_i32(flag.as<int32_t>(), 2, 0, s);
   int64_t *ctr2 = info2 + 3 * NBIN;

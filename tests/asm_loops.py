@@ -13,7 +13,7 @@ the first counter atomic and the LDS store of its result, and reports every
 
 import re
 
-_ATOM = re.compile(r"global_atomic_add_x2 v\[\d+:\d+\], v\d+, v\[\d+:\d+\], (s\[\d+:\d+\]) sc0")
+_ATOM = re.compile(r"global_atomic_add_x2 v\[\d+:\d+\], v\d+, v\[\d+:\d+\], s\[\d+:\d+\] sc0")
 _DSW = re.compile(r"ds_write_b64 (v\d+), v\[\d+:\d+\](?: offset:(\d+))?")
 _DSR = re.compile(r"ds_read_b64 v\[\d+:\d+\], (v\d+)(?: offset:(\d+))?")
 
@@ -86,10 +86,9 @@ def check(text):
             return c
 
         flat = [(bi, ln) for bi, b in enumerate(bl) for ln in b["lines"] if not ln.strip().startswith(";")]
-        slots, base = set(), None
+        slots = set()
         for k, (_, ln) in enumerate(flat):
-            m0 = _ATOM.search(ln)
-            if not m0:
+            if not _ATOM.search(ln):
                 continue
             for kk in range(k + 1, min(k + 14, len(flat))):
                 m = _DSW.search(flat[kk][1])
@@ -97,16 +96,17 @@ def check(text):
                     c = _vgpr_const(flat, kk, m.group(1))
                     if c is not None:
                         slots.add(c + int(m.group(2) or 0))
-                        base = m0.group(1)
                     break
             break
         if not slots:
             continue
         kernels += 1
+        # the counter may sit in different SGPRs at different fetches; these
+        # kernels have no other returning 64-bit atomic add, so every one
+        # counts as a fetch
         atom_loops = set()
         for bi, ln in flat:
-            m0 = _ATOM.search(ln)
-            if m0 and m0.group(1) == base:
+            if _ATOM.search(ln):
                 atom_loops.update(chain(bl[bi]["loop"]))
         for k, (bi, ln) in enumerate(flat):
             m = _DSR.search(ln)

@@ -158,6 +158,32 @@ def test_spgemm_drops_identity_results(ctx):
         assert rp.tolist() == [0, 0, 1] and col.tolist() == [0] and val.tolist() == [-6.0]
 
 
+def test_spgemm_drops_identities_with_empty_rows(ctx):
+    # Most output rows are empty (in no bin) and many results cancel to 0, so
+    # the compaction after the numeric pass must see 0 outputs for every
+    # empty row, whatever the recycled scratch memory held before.
+    say("identity drops with empty rows")
+    n = 3000
+    rng_rows = np.arange(1, n, 2)
+    rows = np.repeat(rng_rows, 2)
+    cols = np.tile([0, 1], rng_rows.size)
+    vals = np.tile([1.0, 1.0], rng_rows.size)
+    A = gpu_fold(ctx, "plus_times", "f64", rows, cols, vals, n, n)
+    Ah = oracle.fold("plus_times", "f64", rows, cols, vals, n, n)
+    # B: rows 0 and 1 cancel on columns 0..99 and agree on 100..149
+    bc = np.concatenate([np.arange(150), np.arange(150)])
+    br = np.concatenate([np.zeros(150, np.int64), np.ones(150, np.int64)])
+    bv = np.concatenate([np.full(150, 3.0), np.concatenate([np.full(100, -3.0), np.full(50, 2.0)])])
+    B = gpu_fold(ctx, "plus_times", "f64", br, bc, bv, n, n)
+    Bh = oracle.fold("plus_times", "f64", br, bc, bv, n, n)
+    exp = oracle.spgemm("plus_times", "f64", Ah, Bh)
+    assert exp.rowptr[-1] == 50 * rng_rows.size
+    for sch in range(srtc.NUM_SCHEDULES):
+        junk = [torch.full((n * 8,), 0x55, dtype=torch.uint8, device="cuda") for _ in range(8)]
+        del junk
+        check_csr(ctx.contract("plus_times", "ik", A, "kj", B, "ij", schedule=sch), exp, "plus_times", "f64")
+
+
 def test_spgemm_accumulate_path_doubling(ctx):
     # APSP of the 64-vertex instance: (I (+) A)^n by ceil(log2 n) rounds of
     # P (+)= P (x) P, against Floyd-Warshall
