@@ -218,12 +218,203 @@ def run_rmat18(args):
     return out
 
 
+def run_rmat20_sssp(args):
+    """Multi-source SSSP and BFS: R-MAT 20 (edge factor 16, int32 weights in
+    [1,255]), 64 seeded sources; a step = fold + Bellman-Ford fixpoint as a
+    (min,+) SpMM with graph-captured steps + bit-packed BFS."""
+    import torch
+    import oracle
+    import paper_1512_00066_amd as srtc
+    from gen import synth
+
+    ctx = srtc.Context(0)
+    scale, nsrc = 20, 64
+    n = 1 << scale
+    log("generating R-MAT 20 ...")
+    src, dst = synth.rmat_edges(scale, 16, 0.57, 0.19, 0.19, synth.SEED_CFG2)
+    w = synth.edge_values("i32", src.size, synth.SEED_CFG2, lo=1, hi=255)
+    sources = synth.pick_sources(n, src, nsrc, synth.SEED_CFG2)
+    coo = srtc.COO(torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda"), torch.as_tensor(w, device="cuda"),
+                   (n, n))
+    P0 = np.full((n, nsrc), oracle.INT_INF, np.int32)
+    P0[sources, np.arange(nsrc)] = 0
+    P0d = torch.as_tensor(P0, device="cuda")
+    X = torch.empty_like(P0d)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    rec = {}
+
+    def step():
+        A = ctx.fold("min_plus", coo, "ij", "i", "j")
+        X.copy_(P0d)
+        ev[0].record()
+        it = ctx.fixpoint("min_plus", A, X, steps_per_check=4)
+        ev[1].record()
+        lev, depth = ctx.bfs_levels(A, sources)
+        ev[2].record()
+        rec.update(nnz=A.nnz, it=it, depth=depth)
+        return A
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_bf = t_bfs = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        t_bf += ev[0].elapsed_time(ev[1])
+        t_bfs += ev[1].elapsed_time(ev[2])
+    t1 = time.perf_counter()
+    nnz, it, depth = rec["nnz"], rec["it"], rec["depth"]
+    ops_step = it * nnz * nsrc + (depth + 1) * nnz * nsrc
+    ms = (t1 - t0) * 1e3 / args.steps
+    # one fixpoint step reads A (col + val + rowptr), reads P and writes P
+    step_bytes = 8.0 * nnz + 8.0 * (n + 1) + 2.0 * 4 * n * nsrc
+    step_ms = t_bf / args.steps / it
+    achieved = step_bytes / (step_ms / 1e3) / 1e9
+    log(f"nnz(A)={nnz} BF steps={it} BFS depth={depth}; BF {t_bf / args.steps:.2f} ms, BFS {t_bfs / args.steps:.2f} ms, "
+        f"step {ms:.2f} ms")
+    out = {"metric": METRIC, "value": ops_step * args.steps / (t1 - t0), "unit": "semiring-ops/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+           "config": {"workload": "rmat20_64src_bellman_ford_fixpoint+bfs", "rmat_scale": 20, "edge_factor": 16,
+                      "weights": [1, 255], "sources": nsrc, "nnz_A": nnz, "bf_steps": it, "bfs_depth": depth,
+                      "steps_per_graph": 4, "bf_ms": t_bf / args.steps, "bfs_ms": t_bfs / args.steps},
+           "roofline": {"bound": "hbm", "kernel": "spmm.fixpoint_step (graph-captured; fixpoint time / steps)",
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(step_ms, 4), "algorithmic_bytes_per_launch": round(step_bytes)}}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        O = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+        t2 = time.perf_counter()
+        _, it_o, _ = oracle.bellman_ford("min_plus", "i32", O, P0)
+        lev = oracle.bfs_levels(O, sources)
+        t3 = time.perf_counter()
+        ops_o = it_o * O.nnz * nsrc + (int(lev.max()) + 1) * O.nnz * nsrc
+        out["cpu_baseline"] = {"value": ops_o / (t3 - t2), "unit": "semiring-ops/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"the whole workload: Bellman-Ford from all {nsrc} sources "
+                               f"({it_o} steps) + BFS; {t3 - t2:.1f} s"}
+    return out
+
+
+def run_batch512(args):
+    """512 uneven ER instances (n log-uniform in [1e3,1e5], degree uniform in
+    [4,32], int32 weights [1,100]): each gets a (min,+) A.A and an 8-source
+    Bellman-Ford fixpoint.  The step runs all instances batched (one set of
+    persistent launches per phase); the same work as per-instance calls is
+    timed in the same run for comparison."""
+    import torch
+    import oracle
+    import paper_1512_00066_amd as srtc
+    from gen import synth
+
+    ctx = srtc.Context(0)
+    ninst, nsrc = 512, 8
+    ns, ds = synth.er_batch_params(ninst, synth.SEED_CFG3)
+    log("generating 512 ER instances ...")
+    As, X0s, host = [], [], []
+    products = 0
+    for b in range(ninst):
+        n = int(ns[b])
+        src, dst = synth.er_edges(n, float(ds[b]), synth.SEED_CFG3, tag=b)
+        w = synth.edge_values("i32", src.size, synth.SEED_CFG3, tag=b, lo=1, hi=100)
+        coo = srtc.COO(torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda"),
+                       torch.as_tensor(w, device="cuda"), (n, n))
+        A = ctx.fold("min_plus", coo, "ij", "i", "j")
+        rn = torch.diff(A.rowptr)
+        products += int(rn[A.col.long()].sum().item())
+        sources = synth.pick_sources(n, src, nsrc, synth.SEED_CFG3, tag=b)
+        X0 = torch.full((n, nsrc), oracle.INT_INF, dtype=torch.int32, device="cuda")
+        X0[torch.as_tensor(sources, device="cuda"), torch.arange(sources.size, device="cuda")] = 0
+        As.append(A)
+        X0s.append(X0)
+        host.append((src, dst, w, sources))
+    nnz = [A.nnz for A in As]
+    log(f"sum n={int(ns.sum())} sum nnz={sum(nnz)} products={products}")
+
+    def batched():
+        Cs = ctx.batch_contract("min_plus", As, As)
+        Xs = [x.clone() for x in X0s]
+        its = ctx.batch_fixpoint("min_plus", As, Xs, steps_per_check=4)
+        del Cs, Xs
+        return its
+
+    def single():
+        its = []
+        for A, x0 in zip(As, X0s):
+            C = ctx.contract("min_plus", "ik", A, "kj", A, "ij")
+            X = x0.clone()
+            its.append(ctx.fixpoint("min_plus", A, X, steps_per_check=4))
+            del C, X
+        return its
+
+    def timed(fn, k, profile=False):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        if profile:
+            srtc.lib().srtc_profile_enable(ctx._h, 1)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            its = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k, its
+
+    t_b, its_b = timed(batched, args.steps, profile=True)
+    prof = profile_table(ctx)
+    srtc.lib().srtc_profile_enable(ctx._h, 0)
+    t_s, its_s = timed(single, max(1, args.steps // 2))
+    assert list(its_b) == list(its_s), "batched and per-instance fixpoints took different step counts"
+    ops_step = products + sum(it * z * nsrc for it, z in zip(its_b, nnz))
+    log(f"batched {t_b * 1e3:.2f} ms, per-instance {t_s * 1e3:.2f} ms, speedup {t_s / t_b:.2f}x")
+    log("kernel profile (batched steps):")
+    for nm, cnt, tms, by in sorted(prof, key=lambda r: -r[2])[:12]:
+        log(f"  {nm:32s} {cnt:5d} {tms:10.3f} {by / max(tms, 1e-9) / 1e6:10.1f}")
+    nm, cnt, tms, by = max(prof, key=lambda r: r[2])
+    achieved = (by / cnt) / (tms / cnt / 1e3) / 1e9
+    out = {"metric": METRIC, "value": ops_step / t_b, "unit": "semiring-ops/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t_b * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+           "config": {"workload": "batch512_er_minplus_AxA+8src_bellman_ford", "instances": ninst,
+                      "sum_n": int(ns.sum()), "sum_nnz": int(sum(nnz)), "products": products,
+                      "bf_steps_max": int(max(its_b)), "per_instance_ms_per_step": t_s * 1e3,
+                      "batched_speedup": t_s / t_b, "per_instance_value": ops_step / t_s},
+           "roofline": {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(tms / cnt, 4), "algorithmic_bytes_per_launch": round(by / cnt)}}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        ops_o, t_o, k = 0.0, 0.0, 0
+        for b in range(ninst):
+            src, dst, w, sources = host[b]
+            n = int(ns[b])
+            t2 = time.perf_counter()
+            O = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+            t3 = time.perf_counter()
+            C = oracle.spgemm("min_plus", "i32", O, O)
+            P0 = np.full((n, nsrc), oracle.INT_INF, np.int32)
+            P0[sources, np.arange(sources.size)] = 0
+            _, it_o, _ = oracle.bellman_ford("min_plus", "i32", O, P0)
+            t4 = time.perf_counter()
+            rn = np.diff(O.rowptr)
+            ops_o += float(rn[O.col].sum()) + it_o * O.nnz * nsrc
+            t_o += t4 - t3
+            k += 1
+            if t_o > args.cpu_seconds:
+                break
+        out["cpu_baseline"] = {"value": ops_o / t_o, "unit": "semiring-ops/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"the first {k} of {ninst} instances (A.A + "
+                               f"{nsrc}-source Bellman-Ford each); {t_o:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat18", choices=["rmat18"])
+    ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512"])
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
     ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -234,7 +425,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
-    out = run_rmat18(args)
+    out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

@@ -81,16 +81,6 @@ __global__ void split_rowptr(const int64_t *rpC, const int64_t *rowoff, int nins
   }
 }
 
-__global__ void localize_cols(const int64_t *rpC, const int32_t *row_inst, const int64_t *coloff, int64_t total_rows,
-                              int32_t *col) {
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
-  for (int64_t r = wid; r < total_rows; r += nw) {
-    const int32_t off = (int32_t)coloff[row_inst[r]];
-    for (int64_t p = rpC[r] + lane_id(); p < rpC[r + 1]; p += WAVE) col[p] -= off;
-  }
-}
-
 __global__ void gather_instance_starts(const int64_t *rpC, const int64_t *rowoff, int ninst, int64_t *out) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b <= ninst) out[b] = rpC[rowoff[b]];
@@ -217,16 +207,18 @@ srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add
     Ctx *c = &ctx->c;
     hipStream_t s = (hipStream_t)stream;
     ctx->c.stream = s;
-    // A's columns follow B's row blocks; B's columns follow C's column blocks
-    std::vector<int64_t> a_shift(ninst), b_shift(ninst);
+    // A's columns follow B's row blocks; B keeps each instance's own columns
+    // (a row of A only reaches B rows of its instance), so C comes out with
+    // instance-local columns and every column-width cost of the SpGEMM
+    // (bitmaps, dense windows) is that of the widest instance, not of the sum
+    std::vector<int64_t> a_shift(ninst), b_shift(ninst, 0);
     int64_t kk = 0, nn = 0;
     for (int b = 0; b < ninst; b++) {
       a_shift[b] = kk;
-      b_shift[b] = nn;
       kk += As[b].dims[1];
-      nn += Bs[b].dims[1];
+      nn = std::max<int64_t>(nn, Bs[b].dims[1]);
     }
-    if (nn >= 0x7fffffff || kk >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "batch: more than 2^31-2 columns in total");
+    if (kk >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "batch: more than 2^31-2 inner rows in total");
     BlockDiag A, B;
     build_block_diag(c, As, ninst, a_shift, kk, &A, s);
     build_block_diag(c, Bs, ninst, b_shift, nn, &B, s);
@@ -239,11 +231,6 @@ srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add
     split_rowptr<<<gridn(A.rows + ninst), 256, 0, s>>>(C.rowptr.as<int64_t>(), A.rowoff_d.as<int64_t>(), ninst, A.rows,
                                                       rp_all.as<int64_t>());
     SRTC_LAUNCH_CHECK("split_rowptr");
-    if (C.nnz > 0) {
-      localize_cols<<<gridn(A.rows * WAVE, 256, 16384), 256, 0, s>>>(C.rowptr.as<int64_t>(), A.row_inst.as<int32_t>(),
-                                                                      B.coloff_d.as<int64_t>(), A.rows, C.col.as<int32_t>());
-      SRTC_LAUNCH_CHECK("localize_cols");
-    }
     Buf starts(c, sizeof(int64_t) * (size_t)(ninst + 1));
     gather_instance_starts<<<gridn(ninst + 1), 256, 0, s>>>(C.rowptr.as<int64_t>(), A.rowoff_d.as<int64_t>(), ninst,
                                                            starts.as<int64_t>());

@@ -125,7 +125,7 @@ struct Schedule {
   // (512-slot hash), <= t_mid (4096-slot hash), <= t_big (8192-slot hash),
   // above: dense LDS windows
   int64_t t_tiny, t_small, t_mid, t_big;
-  int small_bitmap;  // 512-slot bin extracts through a bitmap (1) or a sort (0)
+  int small_wave;    // 512-slot bin: one 64-thread wave per row (1) or two waves (0)
   int dense_bs;      // dense-window block size (256 or 512)
   int dense_wide;    // dense window of 16K (1) or 8K (0) 8-byte accumulators
 };

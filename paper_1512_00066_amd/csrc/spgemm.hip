@@ -10,10 +10,10 @@
 //   3. symbolic       nnz_i per row: LDS hash of column keys (light rows) or
 //                     an LDS bitmap over the columns (heavy rows)
 //   4. scan           rowptr of C; the single host sync sizes C
-//   5. numeric        per bin: LDS hash + in-LDS bitonic sort (tiny rows),
-//                     LDS hash + bitmap-ranked extraction (medium rows), or
-//                     dense LDS accumulator windows over the columns (heavy
-//                     rows, whose outputs are a sizeable fraction of n)
+//   5. numeric        per bin: LDS hash, then the kept entries compacted and
+//                     bitonic-sorted in LDS (up to 4096 outputs), or dense
+//                     LDS accumulator windows over the columns (heavy rows,
+//                     whose outputs are a sizeable fraction of n)
 //   6. compaction     only if some result equalled the additive identity
 //                     (dropped), the rows are packed again.
 // Every per-bin kernel is persistent: a grid sized to the machine pulls rows
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
 // Output bookkeeping: row_kept[i] = entries written; any_short is raised if
 // some result equalled the identity and was dropped.
 
-// EXTRACT: 0 = bitonic sort of the table, 1 = bitmap-ranked (sorted), 2 = table order
+// EXTRACT: 0 = sorted (kept entries compacted, then bitonic-sorted by column), 2 = table order
 template <class SR, int BS, int TBL, int EXTRACT>
 __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
                                                int bin, const int64_t *__restrict__ rpA,
@@ -403,7 +403,6 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
   __shared__ A vals[NV];
   __shared__ Chunk<BS, V> L;
   __shared__ int64_t red[BS / WAVE + 1];
-  extern __shared__ uint32_t bits[];
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
   for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
@@ -433,27 +432,8 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
     __syncthreads();
     const int64_t base = rpC[i];
     int64_t written = 0;
-    if (EXTRACT == 0 || EXTRACT == 2) {
-      if (EXTRACT == 0) {
-        // bitonic sort of (key, value) over the whole table; EMPTY sorts last
-        for (int k = 2; k <= TBL; k <<= 1) {
-          for (int jst = k >> 1; jst > 0; jst >>= 1) {
-            for (int q = threadIdx.x; q < TBL / 2; q += BS) {
-              const int lo = (q / jst) * 2 * jst + (q % jst);
-              const int hi = lo + jst;
-              const bool up = (lo & k) == 0;
-              const int32_t ka = keys[lo], kb = keys[hi];
-              if ((ka > kb) == up) {
-                keys[lo] = kb;
-                keys[hi] = ka;
-                if (SR::HAS_VALS) { const A t = vals[lo]; vals[lo] = vals[hi]; vals[hi] = t; }
-              }
-            }
-            __syncthreads();
-          }
-        }
-      }
-      // compact in table order
+    if (EXTRACT == 2) {
+      // compact in table order (unsorted output)
       for (int c0 = 0; c0 < TBL; c0 += BS) {
         const int s = c0 + threadIdx.x;
         const int32_t kk = keys[s];
@@ -468,60 +448,59 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
         written += tot;
       }
     } else {
-      // bitmap ranks: walk the columns in order through a bitmap window
-      const int64_t wcols = (int64_t)wwords * 32;
-      const int per = (wwords + BS - 1) / BS;  // words per thread (contiguous)
-      for (int64_t w0 = 0; w0 < ncols; w0 += wcols) {
-        for (int s = threadIdx.x; s < wwords; s += BS) bits[s] = 0;
-        __syncthreads();
-        for (int s = threadIdx.x; s < TBL; s += BS) {
-          const int32_t kk = keys[s];
-          if (kk != EMPTY) {
-            const int64_t jj = (int64_t)kk - w0;
-            if (jj >= 0 && jj < wcols) atomicOr(&bits[jj >> 5], 1u << (jj & 31));
-          }
-        }
-        __syncthreads();
-        // pass 1: kept entries per thread
-        int64_t mine = 0;
-        const int u0 = threadIdx.x * per;
-        for (int u = u0; u < u0 + per && u < wwords; u++) {
-          uint32_t wd = bits[u];
-          while (wd) {
-            const int b = __ffs(wd) - 1;
-            wd &= wd - 1;
-            const int32_t j = (int32_t)(w0 + u * 32 + b);
-            if (SR::HAS_VALS) {
-              uint32_t h = hash_slot(j, LG);
-              for (int probes = 0; keys[h] != j && probes < TBL; probes++) h = (h + 1) & (TBL - 1);
-              if (SR::acc_absent(vals[h], id)) continue;
-            }
-            mine++;
-          }
-        }
-        int64_t tot;
-        int64_t pos = base + written + block_excl_scan<BS>(mine, red, &tot);
-        for (int u = u0; u < u0 + per && u < wwords; u++) {
-          uint32_t wd = bits[u];
-          while (wd) {
-            const int b = __ffs(wd) - 1;
-            wd &= wd - 1;
-            const int32_t j = (int32_t)(w0 + u * 32 + b);
-            A v = (A)1;
-            if (SR::HAS_VALS) {
-              uint32_t h = hash_slot(j, LG);
-              for (int probes = 0; keys[h] != j && probes < TBL; probes++) h = (h + 1) & (TBL - 1);
-              v = vals[h];
-              if (SR::acc_absent(v, id)) continue;
-            }
-            cC[pos] = j;
-            vC[pos] = SR::out(v);
-            pos++;
-          }
-        }
-        written += tot;
-        __syncthreads();
+      // sorted output: gather the kept entries (results equal to the
+      // identity are dropped) to the front of the table, bitonic-sort the
+      // next power of two of them by column, write them out in order
+      constexpr int PER = TBL / BS;
+      int32_t kk[PER];
+      A vv[PER];
+      int32_t mine = 0;
+#pragma unroll
+      for (int q = 0; q < PER; q++) {
+        const int s = q * BS + threadIdx.x;
+        kk[q] = keys[s];
+        vv[q] = SR::HAS_VALS ? vals[s] : (A)1;
+        if (kk[q] != EMPTY && SR::acc_absent(vv[q], id)) kk[q] = EMPTY;
+        mine += kk[q] != EMPTY ? 1 : 0;
       }
+      int32_t cnt;
+      int32_t pos = block_excl_scan<BS, int32_t>(mine, L.tmp, &cnt);  // ends with a barrier: table reads done
+#pragma unroll
+      for (int q = 0; q < PER; q++) {
+        if (kk[q] != EMPTY) {
+          keys[pos] = kk[q];
+          if (SR::HAS_VALS) vals[pos] = vv[q];
+          pos++;
+        }
+      }
+      const int P = cnt <= 1 ? 1 : 1 << (32 - __clz(cnt - 1));  // next power of two >= cnt
+      for (int s = cnt + threadIdx.x; s < P; s += BS) keys[s] = EMPTY;
+      __syncthreads();
+      for (int k = 2; k <= P; k <<= 1) {
+        for (int jst = k >> 1; jst > 0; jst >>= 1) {
+          for (int q = threadIdx.x; q < P / 2; q += BS) {
+            const int lo = q + (q & ~(jst - 1));  // jst is a power of two
+            const int hi = lo + jst;
+            const bool up = (lo & k) == 0;
+            const int32_t ka = keys[lo], kb = keys[hi];
+            if ((ka > kb) == up) {
+              keys[lo] = kb;
+              keys[hi] = ka;
+              if (SR::HAS_VALS) {
+                const A t = vals[lo];
+                vals[lo] = vals[hi];
+                vals[hi] = t;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (int s = threadIdx.x; s < cnt; s += BS) {
+        cC[base + s] = keys[s];
+        vC[base + s] = SR::out(SR::HAS_VALS ? vals[s] : (A)1);
+      }
+      written = cnt;
     }
     if (threadIdx.x == 0) {
       row_kept[i] = written;
@@ -531,22 +510,44 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
   }
 }
 
-// Extraction of one dense window of a value semiring: every slot that does
-// not hold the identity is written out in column order, and all slots are
-// reset.  Wave wv owns the slot range [wv*SPW, (wv+1)*SPW) and walks it 64
-// slots at a time; a ballot gives each kept slot its place.  Returns the
-// number of entries written (the same on every thread).
+// Extraction of one dense window: `bits` marks the touched columns (for the
+// boolean semiring they are the values), `vals` holds the accumulators of a
+// value semiring.  Every touched slot that does not hold the identity is
+// written out in column order; touched slots and their bits are reset.  Wave
+// wv owns words [wv*WPW, (wv+1)*WPW), a lane one word at a time, and walks
+// its set bits; ranks come from wave scans of the per-word counts and one
+// block-level prefix over the waves.  Returns the number of entries written
+// (the same on every thread).
 template <class SR, int BS, int W>
-__device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, typename SR::acc_t id, int64_t w0,
-                                                  int64_t pos0, int32_t *__restrict__ cC,
+__device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint32_t *bits, typename SR::acc_t id,
+                                                  int64_t w0, int64_t pos0, int32_t *__restrict__ cC,
                                                   typename SR::val_t *__restrict__ vC, int64_t *red) {
-  constexpr int NW = BS / WAVE, SPW = W / NW;
-  static_assert(W % (NW * WAVE) == 0, "window split");
+  using A = typename SR::acc_t;
+  constexpr bool VALS = SR::HAS_VALS;
+  constexpr int NW = BS / WAVE, NWORD = W / 32, WPW = NWORD / NW, NG = (WPW + WAVE - 1) / WAVE;
+  static_assert(NWORD % NW == 0, "window split");
   const int wv = threadIdx.x / WAVE, l = lane_id();
-  int cntw = 0;
-  for (int g = 0; g < SPW; g += WAVE)
-    cntw += __popcll(__ballot(!SR::acc_absent(vals[wv * SPW + g + l], id)));
-  if (l == 0) red[wv] = cntw;
+  // kept entries per word (value semirings re-read the accumulators; for
+  // the boolean one the count is the word's popcount, recomputed below)
+  int32_t cnt[VALS ? NG : 1];
+  int64_t wtot = 0;
+#pragma unroll 2
+  for (int g = 0; g < NG; g++) {
+    const int uw = g * WAVE + l;
+    const int u = wv * WPW + uw;
+    uint32_t wd = uw < WPW ? bits[u] : 0u;
+    if (VALS) {
+      uint32_t t2 = wd;
+      while (t2) {
+        const int b = __ffs(t2) - 1;
+        t2 &= t2 - 1;
+        if (SR::acc_absent(vals[u * 32 + b], id)) wd &= ~(1u << b);
+      }
+      cnt[g] = __popc(wd);
+    }
+    wtot += wave_sum((int32_t)__popc(wd));
+  }
+  if (l == 0) red[wv] = wtot;
   __syncthreads();
   int64_t before = 0, tot = 0;
 #pragma unroll
@@ -556,19 +557,34 @@ __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, type
     tot += x;
   }
   int64_t pos = pos0 + before;
-  const uint64_t lt = lanemask_lt();
-  for (int g = 0; g < SPW; g += WAVE) {
-    const int s = wv * SPW + g + l;
-    const typename SR::acc_t v = vals[s];
-    const bool keep = !SR::acc_absent(v, id);
-    const uint64_t m = __ballot(keep);
-    if (keep) {
-      const int64_t o = pos + __popcll(m & lt);
-      cC[o] = (int32_t)(w0 + s);
-      vC[o] = SR::out(v);
+#pragma unroll 2
+  for (int g = 0; g < NG; g++) {
+    const int uw = g * WAVE + l;
+    const int u = wv * WPW + uw;
+    int32_t c;
+    if constexpr (VALS) c = cnt[g];
+    else c = uw < WPW ? __popc(bits[u]) : 0;
+    const int32_t inc = wave_incl_scan(c);
+    int64_t p = pos + (inc - c);
+    if (uw < WPW) {
+      uint32_t wd = bits[u];
+      bits[u] = 0;
+      while (wd) {
+        const int b = __ffs(wd) - 1;
+        wd &= wd - 1;
+        const int s = u * 32 + b;
+        A v = (A)1;
+        if (VALS) {
+          v = vals[s];
+          vals[s] = id;
+          if (SR::acc_absent(v, id)) continue;
+        }
+        cC[p] = (int32_t)(w0 + s);
+        vC[p] = SR::out(v);
+        p++;
+      }
     }
-    pos += __popcll(m);
-    vals[s] = id;
+    pos += lane63(inc);
   }
   __syncthreads();
   return tot;
@@ -596,8 +612,7 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
   using V = typename SR::val_t;
   using A = typename SR::acc_t;
   constexpr bool VALS = SR::HAS_VALS;
-  constexpr int NWORD = VALS ? 1 : W / 32;
-  constexpr int PER = (NWORD + BS - 1) / BS;
+  constexpr int NWORD = W / 32;
   constexpr int NV = VALS ? W : 1;
   __shared__ A vals[NV];
   __shared__ uint32_t bits[NWORD];
@@ -614,37 +629,9 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
     const int64_t base = rpC[i];
     const int64_t pa = rpA[i], pe = rpA[i + 1];
     int64_t written = 0;
-    // one window: accumulate (already walked), then write out and reset
+    // one window: accumulated (already walked); write out and reset
     auto finish = [&](int64_t w0) {
-      if constexpr (VALS) {
-        written += extract_window<SR, BS, W>(vals, id, w0, base + written, cC, vC, red);
-      } else {
-        int64_t mine = 0;
-        const int u0 = t * PER;
-#pragma unroll
-        for (int q = 0; q < PER; q++) {
-          const int u = u0 + q;
-          if (u < NWORD) mine += __popc(bits[u]);
-        }
-        int64_t tot;
-        int64_t pos = base + written + block_excl_scan<BS>(mine, red, &tot);
-#pragma unroll
-        for (int q = 0; q < PER; q++) {
-          const int u = u0 + q;
-          if (u >= NWORD) break;
-          uint32_t wd = bits[u];
-          bits[u] = 0;
-          while (wd) {
-            const int b = __ffs(wd) - 1;
-            wd &= wd - 1;
-            cC[pos] = (int32_t)(w0 + u * 32 + b);
-            vC[pos] = SR::out((A)1);
-            pos++;
-          }
-        }
-        written += tot;
-        __syncthreads();
-      }
+      written += extract_window<SR, BS, W>(vals, bits, id, w0, base + written, cC, vC, red);
     };
     auto adder = [&](int64_t w0) {
       return [&, w0](int32_t j, V a, V b) {
@@ -653,7 +640,7 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
         if (jl < 0 || jl >= W) return;  // B rows must list columns in ascending order
         const int jj = (int)jl;
         if constexpr (VALS) SR::lds_add(&vals[jj], SR::mul(a, b));
-        else atomicOr(&bits[jj >> 5], 1u << (jj & 31));
+        atomicOr(&bits[jj >> 5], 1u << (jj & 31));
       };
     };
     if (pe - pa <= BS) {
@@ -766,9 +753,9 @@ void heavy_first(Ctx *c, int32_t *seg, int64_t nb, const int64_t *w, hipStream_t
 // Schedules: symbolic hash ceiling, numeric bin edges, extraction and dense
 // window shape.  Index = schedule id.
 const Schedule kSchedules[SRTC_NUM_SCHEDULES] = {
-    // sym_hash_max, t_tiny, t_small, t_mid, t_big, small_bitmap, dense_bs, dense_wide
+    // sym_hash_max, t_tiny, t_small, t_mid, t_big, small_wave, dense_bs, dense_wide
     {2048, 32, 256, 2048, 4096, 0, 256, 0},   // 0 balanced
-    {2048, 32, 256, 2048, 4096, 1, 256, 0},   // 1 small bin ranked by bitmap
+    {2048, 32, 256, 2048, 4096, 1, 256, 0},   // 1 as 0 with one wave per row in the 512-slot bin
     {2048, 32, 256, 256, 256, 1, 256, 0},     // 2 dense windows from 257 outputs
     {8192, 32, 256, 2048, 4096, 0, 512, 1},   // 3 hash-heavy, wide dense windows
     {0, 0, 0, 0, 0, 0, 256, 0},               // 4 dense windows for every row
@@ -882,16 +869,8 @@ template <class SR> struct NumLaunch {
     if (rows == 0) return;
     constexpr int NV = SR::HAS_VALS ? TBL : 1;
     const int stat = TBL * 4 + NV * (int)sizeof(A) + (int)sizeof(Chunk<BS, V>) + 64;
-    int32_t ww = 0;
-    size_t dyn = 0;
-    if (EX == 1) {
-      ww = bitmap_words(Bm.n, BS, LDS_BYTES - stat - 1024);
-      dyn = (size_t)ww * 4;
-    }
-    auto kern = num_hash<SR, BS, TBL, EX>;
-    if (dyn > 64 * 1024) SRTC_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-    kern<<<L.grid(rows, stat + (int)dyn, BS), BS, dyn, L.s>>>(
-        list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, ww,
+    num_hash<SR, BS, TBL, EX><<<L.grid(rows, stat, BS), BS, 0, L.s>>>(
+        list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, 0,
         rpC, cC, vC, id, kept, any_short, ctr);
     SRTC_LAUNCH_CHECK("num_hash");
   }
@@ -901,7 +880,7 @@ template <class SR> struct NumLaunch {
                     int32_t *cC, V *vC, A id, int64_t *kept, int32_t *any_short, int64_t *ctr) {
     if (rows == 0) return;
     constexpr int NV = SR::HAS_VALS ? W : 1;
-    const int stat = NV * (int)sizeof(A) + (SR::HAS_VALS ? 4 : W / 8) + (int)sizeof(Chunk<BS, V>) + 64;
+    const int stat = NV * (int)sizeof(A) + W / 8 + (int)sizeof(Chunk<BS, V>) + 64;
     num_dense<SR, BS, W><<<L.grid(rows, stat, BS), BS, 0, L.s>>>(
         list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, woff,
         nwin, rpC, cC, vC, id, kept, any_short, ctr);
@@ -1011,13 +990,13 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
       else NL::template hash<64, 64, 2>(L, hinfo2[1], lst, info2, 1, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 1);
     } else if (b == 2) {
       if (!sorted) NL::template hash<128, 512, 2>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
-      else if (S.small_bitmap) NL::template hash<128, 512, 1>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
+      else if (S.small_wave) NL::template hash<64, 512, 0>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
       else NL::template hash<128, 512, 0>(L, hinfo2[2], lst, info2, 2, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 2);
     } else if (b == 3) {
-      if (sorted) NL::template hash<256, 4096, 1>(L, hinfo2[3], lst, info2, 3, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 3);
+      if (sorted) NL::template hash<256, 4096, 0>(L, hinfo2[3], lst, info2, 3, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 3);
       else NL::template hash<256, 4096, 2>(L, hinfo2[3], lst, info2, 3, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 3);
     } else {
-      if (sorted) NL::template hash<512, 8192, 1>(L, hinfo2[4], lst, info2, 4, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 4);
+      if (sorted) NL::template hash<512, 8192, 0>(L, hinfo2[4], lst, info2, 4, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 4);
       else NL::template hash<512, 8192, 2>(L, hinfo2[4], lst, info2, 4, Am, Bm, rpC, cC, vC, id, kp, fl, ctr2 + 4);
     }
   }

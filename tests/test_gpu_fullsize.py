@@ -1,9 +1,12 @@
-"""Full-size parity of the benchmarked workload (GPU only).
+"""Full-size parity of the measured workloads (GPU only).
 
-R-MAT scale 18, edge factor 16, A.A over (+,x) in fp64 and fp32, in every
-SpGEMM schedule, compared on sampled rows (the heaviest rows and a seeded
-random sample) with the oracle computing just those rows; plus the order-3
-tensor contraction of the same workload in full."""
+* R-MAT scale 18, edge factor 16, A.A over (+,x) in fp64 and fp32, in every
+  SpGEMM schedule, compared on sampled rows (the heaviest rows and a seeded
+  random sample) with the oracle computing just those rows; the order-3
+  tensor contraction of the same workload in full.
+* R-MAT scale 20: 64-source Bellman-Ford fixpoint and BFS in full.
+* 512 uneven ER instances, batched against per-instance and the oracle.
+"""
 
 import numpy as np
 import pytest
@@ -60,3 +63,82 @@ def test_tensor512_contraction_full():
     exp, _ = oracle.spmm("plus_times", "f32", F, M)
     got = C.cpu().numpy().reshape(-1, 64).astype(np.float64)
     assert np.all(np.abs(got - exp) <= 1e-5 * np.abs(exp))
+
+
+def test_rmat20_multi_source_sssp_and_bfs():
+    # R-MAT 20, edge factor 16, int32 weights [1,255], 64 sources: the
+    # Bellman-Ford fixpoint as a (min,+) SpMM with graph-captured steps and
+    # the bit-packed BFS.  All 64 distance columns and the step count are
+    # checked against the oracle's Bellman-Ford, a seeded sample of 4 sources
+    # also against Dijkstra; BFS levels of all 64 sources against the
+    # oracle's queue BFS.
+    scale = 20
+    n = 1 << scale
+    src, dst = synth.rmat_edges(scale, 16, 0.57, 0.19, 0.19, synth.SEED_CFG2)
+    w = synth.edge_values("i32", src.size, synth.SEED_CFG2, lo=1, hi=255)
+    ctx = srtc.Context(0)
+    keys = torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda")
+    G = ctx.fold("min_plus", srtc.COO(keys, torch.as_tensor(w, device="cuda"), (n, n)), "ij", "i", "j")
+    O = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+    sources = synth.pick_sources(n, src, 64, synth.SEED_CFG2)
+    P0 = np.full((n, 64), oracle.INT_INF, np.int32)
+    P0[sources, np.arange(64)] = 0
+    X = torch.as_tensor(P0, device="cuda")
+    say("rmat20 BF fixpoint")
+    it = ctx.fixpoint("min_plus", G, X, steps_per_check=4)
+    got = X.cpu().numpy()
+    Pexp, it_exp, conv = oracle.bellman_ford("min_plus", "i32", O, P0)
+    assert conv and it == it_exp
+    assert np.array_equal(got, Pexp)
+    pick = np.sort(synth.permutation(synth.stream_key(synth.SEED_CFG2, 5), 64)[:4])
+    assert np.array_equal(Pexp[:, pick].astype(np.int64), oracle.dijkstra(O, sources[pick]))
+    say("rmat20 BFS")
+    lev, depth = ctx.bfs_levels(G, sources)
+    exp = oracle.bfs_levels(O, sources)
+    assert np.array_equal(lev.cpu().numpy(), exp) and depth == exp.max()
+
+
+def test_batch512_matches_per_instance_and_oracle():
+    # 512 ER instances, n log-uniform in [1e3,1e5], degree uniform in
+    # [4,32], int32 weights [1,100]: (min,+) A.A and an 8-source
+    # Bellman-Ford each.  Batched results equal per-instance results bit
+    # for bit on every instance; six sampled instances (the largest among
+    # them) are checked against the oracle.
+    ninst, nsrc = 512, 8
+    ns, ds = synth.er_batch_params(ninst, synth.SEED_CFG3)
+    ctx = srtc.Context(0)
+    As, X0s, host = [], [], []
+    for b in range(ninst):
+        n = int(ns[b])
+        src, dst = synth.er_edges(n, float(ds[b]), synth.SEED_CFG3, tag=b)
+        w = synth.edge_values("i32", src.size, synth.SEED_CFG3, tag=b, lo=1, hi=100)
+        keys = torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda")
+        As.append(ctx.fold("min_plus", srtc.COO(keys, torch.as_tensor(w, device="cuda"), (n, n)), "ij", "i", "j"))
+        sources = synth.pick_sources(n, src, nsrc, synth.SEED_CFG3, tag=b)
+        P0 = np.full((n, nsrc), oracle.INT_INF, np.int32)
+        P0[sources, np.arange(sources.size)] = 0
+        X0s.append(P0)
+        host.append((src, dst, w))
+    say("batch512 batched")
+    Cs = ctx.batch_contract("min_plus", As, As)
+    Xs = [torch.as_tensor(p, device="cuda") for p in X0s]
+    its = ctx.batch_fixpoint("min_plus", As, Xs, steps_per_check=4)
+    say("batch512 per instance")
+    for b in range(ninst):
+        C = ctx.contract("min_plus", "ik", As[b], "kj", As[b], "ij")
+        assert C.nnz == Cs[b].nnz, b
+        assert torch.equal(C.rowptr, Cs[b].rowptr) and torch.equal(C.col, Cs[b].col) and torch.equal(C.val, Cs[b].val), b
+        X = torch.as_tensor(X0s[b], device="cuda")
+        assert ctx.fixpoint("min_plus", As[b], X, steps_per_check=4) == its[b], b
+        assert torch.equal(X, Xs[b]), b
+        del C, X
+    say("batch512 oracle samples")
+    pick = set(synth.permutation(synth.stream_key(synth.SEED_CFG3, 7), ninst)[:5].tolist()) | {int(np.argmax(ns))}
+    for b in sorted(pick):
+        src, dst, w = host[b]
+        n = int(ns[b])
+        O = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+        check_csr(Cs[b], oracle.spgemm("min_plus", "i32", O, O), "min_plus", "i32")
+        exp, it_exp, conv = oracle.bellman_ford("min_plus", "i32", O, X0s[b])
+        assert conv and its[b] == it_exp
+        assert np.array_equal(Xs[b].cpu().numpy(), exp)
