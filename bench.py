@@ -409,23 +409,148 @@ def run_batch512(args):
     return out
 
 
+def run_selector(args):
+    """Learned schedule selection.  Training set: ``--selector-matrices``
+    generated matrices (ER, R-MAT, 27-point stencil, power-law rows), each as
+    (+,x) fp32 and (min,+) int32 A.A, every schedule timed by the exhaustive
+    tuner; the MLP is trained on the GPU.  Held out: a row panel of R-MAT
+    scale 21 (edge factor 16, default a,b,c,d; rows 0..2^18-1 of the
+    relabelled graph, i.e. a random eighth) times the whole matrix, in both
+    semirings.  The step timed is the held-out panel product with the
+    selected schedule, both semirings."""
+    import torch
+    import oracle
+    import paper_1512_00066_amd as srtc
+    from paper_1512_00066_amd import selector as S
+    from gen import synth
+
+    ctx = srtc.Context(0)
+    pairs = (("plus_times", "f32"), ("min_plus", "i32"))
+    X, T, fams = [], [], []
+    t0 = time.perf_counter()
+    for i in range(args.selector_matrices):
+        fam, n, src, dst, _ = synth.selector_matrix(i, synth.SEED_CFG4)
+        keys = torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda")
+        for sr, dt in pairs:
+            v = synth.edge_values(dt, src.size, synth.SEED_CFG4, tag=i, lo=1, hi=100)
+            A = ctx.fold(sr, srtc.COO(keys, torch.as_tensor(v, device="cuda"), (n, n)), "ij", "i", "j")
+            f, t = S.collect(ctx, sr, A, A, reps=2)
+            X.append(f)
+            T.append(t)
+            fams.append(fam + "/" + sr)
+            del A
+        if i % 200 == 0:
+            log(f"  training matrix {i}: {time.perf_counter() - t0:.1f} s")
+    X, T = np.array(X, dtype=np.float32), np.array(T, dtype=np.float64)
+    t_collect = time.perf_counter() - t0
+    fixed = S.best_fixed(T)
+    t1 = time.perf_counter()
+    loss = S.train(ctx, X, T, epochs=args.selector_epochs, batch=128, lr=1e-3, seed=0)
+    t_train = time.perf_counter() - t1
+    ins = S.evaluate(ctx, X, T, fixed)
+    log(f"collected {len(X)} samples in {t_collect:.1f} s; trained in {t_train:.1f} s, loss {loss:.4f}; "
+        f"fixed schedule {fixed}; in-sample mean regret {ins['mean_regret']:.3f} "
+        f"(fixed {ins['fixed_regret']:.3f}), gain {ins['total_gain']:.3f}")
+
+    log("generating R-MAT 21 ...")
+    scale = 21
+    n = 1 << scale
+    prow = 1 << 18
+    src, dst = synth.rmat_edges(scale, 16, 0.57, 0.19, 0.19, synth.SEED_CFG4, tag=21)
+    sel = dst < prow
+    held = {}
+    for sr, dt in pairs:
+        v = synth.edge_values(dt, src.size, synth.SEED_CFG4, tag=21, lo=1, hi=100)
+        B = ctx.fold(sr, srtc.COO(torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda"),
+                                  torch.as_tensor(v, device="cuda"), (n, n)), "ij", "i", "j")
+        Ap = ctx.fold(sr, srtc.COO(torch.as_tensor(dst[sel].astype(np.int64) * n + src[sel], device="cuda"),
+                                   torch.as_tensor(v[sel], device="cuda"), (prow, n)), "ij", "i", "j")
+        f, t = S.collect(ctx, sr, Ap, B, reps=2)
+        ev = S.evaluate(ctx, f[None, :], t[None, :], fixed)
+        rp = Ap.rowptr
+        nb = torch.diff(B.rowptr)
+        products = int(nb[Ap.col.long()].sum().item())
+        held[sr] = {"times_ms": [round(float(x), 3) for x in t], "pick": ev["picks"][0], "best": int(np.argmin(t)),
+                    "regret": ev["regret"][0], "gain_over_fixed": ev["gain"][0], "products": products, "A": Ap, "B": B}
+        log(f"held-out {sr}: times {np.round(t, 1).tolist()} pick {ev['picks'][0]} best {int(np.argmin(t))} "
+            f"regret {ev['regret'][0]:.3f} gain over fixed {ev['gain'][0]:.3f}")
+
+    def step():
+        for sr, _ in pairs:
+            h = held[sr]
+            C = ctx.contract(sr, "ik", h["A"], "kj", h["B"], "ij", schedule=h["pick"])
+            del C
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    srtc.lib().srtc_profile_enable(ctx._h, 1)
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    prof = profile_table(ctx)
+    srtc.lib().srtc_profile_enable(ctx._h, 0)
+    ms = (t3 - t2) * 1e3 / args.steps
+    ops_step = sum(held[sr]["products"] for sr, _ in pairs)
+    nm, cnt, tms, by = max(prof, key=lambda r: r[2])
+    achieved = (by / cnt) / (tms / cnt / 1e3) / 1e9
+    out = {"metric": METRIC, "value": ops_step / (ms / 1e3), "unit": "semiring-ops/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+i32", "data": "synthetic",
+           "config": {"workload": "rmat21_panel_AxA_learned_schedule", "rmat_scale": 21, "edge_factor": 16,
+                      "panel_rows": prow, "training_samples": int(len(X)), "training_matrices": args.selector_matrices,
+                      "fixed_schedule": fixed, "train_loss": loss, "collect_s": t_collect, "train_s": t_train,
+                      "in_sample": {k: ins[k] for k in ("mean_regret", "max_regret", "fixed_regret", "total_gain",
+                                                         "hits")},
+                      "held_out": {sr: {k: v for k, v in h.items() if k not in ("A", "B")} for sr, h in held.items()}},
+           "roofline": {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(tms / cnt, 4), "algorithmic_bytes_per_launch": round(by / cnt)}}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        sr, dt = pairs[0]
+        v = synth.edge_values(dt, src.size, synth.SEED_CFG4, tag=21)
+        Bo = oracle.fold(sr, dt, dst, src, v, n, n)
+        nb = np.diff(Bo.rowptr)
+        w = np.zeros(n, dtype=np.int64)
+        np.add.at(w, np.repeat(np.arange(n), nb), nb[Bo.col])
+        perm = synth.permutation(synth.stream_key(synth.SEED_CFG4, 77), prow)
+        k, t_o, ops_o = 256, 0.0, 0.0
+        while t_o < args.cpu_seconds / 2 and k <= prow:
+            rows = perm[:k]
+            t4 = time.perf_counter()
+            oracle.spgemm(sr, dt, Bo, Bo, rows=rows)
+            t_o = time.perf_counter() - t4
+            ops_o = float(w[rows].sum())
+            k *= 2
+        out["cpu_baseline"] = {"value": ops_o / t_o, "unit": "semiring-ops/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{k // 2} random panel rows of the (+,x) fp32 product "
+                               f"({int(ops_o)} products); {t_o:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512"])
+    ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512", "selector"])
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
     ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--selector-matrices", type=int, default=2000)
+    ap.add_argument("--selector-epochs", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
-    out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512}[args.workload](args)
+    out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512,
+           "selector": run_selector}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

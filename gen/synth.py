@@ -26,7 +26,7 @@ __all__ = [
     "GOLDEN", "mix64", "stream_key", "rand_u64", "uniform_f64", "uniform_f32",
     "randint", "permutation", "er_edges", "rmat_edges", "stencil27_edges",
     "powerlaw_edges", "bernoulli_keys", "pick_sources", "edge_values",
-    "er_batch_params", "SEED_CFG0", "SEED_CFG1", "SEED_CFG2", "SEED_CFG3",
+    "er_batch_params", "selector_matrix", "FAMILIES", "SEED_CFG0", "SEED_CFG1", "SEED_CFG2", "SEED_CFG3",
     "SEED_CFG4",
 ]
 
@@ -260,3 +260,37 @@ def er_batch_params(count: int, seed: int, nmin: float = 1e3, nmax: float = 1e5,
     n = np.floor(np.exp(np.log(nmin) + u * (np.log(nmax) - np.log(nmin)))).astype(np.int64)
     d = dmin + v * (dmax - dmin)
     return n, d
+
+
+FAMILIES = ("er", "rmat", "stencil27", "powerlaw")
+
+
+def selector_matrix(i: int, seed: int):
+    """Matrix i of the schedule-selector training set: family i % 4 with
+    seeded parameters.  Returns (family, n, src, dst, params).  Sizes:
+    ER n log-uniform in [2^12, 2^16], degree uniform in [2, 24]; R-MAT
+    scale 12-15, edge factor 4-16, a uniform in [0.45, 0.70] with
+    b = c = 0.19 (1 - a) / 0.43; 27-point stencil on g^3, g in [16, 40];
+    power-law rows, n log-uniform in [2^12, 2^15], exponent in [1.8, 2.6]."""
+    fam = FAMILIES[i % 4]
+    u = uniform_f64(stream_key(seed, 5000 + i), 4)
+    if fam == "er":
+        n = int(2 ** (12 + 4 * u[0]))
+        d = 2.0 + 22.0 * u[1]
+        src, dst = er_edges(n, d, seed, tag=5000 + i)
+        return fam, n, src, dst, {"n": n, "d": d}
+    if fam == "rmat":
+        scale = 12 + int(u[0] * 4)
+        ef = 4 + int(u[1] * 13)
+        a = 0.45 + 0.25 * u[2]
+        b = 0.19 * (1.0 - a) / 0.43
+        src, dst = rmat_edges(scale, ef, a, b, b, seed, tag=5000 + i)
+        return fam, 1 << scale, src, dst, {"scale": scale, "ef": ef, "a": a}
+    if fam == "stencil27":
+        g = 16 + int(u[0] * 25)
+        src, dst = stencil27_edges(g)
+        return fam, g ** 3, src, dst, {"g": g}
+    n = int(2 ** (12 + 3 * u[0]))
+    gamma = 1.8 + 0.8 * u[1]
+    src, dst = powerlaw_edges(n, gamma, seed, tag=5000 + i)
+    return fam, n, src, dst, {"n": n, "gamma": gamma}
