@@ -247,7 +247,7 @@ def run_rmat20_sssp(args):
         A = ctx.fold("min_plus", coo, "ij", "i", "j")
         X.copy_(P0d)
         ev[0].record()
-        it = ctx.fixpoint("min_plus", A, X, steps_per_check=4)
+        it = ctx.fixpoint("min_plus", A, X, steps_per_check=4, changed_rows_only=args.changed_rows)
         ev[1].record()
         lev, depth = ctx.bfs_levels(A, sources)
         ev[2].record()
@@ -279,7 +279,10 @@ def run_rmat20_sssp(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
            "config": {"workload": "rmat20_64src_bellman_ford_fixpoint+bfs", "rmat_scale": 20, "edge_factor": 16,
                       "weights": [1, 255], "sources": nsrc, "nnz_A": nnz, "bf_steps": it, "bfs_depth": depth,
-                      "steps_per_graph": 4, "bf_ms": t_bf / args.steps, "bfs_ms": t_bfs / args.steps},
+                      "steps_per_graph": 4, "bf_ms": t_bf / args.steps, "bfs_ms": t_bfs / args.steps,
+                      "changed_rows_only": bool(args.changed_rows),
+                      "ops_note": "nnz(A) x sources per Bellman-Ford step and per BFS level; with changed-rows-only "
+                                  "steps the iterates are the same and ops are counted as for full steps"},
            "roofline": {"bound": "hbm", "kernel": "spmm.fixpoint_step (graph-captured; fixpoint time / steps)",
                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -531,6 +534,21 @@ def run_selector(args):
     return out
 
 
+def copy_calibration(args):
+    """A plain device copy of known size (1 GiB read, 1 GiB written per
+    launch), run under the same HBM counters as the kernels, to scale
+    FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": args.steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -544,11 +562,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--selector-matrices", type=int, default=2000)
     ap.add_argument("--selector-epochs", type=int, default=400)
+    ap.add_argument("--changed-rows", action="store_true",
+                    help="rmat20_sssp: fixpoint steps gather only from rows changed in the previous step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args)
+        return
     out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512,
            "selector": run_selector}[args.workload](args)
     print(json.dumps(out), flush=True)

@@ -214,6 +214,20 @@ srtc_status srtc_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
                           const srtc_tensor *A, srtc_tensor *X, int64_t max_iters,
                           int32_t steps_per_check, int64_t *iters_out, void *stream);
 
+/* srtc_fixpoint with options.  flags:
+ *   SRTC_FIXPOINT_CHANGED_ROWS  each step gathers only from rows of X that
+ *     changed in the previous step (the first step from all rows).  An
+ *     unchanged row's term is already part of every row it reaches, and the
+ *     additive op of every supported semiring is idempotent, so the
+ *     iterates, X and *iters_out are exactly those of srtc_fixpoint; the
+ *     gathers drop to the frontier's changed rows.  Needs 2n bytes of
+ *     scratch.
+ * Other arguments, errors and support as srtc_fixpoint. */
+#define SRTC_FIXPOINT_CHANGED_ROWS 1
+srtc_status srtc_fixpoint_ex(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const srtc_tensor *A,
+                             srtc_tensor *X, int64_t max_iters, int32_t steps_per_check, int32_t flags,
+                             int64_t *iters_out, void *stream);
+
 /* Multi-source breadth-first levels over the (or,and) semiring with a
  * bit-packed frontier (one uint64 per vertex, bit t = source t, nsrc <= 64).
  * A's pattern gives the edges (entry (i, j) = edge j -> i; values ignored).

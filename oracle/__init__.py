@@ -217,6 +217,12 @@ def spgemm(semiring, dtype, A: CSR, B: CSR, add_id=None, rows=None, C_old: CSR =
     return CSR(rp, oc[:total], ov[:total], sel.size, B.ncols)
 
 
+def dense_plus_times(A, B):
+    """Dense (+,x) product C = A B in fp64: the contraction's definition
+    over full operands (the dense case of Section 3.3.1), one library matmul."""
+    return np.asarray(A, dtype=np.float64) @ np.asarray(B, dtype=np.float64)
+
+
 def spmm(semiring, dtype, A: CSR, X, add_id=None, self_term=False):
     """Y = [X (+)] A (x) X for dense row-major X (n x s).  Returns (Y, changed).
     (+,x) gives fp64; other semirings keep the stored type."""

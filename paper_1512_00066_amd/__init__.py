@@ -96,6 +96,7 @@ def lib():
             "srtc_contract": ([P, ctypes.c_int, P, ctypes.c_int, S, T, S, T, S, T, ctypes.POINTER(_Opts), P],
                               ctypes.c_int),
             "srtc_fixpoint": ([P, ctypes.c_int, P, T, T, I64_, I32_, ctypes.POINTER(I64_), P], ctypes.c_int),
+            "srtc_fixpoint_ex": ([P, ctypes.c_int, P, T, T, I64_, I32_, I32_, ctypes.POINTER(I64_), P], ctypes.c_int),
             "srtc_bfs_levels": ([P, T, ctypes.POINTER(I64_), I32_, P, ctypes.POINTER(I32_), P], ctypes.c_int),
             "srtc_batch_contract": ([P, ctypes.c_int, P, I32_, T, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
             "srtc_batch_fixpoint": ([P, ctypes.c_int, P, I32_, T, T, I64_, I32_, ctypes.POINTER(I64_), P],
@@ -300,11 +301,12 @@ class Context:
         return self._csr_out(out)
 
     def contract(self, semiring, ia: str, A, ib: str, B, ic: str, C=None, accumulate=False, add_id=None,
-                 schedule: int = -1, sorted: bool = True, out_dims=None):
+                 schedule: int = -1, sorted: bool = True, out_dims=None, validate: bool = False):
         """C[ic] (+)= A[ia] (x) B[ib].  Sparse x sparse returns a CSR; with a
-        dense operand C must be a preallocated dense tensor (returned)."""
+        dense operand C must be a preallocated dense tensor (returned).
+        validate: check the sparse operands' structure first."""
         ad, bd = _desc(A), _desc(B)
-        opts = _Opts(schedule, 1 if sorted else 0, 0, 0)
+        opts = _Opts(schedule, 1 if sorted else 0, 1 if validate else 0, 0)
         if C is None:
             # sparse result: dims of C from the index strings
             ext = {}
@@ -329,13 +331,15 @@ class Context:
         return C
 
     def fixpoint(self, semiring, A: CSR, X: torch.Tensor, max_iters: int = 0, steps_per_check: int = 4,
-                 add_id=None) -> int:
-        """X <- X (+) A (x) X until unchanged (in place); returns the step count."""
+                 add_id=None, changed_rows_only: bool = False) -> int:
+        """X <- X (+) A (x) X until unchanged (in place); returns the step count.
+        changed_rows_only: each step gathers only from rows that changed in
+        the previous one (same iterates and result)."""
         ad, xd = _desc(A), _desc(X)
         it = ctypes.c_int64(0)
-        st = lib().srtc_fixpoint(self._h, _sr(semiring), _add_id(add_id, ad.dtype), ctypes.byref(ad),
-                                 ctypes.byref(xd), int(max_iters), int(steps_per_check), ctypes.byref(it),
-                                 self._stream())
+        st = lib().srtc_fixpoint_ex(self._h, _sr(semiring), _add_id(add_id, ad.dtype), ctypes.byref(ad),
+                                    ctypes.byref(xd), int(max_iters), int(steps_per_check),
+                                    1 if changed_rows_only else 0, ctypes.byref(it), self._stream())
         self._check(st, it.value)
         return it.value
 

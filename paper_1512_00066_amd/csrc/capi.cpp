@@ -557,6 +557,11 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
     brow += p.K;
     bcol += p.N;
     const bool a_sparse = A->format != SRTC_DENSE, b_sparse = B->format != SRTC_DENSE;
+    if (o.validate) {
+      validate_operand(c, sr, A, "A", s);
+      validate_operand(c, sr, B, "B", s);
+      if (accumulate && C->format == SRTC_CSR) validate_operand(c, sr, C, "C", s);
+    }
     if (a_sparse && b_sparse) {
       if (C->format == SRTC_DENSE) fail(SRTC_ERR_UNSUPPORTED, "sparse x sparse gives a sparse (CSR) C");
       Folded fa, fb;
@@ -644,7 +649,14 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
 
 srtc_status srtc_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const srtc_tensor *A, srtc_tensor *X,
                           int64_t max_iters, int32_t steps_per_check, int64_t *iters_out, void *stream) {
+  return srtc_fixpoint_ex(ctx, sr, add_id, A, X, max_iters, steps_per_check, 0, iters_out, stream);
+}
+
+srtc_status srtc_fixpoint_ex(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const srtc_tensor *A,
+                             srtc_tensor *X, int64_t max_iters, int32_t steps_per_check, int32_t flags,
+                             int64_t *iters_out, void *stream) {
   return guard(ctx, [&] {
+    if (flags & ~SRTC_FIXPOINT_CHANGED_ROWS) fail(SRTC_ERR_ARG, "unknown fixpoint flags");
     check_tensor(A, "A");
     check_tensor(X, "X");
     if (A->format != SRTC_CSR || A->order != 2 || A->split != 1) fail(SRTC_ERR_FORMAT, "A must be a CSR matrix");
@@ -667,13 +679,26 @@ srtc_status srtc_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, c
     pl.build(c, av, sw, s);
     const size_t bytes = tensor_value_bytes(X);
     Buf xb(c, bytes);
-    Buf flags(c, sizeof(int32_t) * (size_t)k);
+    Buf chg(c, sizeof(int32_t) * (size_t)k);  // one change flag per step
     void *xa = X->vals;
     void *bufs[2] = {xa, xb.p};
+    // changed-row masks, double-buffered like X: step t reads rch[t&1] and
+    // writes rch[(t&1)^1]; cleared by a fill kernel (graph-safe)
+    const bool delta = (flags & SRTC_FIXPOINT_CHANGED_ROWS) != 0;
+    const int64_t nw = (n + 3) / 4;  // int32 words per mask
+    Buf rch;
+    uint8_t *rbuf[2] = {nullptr, nullptr};
+    if (delta) {
+      rch = Buf(c, sizeof(int32_t) * (size_t)std::max<int64_t>(2 * nw, 1));
+      rbuf[0] = rch.as<uint8_t>();
+      rbuf[1] = rch.as<uint8_t>() + 4 * nw;
+      fill_i32(reinterpret_cast<int32_t *>(rbuf[0]), nw, 0x01010101, s);  // first step: every row
+    }
     auto step = [&](int t, int parity, hipStream_t st) {
-      fill_i32(flags.as<int32_t>() + t, 1, 0, st);
-      spmm_with_plan(pl, sr, dt, id, av, bufs[parity], sw, bufs[parity ^ 1], 1, 0, flags.as<int32_t>() + t,
-                     nullptr, nullptr, nullptr, st);
+      fill_i32(chg.as<int32_t>() + t, 1, 0, st);
+      if (delta) fill_i32(reinterpret_cast<int32_t *>(rbuf[parity ^ 1]), nw, 0, st);
+      spmm_with_plan(pl, sr, dt, id, av, bufs[parity], sw, bufs[parity ^ 1], 1, 0, chg.as<int32_t>() + t,
+                     nullptr, nullptr, nullptr, st, delta ? rbuf[parity] : nullptr, delta ? rbuf[parity ^ 1] : nullptr);
     };
     // capture k steps (k even: the iterate returns to X)
     hipStream_t cap;
@@ -707,7 +732,7 @@ srtc_status srtc_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, c
         for (int t = 0; t < nsteps; t++) step(t, t & 1, s);
         if (nsteps & 1) SRTC_HIP(hipMemcpyAsync(xa, xb.p, bytes, hipMemcpyDeviceToDevice, s));
       }
-      read_to_host(c, hf.data(), flags.p, sizeof(int32_t) * (size_t)nsteps, s);
+      read_to_host(c, hf.data(), chg.p, sizeof(int32_t) * (size_t)nsteps, s);
       for (int t = 0; t < nsteps; t++) {
         if (hf[t] == 0) {
           if (iters_out) *iters_out = r + t + 1;

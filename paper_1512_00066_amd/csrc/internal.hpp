@@ -127,7 +127,7 @@ struct Schedule {
   int64_t t_tiny, t_small, t_mid, t_big;
   int small_wave;    // 512-slot bin: one 64-thread wave per row (1) or two waves (0)
   int dense_bs;      // dense-window block size (256 or 512)
-  int dense_wide;    // dense window of 16K (1) or 8K (0) 8-byte accumulators
+  int dense_wide;    // dense window of 8K (0), 16K (1) or 4K (2) 8-byte accumulators
 };
 const Schedule &schedule(int id);
 
@@ -176,6 +176,10 @@ void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B,
 IdVal make_id_public(int sr, int dt, const void *add_id);
 // Key of the autotune cache for a feature vector.
 std::string tune_key(int sr, int dt, const float *features);
+// Structure checks of a sparse operand (SRTC_ERR_FORMAT on failure); one
+// host sync.
+void validate_operand(Ctx *c, int sr, const srtc_tensor *t, const char *name, hipStream_t s);
+
 }  // namespace srtc
 
 struct srtc_ctx {

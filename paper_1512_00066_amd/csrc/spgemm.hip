@@ -760,7 +760,7 @@ const Schedule kSchedules[SRTC_NUM_SCHEDULES] = {
     {8192, 32, 256, 2048, 4096, 0, 512, 1},   // 3 hash-heavy, wide dense windows
     {0, 0, 0, 0, 0, 0, 256, 0},               // 4 dense windows for every row
     {2048, 32, 256, 2048, 4096, 0, 512, 0},   // 5 as 0 with 512-thread dense blocks
-    {2048, 32, 256, 2048, 4096, 0, 256, 1},   // 6 as 0 with wide dense windows
+    {2048, 32, 256, 2048, 4096, 0, 512, 2},   // 6 as 5 with narrow dense windows (more blocks per CU)
     {256, 32, 256, 1024, 1024, 1, 256, 0},    // 7 bitmap symbolic above 256 products
 };
 
@@ -888,10 +888,11 @@ template <class SR> struct NumLaunch {
   }
 };
 
-// Dense window width (columns) for a semiring and schedule.
-template <class SR> int64_t dense_width(bool wide) {
-  if (!SR::HAS_VALS) return wide ? (1 << 20) : (1 << 18);
-  return (wide ? 16384 : 8192) * (8 / (int)sizeof(typename SR::acc_t));
+// Dense window width (columns) for a semiring and a schedule's width code
+// (0: 64 KB of accumulators, 1: 128 KB, 2: 32 KB).
+template <class SR> constexpr int64_t dense_width(int code) {
+  if (!SR::HAS_VALS) return code == 1 ? (1 << 20) : code == 2 ? (1 << 17) : (1 << 18);
+  return (code == 1 ? 16384 : code == 2 ? 4096 : 8192) * (8 / (int64_t)sizeof(typename SR::acc_t));
 }
 
 template <class SR>
@@ -1001,7 +1002,7 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
     }
   }
   if (hinfo2[5] > 0) {
-    const int64_t W = dense_width<SR>(S.dense_wide != 0);
+    const int64_t W = dense_width<SR>(S.dense_wide);
     const int nwin = (int)((n + W - 1) / W);
     Buf woff;
     if (nwin > 1) {
@@ -1012,12 +1013,15 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
     }
     const int32_t *wo = woff.as<int32_t>();
     ProfScope ps(c, pname(5).c_str(), num_bytes(5) + (nwin > 1 ? 8.0 * hinfo2[SUMA + 5] * nwin : 0.0), s);
-    if (S.dense_wide) {
-      if (S.dense_bs == 512) NL::template dense<512, (int)(SR::HAS_VALS ? 16384 * 8 / sizeof(A) : (1 << 20))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
-      else NL::template dense<256, (int)(SR::HAS_VALS ? 16384 * 8 / sizeof(A) : (1 << 20))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+    constexpr int W0 = (int)dense_width<SR>(0), W1 = (int)dense_width<SR>(1), W2 = (int)dense_width<SR>(2);
+    if (S.dense_wide == 1) {
+      if (S.dense_bs == 512) NL::template dense<512, W1>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      else NL::template dense<256, W1>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+    } else if (S.dense_wide == 2) {
+      NL::template dense<512, W2>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
     } else {
-      if (S.dense_bs == 512) NL::template dense<512, (int)(SR::HAS_VALS ? 8192 * 8 / sizeof(A) : (1 << 18))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
-      else NL::template dense<256, (int)(SR::HAS_VALS ? 8192 * 8 / sizeof(A) : (1 << 18))>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      if (S.dense_bs == 512) NL::template dense<512, W0>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      else NL::template dense<256, W0>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
     }
   }
   // 6. compaction when identity results were dropped

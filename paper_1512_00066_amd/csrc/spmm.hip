@@ -64,7 +64,8 @@ __global__ void __launch_bounds__(256) spmm_items(const int32_t *__restrict__ ir
                                                   void *__restrict__ Yv, typename SR::acc_t *__restrict__ P,
                                                   typename SR::acc_t id, int32_t *changed,
                                                   const int32_t *__restrict__ row_inst,
-                                                  const uint8_t *__restrict__ inst_active, int32_t *inst_changed) {
+                                                  const uint8_t *__restrict__ inst_active, int32_t *inst_changed,
+                                                  const uint8_t *__restrict__ rin, uint8_t *__restrict__ rout) {
   using V = typename SR::val_t;
   using A = typename SR::acc_t;
   // (+,x) SpMM results are stored in the operand type; accumulators are A
@@ -86,21 +87,33 @@ __global__ void __launch_bounds__(256) spmm_items(const int32_t *__restrict__ ir
       A acc = id;
       if (on) {
         int64_t p = b;
-        for (; p + 4 <= e; p += 4) {
-          const int32_t k0 = cA[p], k1 = cA[p + 1], k2 = cA[p + 2], k3 = cA[p + 3];
-          const V a0 = vA[p], a1 = vA[p + 1], a2 = vA[p + 2], a3 = vA[p + 3];
-          const V x0 = X[(int64_t)k0 * s + col], x1 = X[(int64_t)k1 * s + col];
-          const V x2 = X[(int64_t)k2 * s + col], x3 = X[(int64_t)k3 * s + col];
-          if (!SR::absent(a0, id) && !SR::absent(x0, id)) acc = SR::add(acc, SR::mul(a0, x0));
-          if (!SR::absent(a1, id) && !SR::absent(x1, id)) acc = SR::add(acc, SR::mul(a1, x1));
-          if (!SR::absent(a2, id) && !SR::absent(x2, id)) acc = SR::add(acc, SR::mul(a2, x2));
-          if (!SR::absent(a3, id) && !SR::absent(x3, id)) acc = SR::add(acc, SR::mul(a3, x3));
-        }
-        for (; p < e; p++) {
-          const int32_t k = cA[p];
-          const V a = vA[p];
-          const V x = X[(int64_t)k * s + col];
-          if (!SR::absent(a, id) && !SR::absent(x, id)) acc = SR::add(acc, SR::mul(a, x));
+        if (MODE == 1 && rin) {
+          // only rows that changed in the previous step can lower this one:
+          // an unchanged row's term is already part of the row's value
+          for (; p < e; p++) {
+            const int32_t k = cA[p];
+            if (!rin[k]) continue;
+            const V a = vA[p];
+            const V x = X[(int64_t)k * s + col];
+            if (!SR::absent(a, id) && !SR::absent(x, id)) acc = SR::add(acc, SR::mul(a, x));
+          }
+        } else {
+          for (; p + 4 <= e; p += 4) {
+            const int32_t k0 = cA[p], k1 = cA[p + 1], k2 = cA[p + 2], k3 = cA[p + 3];
+            const V a0 = vA[p], a1 = vA[p + 1], a2 = vA[p + 2], a3 = vA[p + 3];
+            const V x0 = X[(int64_t)k0 * s + col], x1 = X[(int64_t)k1 * s + col];
+            const V x2 = X[(int64_t)k2 * s + col], x3 = X[(int64_t)k3 * s + col];
+            if (!SR::absent(a0, id) && !SR::absent(x0, id)) acc = SR::add(acc, SR::mul(a0, x0));
+            if (!SR::absent(a1, id) && !SR::absent(x1, id)) acc = SR::add(acc, SR::mul(a1, x1));
+            if (!SR::absent(a2, id) && !SR::absent(x2, id)) acc = SR::add(acc, SR::mul(a2, x2));
+            if (!SR::absent(a3, id) && !SR::absent(x3, id)) acc = SR::add(acc, SR::mul(a3, x3));
+          }
+          for (; p < e; p++) {
+            const int32_t k = cA[p];
+            const V a = vA[p];
+            const V x = X[(int64_t)k * s + col];
+            if (!SR::absent(a, id) && !SR::absent(x, id)) acc = SR::add(acc, SR::mul(a, x));
+          }
         }
       }
       bool diff = false;
@@ -128,6 +141,7 @@ __global__ void __launch_bounds__(256) spmm_items(const int32_t *__restrict__ ir
         if (diff && (bal & gmask & lanemask_lt()) == 0) {
           *changed = 1;
           if (row_inst) inst_changed[row_inst[row]] = 1;
+          if (rout) rout[row] = 1;
         }
       }
     }
@@ -143,7 +157,8 @@ __global__ void __launch_bounds__(256) spmm_combine(const int32_t *__restrict__ 
                                                     void *__restrict__ Yv, const typename SR::acc_t *__restrict__ P,
                                                     typename SR::acc_t id, int32_t *changed,
                                                     const int32_t *__restrict__ row_inst,
-                                                    const uint8_t *__restrict__ inst_active, int32_t *inst_changed) {
+                                                    const uint8_t *__restrict__ inst_active, int32_t *inst_changed,
+                                                    uint8_t *__restrict__ rout) {
   using V = typename SR::val_t;
   using A = typename SR::acc_t;
   V *Y = reinterpret_cast<V *>(Yv);
@@ -178,6 +193,7 @@ __global__ void __launch_bounds__(256) spmm_combine(const int32_t *__restrict__ 
       if (MODE == 1 && o != X[row * s + col]) {
         *changed = 1;
         if (row_inst) inst_changed[row_inst[row]] = 1;
+        if (rout) rout[row] = 1;
       }
     }
   }
@@ -186,19 +202,19 @@ __global__ void __launch_bounds__(256) spmm_combine(const int32_t *__restrict__ 
 template <class SR, int G, int MODE, bool ACC>
 void run_items(const SpmmPlan &pl, const CsrView &A, const void *X, int64_t s, void *Y, IdVal idv,
                int32_t *changed, const int32_t *row_inst, const uint8_t *inst_active, int32_t *inst_changed,
-               hipStream_t st) {
+               const uint8_t *rin, uint8_t *rout, hipStream_t st) {
   using V = typename SR::val_t;
   using Acc = typename SR::acc_t;
   const Acc id = id_as<SR>(idv);
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(pl.max_items * G / 256 + 1, pl.grid_cap));
   spmm_items<SR, G, MODE, ACC><<<grid, 256, 0, st>>>(pl.irow, pl.ibeg, pl.iend, pl.ipidx, pl.nitems, A.col,
                                                       (const V *)A.val, (const V *)X, s, Y, (Acc *)pl.partial, id,
-                                                      changed, row_inst, inst_active, inst_changed);
+                                                      changed, row_inst, inst_active, inst_changed, rin, rout);
   SRTC_LAUNCH_CHECK("spmm_items");
   if (pl.may_split) {
     spmm_combine<SR, G, MODE, ACC><<<grid, 256, 0, st>>>(pl.irow, pl.ibeg, pl.ipidx, pl.nitems, A.rowptr, pl.T,
                                                           (const V *)X, s, Y, (const Acc *)pl.partial, id, changed,
-                                                          row_inst, inst_active, inst_changed);
+                                                          row_inst, inst_active, inst_changed, rout);
     SRTC_LAUNCH_CHECK("spmm_combine");
   }
 }
@@ -206,15 +222,15 @@ void run_items(const SpmmPlan &pl, const CsrView &A, const void *X, int64_t s, v
 template <class SR, int MODE, bool ACC>
 void run_by_width(const SpmmPlan &pl, const CsrView &A, const void *X, int64_t s, void *Y, IdVal id,
                   int32_t *changed, const int32_t *row_inst, const uint8_t *inst_active, int32_t *inst_changed,
-                  hipStream_t st) {
+                  const uint8_t *rin, uint8_t *rout, hipStream_t st) {
   switch (pl.G) {
-    case 1: run_items<SR, 1, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, st); break;
-    case 2: run_items<SR, 2, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, st); break;
-    case 4: run_items<SR, 4, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, st); break;
-    case 8: run_items<SR, 8, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, st); break;
-    case 16: run_items<SR, 16, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, st); break;
-    case 32: run_items<SR, 32, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, st); break;
-    default: run_items<SR, 64, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, st); break;
+    case 1: run_items<SR, 1, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, rin, rout, st); break;
+    case 2: run_items<SR, 2, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, rin, rout, st); break;
+    case 4: run_items<SR, 4, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, rin, rout, st); break;
+    case 8: run_items<SR, 8, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, rin, rout, st); break;
+    case 16: run_items<SR, 16, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, rin, rout, st); break;
+    case 32: run_items<SR, 32, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, rin, rout, st); break;
+    default: run_items<SR, 64, MODE, ACC>(pl, A, X, s, Y, id, changed, row_inst, inst_active, inst_changed, rin, rout, st); break;
   }
 }
 
@@ -231,17 +247,21 @@ struct SpmmCall {
   const int32_t *row_inst;
   const uint8_t *inst_active;
   int32_t *inst_changed;
+  const uint8_t *rin;
+  uint8_t *rout;
   hipStream_t st;
 };
 
 template <class SR> void spmm_dispatch(const SpmmCall &q) {
   if (q.mode == 1)
     run_by_width<SR, 1, false>(*q.pl, *q.A, q.X, q.s, q.Y, q.id, q.changed, q.row_inst, q.inst_active,
-                               q.inst_changed, q.st);
+                               q.inst_changed, q.rin, q.rout, q.st);
   else if (q.acc)
-    run_by_width<SR, 0, true>(*q.pl, *q.A, q.X, q.s, q.Y, q.id, nullptr, nullptr, nullptr, nullptr, q.st);
+    run_by_width<SR, 0, true>(*q.pl, *q.A, q.X, q.s, q.Y, q.id, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, q.st);
   else
-    run_by_width<SR, 0, false>(*q.pl, *q.A, q.X, q.s, q.Y, q.id, nullptr, nullptr, nullptr, nullptr, q.st);
+    run_by_width<SR, 0, false>(*q.pl, *q.A, q.X, q.s, q.Y, q.id, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, q.st);
 }
 
 // --------------------------------------------------------------------- BFS --
@@ -319,8 +339,9 @@ void SpmmPlan::build(Ctx *c, const CsrView &A, int64_t s_width, hipStream_t st) 
 
 void spmm_with_plan(const SpmmPlan &pl, int sr, int dt, IdVal id, const CsrView &A, const void *X,
                     int64_t s_width, void *Y, int mode, int accumulate, int32_t *changed, const int32_t *row_inst,
-                    const uint8_t *inst_active, int32_t *inst_changed, hipStream_t st) {
-  SpmmCall q{&pl, &A, X, s_width, Y, id, mode, accumulate, changed, row_inst, inst_active, inst_changed, st};
+                    const uint8_t *inst_active, int32_t *inst_changed, hipStream_t st, const uint8_t *rin,
+                    uint8_t *rout) {
+  SpmmCall q{&pl, &A, X, s_width, Y, id, mode, accumulate, changed, row_inst, inst_active, inst_changed, rin, rout, st};
   // algorithmic bytes: A once, X once, Y written (and read for the self
   // term / accumulation)
   const double es = (double)dtype_size(dt);

@@ -22,8 +22,12 @@ struct SpmmPlan {
 
 // mode 0: Y = A (x) X (accumulate: Y (+)= A (x) X); mode 1: fixpoint step
 // Y = X (+) A (x) X raising *changed (and per-instance flags) on change.
+// In mode 1, rin (one byte per row, optional) limits the gathers to rows
+// that changed in the previous step, and rout (optional) marks the rows
+// this step changed; both need an idempotent additive op.
 void spmm_with_plan(const SpmmPlan &pl, int sr, int dt, IdVal id, const CsrView &A, const void *X,
                     int64_t s_width, void *Y, int mode, int accumulate, int32_t *changed, const int32_t *row_inst,
-                    const uint8_t *inst_active, int32_t *inst_changed, hipStream_t st);
+                    const uint8_t *inst_active, int32_t *inst_changed, hipStream_t st, const uint8_t *rin = nullptr,
+                    uint8_t *rout = nullptr);
 
 }  // namespace srtc

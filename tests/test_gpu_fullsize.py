@@ -92,6 +92,9 @@ def test_rmat20_multi_source_sssp_and_bfs():
     assert np.array_equal(got, Pexp)
     pick = np.sort(synth.permutation(synth.stream_key(synth.SEED_CFG2, 5), 64)[:4])
     assert np.array_equal(Pexp[:, pick].astype(np.int64), oracle.dijkstra(O, sources[pick]))
+    X2 = torch.as_tensor(P0, device="cuda")
+    assert ctx.fixpoint("min_plus", G, X2, steps_per_check=4, changed_rows_only=True) == it_exp
+    assert torch.equal(X2, X)
     say("rmat20 BFS")
     lev, depth = ctx.bfs_levels(G, sources)
     exp = oracle.bfs_levels(O, sources)

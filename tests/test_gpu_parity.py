@@ -298,6 +298,16 @@ def test_multi_source_bellman_ford_and_bfs(ctx):
     assert conv and it == it_exp
     assert np.array_equal(X.cpu().numpy(), Pexp)
     assert np.array_equal(Pexp.astype(np.int64), oracle.dijkstra(O, sources))
+    # gathers from changed rows only: same iterates, same result
+    X2 = torch.as_tensor(P0, device="cuda")
+    assert ctx.fixpoint("min_plus", G, X2, steps_per_check=4, changed_rows_only=True) == it_exp
+    assert np.array_equal(X2.cpu().numpy(), Pexp)
+    for cap in (1, 3, 6):
+        Xc = torch.as_tensor(P0, device="cuda")
+        with pytest.raises(srtc.NotConverged):
+            ctx.fixpoint("min_plus", G, Xc, max_iters=cap, steps_per_check=4, changed_rows_only=True)
+        expc, _, _ = oracle.bellman_ford("min_plus", "i32", O, P0, max_iters=cap)
+        assert np.array_equal(Xc.cpu().numpy(), expc), cap
     lev, depth = ctx.bfs_levels(G, sources)
     exp = oracle.bfs_levels(O, sources)
     assert np.array_equal(lev.cpu().numpy(), exp) and depth == exp.max()
@@ -310,6 +320,10 @@ def test_fixpoint_not_converged_and_cap(ctx):
     X = torch.as_tensor(np.array([[0], [INF], [INF]], np.int32), device="cuda")
     with pytest.raises(srtc.NotConverged) as e:
         ctx.fixpoint("min_plus", A, X)
+    assert e.value.iters == 3
+    X = torch.as_tensor(np.array([[0], [INF], [INF]], np.int32), device="cuda")
+    with pytest.raises(srtc.NotConverged) as e:
+        ctx.fixpoint("min_plus", A, X, changed_rows_only=True)
     assert e.value.iters == 3
     # path graph with a cap below its n steps
     n = 50
@@ -340,7 +354,7 @@ def test_dense_mfma(ctx, dtype):
         C = torch.zeros((M, N), dtype=TORCH[dtype], device="cuda")
         ctx.contract("plus_times", "ik", torch.as_tensor(a, device="cuda"), "kj", torch.as_tensor(b, device="cuda"),
                      "ij", C=C)
-        ref = a.astype(np.float64) @ b.astype(np.float64)   # non-negative terms
+        ref = oracle.dense_plus_times(a, b)   # non-negative terms
         tol = 1e-12 if dtype == "f64" else 1e-5
         assert np.all(np.abs(C.cpu().numpy().astype(np.float64) - ref) <= tol * ref)
 
@@ -445,3 +459,41 @@ def test_error_statuses(ctx):
     with pytest.raises(srtc.SrtcError) as e:
         ctx.contract("min_plus", "ik", A, "kj", X, "ij", C=X[:3])   # C is a view of B
     assert e.value.status == -6
+
+
+def test_validate_rejects_malformed_operands(ctx):
+    # With validate=True every malformed sparse operand is reported as
+    # SRTC_ERR_FORMAT before any kernel uses it (malformed operands are
+    # never passed without it).
+    say("validation")
+    good = gpu_fold(ctx, "min_plus", "i32", [0, 0, 1, 2], [0, 2, 1, 0], np.array([1, 2, 3, 4], np.int32), 3, 3)
+    C = ctx.contract("min_plus", "ik", good, "kj", good, "ij", validate=True)
+    assert C.nnz > 0
+
+    def csr(rp, col, val, dims=(3, 3)):
+        return srtc.CSR(torch.tensor(rp, dtype=torch.int64, device="cuda"),
+                        torch.tensor(col, dtype=torch.int32, device="cuda"),
+                        torch.tensor(val, device="cuda"), dims, 1)
+
+    bad = [
+        csr([1, 2, 3, 4], [0, 1, 2, 0], np.array([1, 1, 1, 1], np.int32)),   # rowptr[0] != 0
+        csr([0, 3, 2, 4], [0, 1, 2, 0], np.array([1, 1, 1, 1], np.int32)),   # rowptr decreases
+        csr([0, 1, 2, 3], [0, 1, 2, 0], np.array([1, 1, 1, 1], np.int32)),   # rowptr[m] != nnz
+        csr([0, 2, 3, 4], [0, 5, 2, 0], np.array([1, 1, 1, 1], np.int32)),   # column out of range
+        csr([0, 2, 3, 4], [2, 0, 1, 0], np.array([1, 1, 1, 1], np.int32)),   # row not ascending
+        csr([0, 2, 3, 4], [1, 1, 1, 0], np.array([1, 1, 1, 1], np.int32)),   # repeated column
+    ]
+    for b in bad:
+        with pytest.raises(srtc.SrtcError) as e:
+            ctx.contract("min_plus", "ik", b, "kj", good, "ij", validate=True)
+        assert e.value.status == -5
+    keys = torch.tensor([0, 4, 9], dtype=torch.int64, device="cuda")   # 9 is outside 3 x 3
+    coo = srtc.COO(keys, torch.tensor([1, 1, 1], dtype=torch.int32, device="cuda"), (3, 3))
+    with pytest.raises(srtc.SrtcError) as e:
+        ctx.contract("min_plus", "ik", coo, "kj", good, "ij", validate=True)
+    assert e.value.status == -5
+    fgood = gpu_fold(ctx, "min_plus", "f32", [0, 1], [1, 0], np.array([1.0, 2.0], np.float32), 2, 2)
+    fnan = csr([0, 1, 2], [1, 0], np.array([np.nan, 2.0], np.float32), (2, 2))
+    with pytest.raises(srtc.SrtcError) as e:
+        ctx.contract("min_plus", "ik", fnan, "kj", fgood, "ij", validate=True)
+    assert e.value.status == -5

@@ -386,3 +386,17 @@ def test_mlp_oracle_gradient_matches_finite_differences():
     z[-K:] = np.arange(K)
     y, _ = mlp.forward(z, X, K)
     assert np.array_equal(y, np.tile(np.arange(K, dtype=float), (7, 1)))
+
+
+def test_dense_plus_times_pins():
+    # explicit triple loop on a small case, and the all-ones closed form
+    a = synth.uniform_f64(synth.stream_key(31, 0), 5 * 7).reshape(5, 7)
+    b = synth.uniform_f64(synth.stream_key(31, 1), 7 * 3).reshape(7, 3)
+    ref = np.zeros((5, 3))
+    for i in range(5):
+        for j in range(3):
+            for k in range(7):
+                ref[i, j] += a[i, k] * b[k, j]
+    assert np.allclose(oracle.dense_plus_times(a, b), ref, rtol=1e-15, atol=0)
+    n = 37
+    assert np.array_equal(oracle.dense_plus_times(np.ones((n, n)), np.ones((n, n))), np.full((n, n), float(n)))
