@@ -476,6 +476,10 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
       const int P = cnt <= 1 ? 1 : 1 << (32 - __clz(cnt - 1));  // next power of two >= cnt
       for (int s = cnt + threadIdx.x; s < P; s += BS) keys[s] = EMPTY;
       __syncthreads();
+      // While the stride is at most 64, the pairs of the 64 consecutive q
+      // of one wave stay inside one 128-entry block that no other wave
+      // touches, so consecutive passes with such strides need only a
+      // wave-level sync; a block barrier separates the others.
       for (int k = 2; k <= P; k <<= 1) {
         for (int jst = k >> 1; jst > 0; jst >>= 1) {
           for (int q = threadIdx.x; q < P / 2; q += BS) {
@@ -493,7 +497,14 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
               }
             }
           }
-          __syncthreads();
+          const int next = jst > 1 ? jst >> 1 : (2 * k <= P ? k : 0);
+          if (jst > WAVE || next > WAVE || next == 0) {
+            __syncthreads();
+          } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          }
         }
       }
       for (int s = threadIdx.x; s < cnt; s += BS) {

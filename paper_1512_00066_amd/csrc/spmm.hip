@@ -90,6 +90,17 @@ __global__ void __launch_bounds__(256) spmm_items(const int32_t *__restrict__ ir
         if (MODE == 1 && rin) {
           // only rows that changed in the previous step can lower this one:
           // an unchanged row's term is already part of the row's value
+          for (; p + 4 <= e; p += 4) {
+            const int32_t k0 = cA[p], k1 = cA[p + 1], k2 = cA[p + 2], k3 = cA[p + 3];
+            const bool u0 = rin[k0], u1 = rin[k1], u2 = rin[k2], u3 = rin[k3];
+            const V a0 = vA[p], a1 = vA[p + 1], a2 = vA[p + 2], a3 = vA[p + 3];
+            const V x0 = u0 ? X[(int64_t)k0 * s + col] : id, x1 = u1 ? X[(int64_t)k1 * s + col] : id;
+            const V x2 = u2 ? X[(int64_t)k2 * s + col] : id, x3 = u3 ? X[(int64_t)k3 * s + col] : id;
+            if (!SR::absent(a0, id) && !SR::absent(x0, id)) acc = SR::add(acc, SR::mul(a0, x0));
+            if (!SR::absent(a1, id) && !SR::absent(x1, id)) acc = SR::add(acc, SR::mul(a1, x1));
+            if (!SR::absent(a2, id) && !SR::absent(x2, id)) acc = SR::add(acc, SR::mul(a2, x2));
+            if (!SR::absent(a3, id) && !SR::absent(x3, id)) acc = SR::add(acc, SR::mul(a3, x3));
+          }
           for (; p < e; p++) {
             const int32_t k = cA[p];
             if (!rin[k]) continue;
