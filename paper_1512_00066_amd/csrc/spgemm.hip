@@ -474,7 +474,20 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
         }
       }
       const int P = cnt <= 1 ? 1 : 1 << (32 - __clz(cnt - 1));  // next power of two >= cnt
-      for (int s = cnt + threadIdx.x; s < P; s += BS) keys[s] = EMPTY;
+      // With column < 2^(32 - PB) for PB = log2(P) position bits, a kept
+      // entry's column and compacted position pack into one 32-bit word;
+      // sorting the words moves a third of the bytes of sorting (key,
+      // value) pairs, and the values are read from their slots afterwards.
+      const int PB = 31 - __clz(max(P, 2));
+      const bool packed = SR::HAS_VALS && ncols <= ((int64_t)1 << (32 - PB));
+      if (packed) {
+        __syncthreads();  // the compacted entries come from other threads
+        uint32_t *w32 = reinterpret_cast<uint32_t *>(keys);
+        for (int s = threadIdx.x; s < P; s += BS)
+          w32[s] = s < cnt ? ((uint32_t)keys[s] << PB) | (uint32_t)s : 0xffffffffu;
+      } else {
+        for (int s = cnt + threadIdx.x; s < P; s += BS) keys[s] = EMPTY;
+      }
       __syncthreads();
       // While the stride is at most 64, the pairs of the 64 consecutive q
       // of one wave stay inside one 128-entry block that no other wave
@@ -486,14 +499,23 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
             const int lo = q + (q & ~(jst - 1));  // jst is a power of two
             const int hi = lo + jst;
             const bool up = (lo & k) == 0;
-            const int32_t ka = keys[lo], kb = keys[hi];
-            if ((ka > kb) == up) {
-              keys[lo] = kb;
-              keys[hi] = ka;
-              if (SR::HAS_VALS) {
-                const A t = vals[lo];
-                vals[lo] = vals[hi];
-                vals[hi] = t;
+            if (packed) {
+              uint32_t *w32 = reinterpret_cast<uint32_t *>(keys);
+              const uint32_t ka = w32[lo], kb = w32[hi];
+              if ((ka > kb) == up) {
+                w32[lo] = kb;
+                w32[hi] = ka;
+              }
+            } else {
+              const int32_t ka = keys[lo], kb = keys[hi];
+              if ((ka > kb) == up) {
+                keys[lo] = kb;
+                keys[hi] = ka;
+                if (SR::HAS_VALS) {
+                  const A t = vals[lo];
+                  vals[lo] = vals[hi];
+                  vals[hi] = t;
+                }
               }
             }
           }
@@ -507,9 +529,19 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
           }
         }
       }
-      for (int s = threadIdx.x; s < cnt; s += BS) {
-        cC[base + s] = keys[s];
-        vC[base + s] = SR::out(SR::HAS_VALS ? vals[s] : (A)1);
+      if (packed) {
+        const uint32_t *w32 = reinterpret_cast<const uint32_t *>(keys);
+        const uint32_t pmask = (1u << PB) - 1u;
+        for (int s = threadIdx.x; s < cnt; s += BS) {
+          const uint32_t wv = w32[s];
+          cC[base + s] = (int32_t)(wv >> PB);
+          vC[base + s] = SR::out(vals[wv & pmask]);
+        }
+      } else {
+        for (int s = threadIdx.x; s < cnt; s += BS) {
+          cC[base + s] = keys[s];
+          vC[base + s] = SR::out(SR::HAS_VALS ? vals[s] : (A)1);
+        }
       }
       written = cnt;
     }
