@@ -534,6 +534,76 @@ def run_selector(args):
     return out
 
 
+def run_masked18(args):
+    """Masked contraction on R-MAT 18 (edge factor 16, fp64 values): C = A (.)
+    (A.A) over A's own pattern (the shape of triangle counting); every
+    product is formed and tested against the mask row.  A step = fold + the
+    masked contraction."""
+    import torch
+    import oracle
+    import paper_1512_00066_amd as srtc
+    from gen import synth
+
+    ctx = srtc.Context(0)
+    inp = rmat18_inputs(synth)
+    n = inp["n"]
+    coo = srtc.COO(torch.as_tensor(inp["dst"].astype(np.int64) * n + inp["src"], device="cuda"),
+                   torch.as_tensor(inp["v64"], device="cuda"), (n, n))
+    A0 = ctx.fold("plus_times", coo, "ij", "i", "j")
+    rn = torch.diff(A0.rowptr)
+    products = int(rn[A0.col.long()].sum().item())
+
+    def step():
+        A = ctx.fold("plus_times", coo, "ij", "i", "j")
+        C = ctx.contract_masked("plus_times", "ik", A, "kj", A, "ij", A)
+        return C.nnz
+
+    for _ in range(args.warmup):
+        nz = step()
+    torch.cuda.synchronize()
+    srtc.lib().srtc_profile_enable(ctx._h, 1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nz = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = profile_table(ctx)
+    srtc.lib().srtc_profile_enable(ctx._h, 0)
+    ms = (t1 - t0) * 1e3 / args.steps
+    nm, cnt, tms, by = max(prof, key=lambda r: r[2])
+    achieved = (by / cnt) / (tms / cnt / 1e3) / 1e9
+    log(f"masked: products {products}, nnz(C) {nz}, {ms:.2f} ms/step")
+    out = {"metric": METRIC, "value": products / (ms / 1e3), "unit": "semiring-ops/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "rmat18_masked_A_dot_AxA_f64", "rmat_scale": 18, "edge_factor": 16,
+                      "products": products, "nnz_C": nz, "mask_nnz": A0.nnz},
+           "roofline": {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(tms / cnt, 4), "algorithmic_bytes_per_launch": round(by / cnt)}}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        O = oracle.fold("plus_times", "f64", inp["dst"], inp["src"], inp["v64"], n, n)
+        rno = np.diff(O.rowptr)
+        w = np.zeros(n, dtype=np.int64)
+        np.add.at(w, np.repeat(np.arange(n), rno), rno[O.col])
+        perm = synth.permutation(synth.stream_key(synth.SEED_CFG1, 78), n)
+        k, t_o, ops_o = 1024, 0.0, 0.0
+        while t_o < args.cpu_seconds / 2 and k <= n:
+            rows = np.sort(perm[:k])
+            Asub = oracle.CSR(np.concatenate([[0], np.cumsum(rno[rows])]),
+                              np.concatenate([O.col[O.rowptr[r]:O.rowptr[r + 1]] for r in rows]),
+                              np.concatenate([O.val[O.rowptr[r]:O.rowptr[r + 1]] for r in rows]), k, n)
+            t2 = time.perf_counter()
+            oracle.spgemm_masked("plus_times", "f64", Asub, O, Asub)
+            t_o = time.perf_counter() - t2
+            ops_o = float(w[rows].sum())
+            k *= 2
+        out["cpu_baseline"] = {"value": ops_o / t_o, "unit": "semiring-ops/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{k // 2} random rows ({int(ops_o)} products); {t_o:.1f} s"}
+    return out
+
+
 def copy_calibration(args):
     """A plain device copy of known size (1 GiB read, 1 GiB written per
     launch), run under the same HBM counters as the kernels, to scale
@@ -554,7 +624,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512", "selector"])
+    ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512", "selector", "masked18"])
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
     ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -575,7 +645,7 @@ def main():
         copy_calibration(args)
         return
     out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512,
-           "selector": run_selector}[args.workload](args)
+           "selector": run_selector, "masked18": run_masked18}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

@@ -197,6 +197,21 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
                           const srtc_tensor *B, const char *ic, srtc_tensor *C,
                           const srtc_opts *opts, void *stream);
 
+/* Contraction into a given output pattern (the output with predefined
+ * sparsity that Sections 1 and 7 name as an extension):
+ *   C[ic] = M (.) (A[ia] (x) B[ib])
+ * Only positions present in the mask M (same index string and extents as C;
+ * COO or CSR; its values are ignored, duplicates merge) are formed; every
+ * product landing elsewhere is dropped.  A and B are sparse (COO or CSR);
+ * no index may appear in all of A, B and C.  C (host descriptor, device
+ * buffers from the allocator) receives a CSR over C's row letters whose
+ * pattern is a subset of M's: positions with no product, or whose result is
+ * the additive identity, are absent; rows list columns in ascending order.
+ * opts: only `validate` is used (checks A, B and M).  One host sync. */
+srtc_status srtc_contract_masked(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const char *ia,
+                                 const srtc_tensor *A, const char *ib, const srtc_tensor *B, const char *ic,
+                                 const srtc_tensor *M, srtc_tensor *C, const srtc_opts *opts, void *stream);
+
 /* ----------------------------------------------------------- fixpoint -- */
 
 /* Bellman-Ford as repeated semiring products (Section 4.2):

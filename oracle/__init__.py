@@ -223,6 +223,22 @@ def dense_plus_times(A, B):
     return np.asarray(A, dtype=np.float64) @ np.asarray(B, dtype=np.float64)
 
 
+def spgemm_masked(semiring, dtype, A: CSR, B: CSR, M: CSR, add_id=None) -> CSR:
+    """C = M (.) (A (x) B): the entries of the product whose position is in
+    M's pattern (an output with predefined sparsity, Sections 1 and 7);
+    M's values are ignored.  The full product by its definition, then the
+    positions outside M removed."""
+    if M.nrows != A.nrows or M.ncols != B.ncols:
+        raise ValueError("mask shape")
+    C = spgemm(semiring, dtype, A, B, add_id=add_id)
+    crow = np.repeat(np.arange(C.nrows, dtype=np.int64), np.diff(C.rowptr))
+    mrow = np.repeat(np.arange(M.nrows, dtype=np.int64), np.diff(M.rowptr))
+    keep = np.isin(crow * C.ncols + C.col.astype(np.int64), mrow * M.ncols + M.col.astype(np.int64))
+    rp = np.zeros(C.nrows + 1, dtype=np.int64)
+    np.cumsum(np.bincount(crow[keep], minlength=C.nrows), out=rp[1:])
+    return CSR(rp, C.col[keep], C.val[keep], C.nrows, C.ncols)
+
+
 def spmm(semiring, dtype, A: CSR, X, add_id=None, self_term=False):
     """Y = [X (+)] A (x) X for dense row-major X (n x s).  Returns (Y, changed).
     (+,x) gives fp64; other semirings keep the stored type."""

@@ -97,6 +97,7 @@ def lib():
                               ctypes.c_int),
             "srtc_fixpoint": ([P, ctypes.c_int, P, T, T, I64_, I32_, ctypes.POINTER(I64_), P], ctypes.c_int),
             "srtc_fixpoint_ex": ([P, ctypes.c_int, P, T, T, I64_, I32_, I32_, ctypes.POINTER(I64_), P], ctypes.c_int),
+            "srtc_contract_masked": ([P, ctypes.c_int, P, S, T, S, T, S, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
             "srtc_bfs_levels": ([P, T, ctypes.POINTER(I64_), I32_, P, ctypes.POINTER(I32_), P], ctypes.c_int),
             "srtc_batch_contract": ([P, ctypes.c_int, P, I32_, T, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
             "srtc_batch_fixpoint": ([P, ctypes.c_int, P, I32_, T, T, I64_, I32_, ctypes.POINTER(I64_), P],
@@ -329,6 +330,25 @@ class Context:
         if C is None or isinstance(C, CSR):
             return self._csr_out(cd)
         return C
+
+    def contract_masked(self, semiring, ia: str, A, ib: str, B, ic: str, M, add_id=None,
+                        validate: bool = False) -> "CSR":
+        """C[ic] = M (.) (A[ia] (x) B[ib]): only positions in M's pattern
+        (M sparse, indexed like C; its values are ignored)."""
+        ad, bd, md = _desc(A), _desc(B), _desc(M)
+        opts = _Opts(-1, 1, 1 if validate else 0, 0)
+        cd = _Tensor()
+        cd.order = len(ic)
+        cd.format = CSR_FMT
+        cd.dtype = ad.dtype
+        mdims = M.dims if not isinstance(M, torch.Tensor) else tuple(M.shape)
+        for i in range(len(ic)):
+            cd.dims[i] = int(mdims[i])
+        st = lib().srtc_contract_masked(self._h, _sr(semiring), _add_id(add_id, ad.dtype), ia.encode(),
+                                        ctypes.byref(ad), ib.encode(), ctypes.byref(bd), ic.encode(),
+                                        ctypes.byref(md), ctypes.byref(cd), ctypes.byref(opts), self._stream())
+        self._check(st)
+        return self._csr_out(cd)
 
     def fixpoint(self, semiring, A: CSR, X: torch.Tensor, max_iters: int = 0, steps_per_check: int = 4,
                  add_id=None, changed_rows_only: bool = False) -> int:

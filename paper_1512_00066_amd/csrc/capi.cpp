@@ -647,6 +647,59 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
   });
 }
 
+srtc_status srtc_contract_masked(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const char *ia,
+                                 const srtc_tensor *A, const char *ib, const srtc_tensor *B, const char *ic,
+                                 const srtc_tensor *M, srtc_tensor *C, const srtc_opts *opts, void *stream) {
+  return guard(ctx, [&] {
+    check_tensor(A, "A");
+    check_tensor(B, "B");
+    check_tensor(M, "M");
+    if (!C) fail(SRTC_ERR_ARG, "C: null");
+    if (C->order < 0 || C->order > SRTC_MAX_ORDER) fail(SRTC_ERR_ARG, "C: bad order");
+    if (A->format == SRTC_DENSE || B->format == SRTC_DENSE || M->format == SRTC_DENSE)
+      fail(SRTC_ERR_UNSUPPORTED, "masked contraction: A, B and the mask must be sparse");
+    const std::string a = letters(ia, A, "A"), b = letters(ib, B, "B"), cidx = letters(ic, C, "C");
+    const std::string midx = letters(ic, M, "M");
+    if (A->dtype != B->dtype) fail(SRTC_ERR_DTYPE, "A and B value types differ");
+    const int dt = A->dtype;
+    const IdVal id = make_id(sr, dt, add_id);
+    const Plan p = plan_contraction(a, A, b, B, cidx, C);
+    if (!p.batch.empty()) fail(SRTC_ERR_UNSUPPORTED, "masked contraction: no index may appear in A, B and C");
+    for (size_t q = 0; q < cidx.size(); q++)
+      if (M->dims[q] != p.dim.at(cidx[q])) fail(SRTC_ERR_DIM, "M: extents differ from C's");
+    srtc_opts o{-1, 1, 0, 0};
+    if (opts) o = *opts;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    Ctx *c = &ctx->c;
+    if (o.validate) {
+      validate_operand(c, sr, A, "A", s);
+      validate_operand(c, sr, B, "B", s);
+      validate_operand(c, SRTC_OR_AND, M, "M", s);
+    }
+    const std::string crow = rows_of_c(cidx, p);
+    const std::string acol = p.K, brow = p.K, bcol = p.N;
+    Folded fa, fb, fm;
+    fold_sparse(c, sr, id, A, a, crow, acol, &fa, s);
+    fold_sparse(c, sr, id, B, b, brow, bcol, &fb, s);
+    // the mask's values are ignored: fold it as a pattern (duplicates merge)
+    srtc_tensor mp = *M;
+    const IdVal mid = make_id(SRTC_OR_AND, SRTC_BOOL8, nullptr);
+    Buf ones(c, (size_t)std::max<int64_t>(M->nnz, 1));
+    fill_bytes_value(ones.p, std::max<int64_t>(M->nnz, 1), SRTC_BOOL8, IdVal{1.0, 1}, s);
+    mp.vals = ones.p;
+    mp.dtype = SRTC_BOOL8;
+    fold_sparse(c, SRTC_OR_AND, mid, &mp, midx, crow, bcol, &fm, s);
+    c->tracef("srtc_contract_masked %s,%s->%s semiring %d dtype %d, mask nnz %lld", a.c_str(), b.c_str(),
+              cidx.c_str(), (int)sr, dt, (long long)fm.view.nnz);
+    CsrOut t;
+    spgemm_masked(c, sr, dt, id, fa.view, fb.view, fm.view, &t, s);
+    int64_t dims[SRTC_MAX_ORDER];
+    for (size_t q = 0; q < cidx.size(); q++) dims[q] = p.dim.at(cidx[q]);
+    set_csr_out(C, t, (int)cidx.size(), dims, (int)crow.size(), dt);
+  });
+}
+
 srtc_status srtc_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const srtc_tensor *A, srtc_tensor *X,
                           int64_t max_iters, int32_t steps_per_check, int64_t *iters_out, void *stream) {
   return srtc_fixpoint_ex(ctx, sr, add_id, A, X, max_iters, steps_per_check, 0, iters_out, stream);

@@ -142,6 +142,9 @@ struct SpgemmStats {
 // the context.  Synchronizes once.
 void spgemm(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B, int sched,
             int sorted, CsrOut *out, SpgemmStats *st, hipStream_t s);
+// C = M (.) (A (x) B) over M's pattern (sorted rows; identity results dropped).
+void spgemm_masked(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B, const CsrView &M,
+                   CsrOut *out, hipStream_t s);
 // Row product counts w_i (int64, m entries).
 void row_products(const CsrView &A, const CsrView &B, int64_t *w, hipStream_t s);
 // C = X (+) Y for two CSR matrices of the same shape (sorted rows); the

@@ -738,6 +738,100 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
   }
 }
 
+// --------------------------------------------------------------- masked --
+// C = M (.) (A (x) B): only positions in M's pattern are formed (an output
+// with predefined sparsity, Sections 1 and 7).  A block takes a row; the
+// mask row's sorted columns are staged in LDS LM at a time with their
+// accumulators beside them, every product of the row finds its column by
+// binary search among them (products outside the mask are dropped), and the
+// kept entries are written in mask order into the row's mask-aligned
+// segment; kept[i] counts them for the final compaction.
+template <class SR, int BS>
+__device__ __forceinline__ int64_t write_kept(const typename SR::acc_t *vals, const int32_t *keys, int n,
+                                              typename SR::acc_t id, int64_t pos0, int32_t *__restrict__ cC,
+                                              typename SR::val_t *__restrict__ vC, int64_t *red) {
+  constexpr int NW = BS / WAVE;
+  const int wv = threadIdx.x / WAVE, l = lane_id();
+  const int span = ((n + NW * WAVE - 1) / (NW * WAVE)) * WAVE;  // slots per wave, whole waves
+  const int b0 = wv * span, b1 = min(b0 + span, n);
+  int64_t cnt = 0;
+  for (int g = b0; g < b0 + span; g += WAVE) {
+    const int q = g + l;
+    cnt += __popcll(__ballot(q < b1 && !SR::acc_absent(vals[q], id)));
+  }
+  if (l == 0) red[wv] = cnt;
+  __syncthreads();
+  int64_t before = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < NW; q++) {
+    const int64_t x = red[q];
+    if (q < wv) before += x;
+    tot += x;
+  }
+  int64_t pos = pos0 + before;
+  const uint64_t lt = lanemask_lt();
+  for (int g = b0; g < b0 + span; g += WAVE) {
+    const int q = g + l;
+    const typename SR::acc_t v = q < b1 ? vals[q] : id;
+    const bool keep = q < b1 && !SR::acc_absent(v, id);
+    const uint64_t mk = __ballot(keep);
+    if (keep) {
+      const int64_t o = pos + __popcll(mk & lt);
+      cC[o] = keys[q];
+      vC[o] = SR::out(v);
+    }
+    pos += __popcll(mk);
+  }
+  __syncthreads();
+  return tot;
+}
+
+template <class SR, int BS, int LM>
+__global__ void __launch_bounds__(BS) masked_rows(const int64_t *__restrict__ rpA, const int32_t *__restrict__ cA,
+                                                  const typename SR::val_t *__restrict__ vA,
+                                                  const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB,
+                                                  const typename SR::val_t *__restrict__ vB,
+                                                  const int64_t *__restrict__ rpM, const int32_t *__restrict__ cM,
+                                                  int64_t m, int32_t *__restrict__ cC,
+                                                  typename SR::val_t *__restrict__ vC, typename SR::acc_t id,
+                                                  int64_t *__restrict__ kept) {
+  using V = typename SR::val_t;
+  using A = typename SR::acc_t;
+  __shared__ int32_t keys[LM];
+  __shared__ A vals[LM];
+  __shared__ Chunk<BS, V> L;
+  __shared__ int64_t red[BS / WAVE + 1];
+  const int t = threadIdx.x;
+  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const int64_t m0 = rpM[i], m1 = rpM[i + 1];
+    int64_t written = 0;
+    if (m1 > m0 && rpA[i + 1] > rpA[i]) {
+      for (int64_t s0 = m0; s0 < m1; s0 += LM) {
+        const int n = (int)min((int64_t)LM, m1 - s0);
+        for (int q = t; q < n; q += BS) {
+          keys[q] = cM[s0 + q];
+          vals[q] = id;
+        }
+        __syncthreads();
+        const int32_t c_lo = keys[0], c_hi = keys[n - 1];
+        for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nullptr, 0, 0, L, [&](int32_t j, V a, V b) {
+          if (SR::HAS_VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
+          if (j < c_lo || j > c_hi) return;
+          int lo = 0, hi = n - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (keys[mid] < j) lo = mid + 1; else hi = mid;
+          }
+          if (keys[lo] != j) return;
+          SR::lds_add(&vals[lo], SR::HAS_VALS ? SR::mul(a, b) : (A)1);
+        });
+        written += write_kept<SR, BS>(vals, keys, n, id, m0 + written, cC, vC, red);
+      }
+    }
+    if (t == 0) kept[i] = written;
+  }
+}
+
 // Window table: woff[k*(nwin+1) + w] = first position in B_k with column
 // >= w*W (relative to rowptr[k]); woff[k*(nwin+1)+nwin] = nnz(B_k).
 __global__ void build_woff(const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB, int64_t nrows,
@@ -1137,6 +1231,60 @@ void row_products(const CsrView &A, const CsrView &B, int64_t *w, hipStream_t s)
   if (A.m == 0) return;
   row_products_kernel<<<gridn(A.m * WAVE, 256, 16384), 256, 0, s>>>(A.rowptr, A.col, B.rowptr, A.m, w);
   SRTC_LAUNCH_CHECK("row_products");
+}
+
+template <class SR>
+void masked_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, const CsrView &Mm, CsrOut *out,
+                  hipStream_t s) {
+  using V = typename SR::val_t;
+  using A = typename SR::acc_t;
+  const A id = id_as<SR>(idv);
+  const int64_t m = Am.m;
+  const size_t es = sizeof(V);
+  out->m = m;
+  out->n = Bm.n;
+  if (m == 0 || Am.nnz == 0 || Bm.nnz == 0 || Mm.nnz == 0) {
+    out->rowptr = Buf(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
+    fill_i64(out->rowptr.as<int64_t>(), m + 1, 0, s);
+    out->nnz = 0;
+    out->col = Buf(c, 4, out->kind);
+    out->val = Buf(c, es, out->kind);
+    return;
+  }
+  constexpr int BS = 256, LM = 4096;
+  Buf colM(c, sizeof(int32_t) * (size_t)Mm.nnz), valM(c, es * (size_t)Mm.nnz);
+  Buf kept(c, sizeof(int64_t) * (size_t)m);
+  {
+    ProfScope ps(c, "spgemm.masked", 16.0 * (m + 1) + 12.0 * Am.nnz + (4.0 + es) * Bm.nnz + 4.0 * Mm.nnz +
+                 (4.0 + es) * Mm.nnz, s);
+    const int stat = LM * (4 + (int)sizeof(A)) + (int)sizeof(Chunk<BS, V>) + 64;
+    Launch L{c, s};
+    masked_rows<SR, BS, LM><<<L.grid(m, stat, BS), BS, 0, s>>>(Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr,
+                                                                Bm.col, (const V *)Bm.val, Mm.rowptr, Mm.col, m,
+                                                                colM.as<int32_t>(), valM.as<V>(), id,
+                                                                kept.as<int64_t>());
+    SRTC_LAUNCH_CHECK("masked_rows");
+  }
+  out->rowptr = Buf(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
+  excl_scan_i64(c, kept.as<int64_t>(), out->rowptr.as<int64_t>(), m, s);
+  const int64_t total = read_i64(c, out->rowptr.as<int64_t>() + m, s);
+  out->col = Buf(c, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), out->kind);
+  out->val = Buf(c, es * (size_t)std::max<int64_t>(total, 1), out->kind);
+  out->nnz = total;
+  if (total > 0) {
+    compact_rows<V><<<gridn(m * WAVE, 256, 16384), 256, 0, s>>>(Mm.rowptr, out->rowptr.as<int64_t>(), m,
+                                                                colM.as<int32_t>(), valM.as<V>(),
+                                                                out->col.as<int32_t>(), out->val.as<V>());
+    SRTC_LAUNCH_CHECK("compact_rows");
+  }
+}
+
+void spgemm_masked(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B, const CsrView &M,
+                   CsrOut *out, hipStream_t s) {
+  if (A.n != B.m) fail(SRTC_ERR_DIM, "masked spgemm: inner dimensions differ");
+  if (M.m != A.m || M.n != B.n) fail(SRTC_ERR_DIM, "masked spgemm: mask shape differs from C");
+  if (B.n >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "masked spgemm: more than 2^31-2 columns");
+  SRTC_DISPATCH_SR(sr, dt, masked_typed, c, id, A, B, M, out, s);
 }
 
 void spgemm(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B, int sched, int sorted,

@@ -497,3 +497,40 @@ def test_validate_rejects_malformed_operands(ctx):
     with pytest.raises(srtc.SrtcError) as e:
         ctx.contract("min_plus", "ik", fnan, "kj", fgood, "ij", validate=True)
     assert e.value.status == -5
+
+
+# ----------------------------------------------------------------- masked --
+@pytest.mark.parametrize("semiring,dtype", PAIRS)
+def test_masked_contraction(ctx, semiring, dtype):
+    say("masked", semiring, dtype)
+    for case, dens in (("er500", 0.02), ("rmat11", 0.01), ("rmat11", 0.2)):
+        (src, dst), n = CASES[case]()
+        G, O = pair_inputs(ctx, semiring, dtype, src, dst, n, 21)
+        mk = synth.bernoulli_keys((n, n), dens, seed=31, tag=len(case))
+        Mo = oracle.fold("or_and", "bool", mk // n, mk % n, np.ones(mk.size, np.uint8), n, n)
+        M = srtc.COO(torch.as_tensor(mk, device="cuda"), torch.ones(mk.size, dtype=torch.uint8, device="cuda"), (n, n))
+        C = ctx.contract_masked(semiring, "ik", G, "kj", G, "ij", M, validate=True)
+        check_csr(C, oracle.spgemm_masked(semiring, dtype, O, O, Mo), semiring, dtype)
+
+
+def test_masked_contraction_edge_cases(ctx):
+    say("masked edge cases")
+    n = 6000
+    src, dst = synth.er_edges(n, 4, seed=41)
+    w = synth.edge_values("i32", src.size, 41, lo=1, hi=100)
+    G = gpu_fold(ctx, "min_plus", "i32", dst, src, w, n, n)
+    O = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+    # rows longer than one LDS chunk, duplicate mask keys, zero mask values
+    long_rows = np.concatenate([r * n + np.arange(n) for r in (0, 5, 4321)])
+    mk = np.concatenate([synth.bernoulli_keys((n, n), 0.002, seed=42), long_rows, long_rows[:100]])
+    mv = np.zeros(mk.size, np.uint8)
+    M = srtc.COO(torch.as_tensor(mk, device="cuda"), torch.as_tensor(mv, device="cuda"), (n, n))
+    Mo = oracle.fold("or_and", "bool", mk // n, mk % n, np.ones(mk.size, np.uint8), n, n)
+    check_csr(ctx.contract_masked("min_plus", "ik", G, "kj", G, "ij", M), oracle.spgemm_masked("min_plus", "i32", O, O, Mo),
+              "min_plus", "i32")
+    # an empty mask gives an empty C; a mask covering the product changes nothing
+    E = srtc.COO(torch.zeros(0, dtype=torch.int64, device="cuda"), torch.zeros(0, dtype=torch.uint8, device="cuda"), (n, n))
+    assert ctx.contract_masked("min_plus", "ik", G, "kj", G, "ij", E).nnz == 0
+    full = ctx.contract("min_plus", "ik", G, "kj", G, "ij")
+    again = ctx.contract_masked("min_plus", "ik", G, "kj", G, "ij", full)
+    assert torch.equal(again.rowptr, full.rowptr) and torch.equal(again.col, full.col) and torch.equal(again.val, full.val)

@@ -400,3 +400,45 @@ def test_dense_plus_times_pins():
     assert np.allclose(oracle.dense_plus_times(a, b), ref, rtol=1e-15, atol=0)
     n = 37
     assert np.array_equal(oracle.dense_plus_times(np.ones((n, n)), np.ones((n, n))), np.full((n, n), float(n)))
+
+
+@pytest.mark.parametrize("semiring,dtype", PAIRS)
+def test_spgemm_masked_pins(semiring, dtype):
+    # brute force with a dense mask; the identity pattern keeps the
+    # diagonal; a mask covering the product changes nothing
+    m, k, n = 23, 19, 21
+    A = rand_matrix(semiring, dtype, m, k, 0.3, 77, 1)
+    B = rand_matrix(semiring, dtype, k, n, 0.3, 77, 7)
+    M = rand_matrix("or_and", "bool", m, n, 0.4, 77, 13)
+    C = oracle.spgemm_masked(semiring, dtype, A, B, M)
+    fill = identity_fill(semiring, dtype)
+    npdt = oracle.NP_DTYPES[dtype]
+    DA, MA = csr_to_dense(A, fill, npdt)
+    DB, MB = csr_to_dense(B, fill, npdt)
+    DC, MC = dense_product(semiring, dtype, DA, MA, DB, MB)
+    _, MM = csr_to_dense(M, 0, np.uint8)
+    want = MC & MM
+    got = np.zeros((m, n), dtype=bool)
+    for i in range(m):
+        c, v = C.row(i)
+        got[i, c] = True
+        if semiring == "plus_times":
+            np.testing.assert_allclose(v, DC[i, c], rtol=1e-14)
+        else:
+            assert np.array_equal(v.astype(np.float64), DC[i, c].astype(np.float64))
+    assert np.array_equal(got, want)
+    sq = rand_matrix(semiring, dtype, 30, 30, 0.2, 78, 1)
+    I = oracle.fold("or_and", "bool", np.arange(30), np.arange(30), np.ones(30, np.uint8), 30, 30)
+    full = oracle.spgemm(semiring, dtype, sq, sq)
+    diag = oracle.spgemm_masked(semiring, dtype, sq, sq, I)
+    for i in range(30):
+        c, v = diag.row(i)
+        fc, fv = full.row(i)
+        assert c.tolist() == ([i] if i in fc.tolist() else [])
+        if c.size:
+            assert v[0] == fv[fc.tolist().index(i)]
+    cover = oracle.fold("or_and", "bool", np.repeat(np.arange(30), 30), np.tile(np.arange(30), 30),
+                        np.ones(900, np.uint8), 30, 30)
+    again = oracle.spgemm_masked(semiring, dtype, sq, sq, cover)
+    assert np.array_equal(again.rowptr, full.rowptr) and np.array_equal(again.col, full.col)
+    assert np.array_equal(again.val, full.val)
