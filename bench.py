@@ -604,6 +604,77 @@ def run_masked18(args):
     return out
 
 
+def run_apsp2048(args):
+    """All-pairs shortest paths by Tiskin's path doubling on the paper's APSP
+    workload: a complete directed graph on n = 2,048 vertices with integer
+    weights uniform in [1, n^2].  A step = fold of the edge list + every
+    round (sparsify the exactly-l-hop paths, P <- P (+) P_l (x) P over packed
+    (weight, hops) paths) + distance/hop extraction.  Ops = path sums formed,
+    sum over rounds of nnz(P_l) * n."""
+    import torch
+    import oracle
+    import paper_1512_00066_amd as srtc
+    from gen import synth
+
+    ctx = srtc.Context(0)
+    n = args.apsp_n
+    src, dst, w = synth.dense_graph(n, synth.SEED_CFG0)
+    coo = srtc.COO(torch.as_tensor(dst * n + src, device="cuda"), torch.as_tensor(w, device="cuda"), (n, n))
+    rn = []
+
+    def step():
+        return ctx.apsp_tiskin(coo, round_nnz=rn)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    srtc.lib().srtc_profile_enable(ctx._h, 1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, H, rounds = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = profile_table(ctx)
+    srtc.lib().srtc_profile_enable(ctx._h, 0)
+    ms = (t1 - t0) * 1e3 / args.steps
+    ops = float(sum(rn)) * n
+    dense_rounds = int(np.ceil(np.log2(n)))
+    sp = [r for r in prof if r[0] == "spmm.product"]
+    _, cnt, tms, _ = sp[0]
+    # each path sum: a 64-bit add and a 64-bit compare-select (5 VALU
+    # instructions per lane) at 64 lanes x 256 CUs x 2.4 GHz
+    alu_peak = 256 * 64 * 2.4e9 / 5 / 1e12
+    achieved = ops * args.steps / (tms / 1e3) / 1e12
+    log(f"apsp n={n}: rounds {rounds}, nnz(P_l) {rn}, max hops {int(H.max())}, {ms:.2f} ms/step, "
+        f"spmm {tms / args.steps:.2f} ms/step over {cnt // args.steps} launches")
+    out = {"metric": METRIC, "value": ops / (ms / 1e3), "unit": "semiring-ops/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64 (i32 weight, u32 hops)", "data": "synthetic",
+           "config": {"workload": f"apsp_tiskin_dense{n}", "n": n, "weights": [1, n * n], "rounds": rounds,
+                      "round_nnz": rn, "path_sums": ops, "dense_doubling_path_sums": float(dense_rounds) * n ** 3,
+                      "work_ratio_vs_dense_doubling": round(ops / (float(dense_rounds) * n ** 3), 4),
+                      "spmm_ms": tms / args.steps},
+           "roofline": {"bound": "alu", "kernel": "spmm.product (packed-path (min,+))",
+                        "achieved": round(achieved, 3), "peak": round(alu_peak, 3), "unit": "T path-sums/s",
+                        "frac": round(achieved / alu_peak, 4), "traffic": None,
+                        "avg_launch_ms": round(tms / cnt, 4), "path_sums_per_launch": round(ops / rounds)}}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        m, t_o, ops_o = 256, 0.0, 0.0
+        while t_o < args.cpu_seconds / 4 and m <= n:
+            s2, d2, w2 = synth.dense_graph(m, synth.SEED_CFG0)
+            O = oracle.fold("min_plus", "i32", d2, s2, w2, m, m)
+            t2 = time.perf_counter()
+            _, _, _, pl = oracle.apsp_tiskin(O)
+            t_o = time.perf_counter() - t2
+            ops_o = float(sum(pl)) * m
+            m *= 2
+        out["cpu_baseline"] = {"value": ops_o / t_o, "unit": "semiring-ops/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"the same recipe at n = {m // 2} "
+                               f"({int(ops_o)} path sums); {t_o:.1f} s"}
+    return out
+
+
 def copy_calibration(args):
     """A plain device copy of known size (1 GiB read, 1 GiB written per
     launch), run under the same HBM counters as the kernels, to scale
@@ -624,7 +695,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512", "selector", "masked18"])
+    ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512", "selector", "masked18",
+                                                               "apsp2048"])
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
     ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -632,6 +704,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--selector-matrices", type=int, default=2000)
     ap.add_argument("--selector-epochs", type=int, default=400)
+    ap.add_argument("--apsp-n", type=int, default=2048, help="apsp2048: vertices of the dense graph")
     ap.add_argument("--changed-rows", action="store_true",
                     help="rmat20_sssp: fixpoint steps gather only from rows changed in the previous step")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -645,7 +718,7 @@ def main():
         copy_calibration(args)
         return
     out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512,
-           "selector": run_selector, "masked18": run_masked18}[args.workload](args)
+           "selector": run_selector, "masked18": run_masked18, "apsp2048": run_apsp2048}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

@@ -26,7 +26,7 @@ __all__ = [
     "GOLDEN", "mix64", "stream_key", "rand_u64", "uniform_f64", "uniform_f32",
     "randint", "permutation", "er_edges", "rmat_edges", "stencil27_edges",
     "powerlaw_edges", "bernoulli_keys", "pick_sources", "edge_values",
-    "er_batch_params", "selector_matrix", "FAMILIES", "SEED_CFG0", "SEED_CFG1", "SEED_CFG2", "SEED_CFG3",
+    "er_batch_params", "selector_matrix", "dense_graph", "FAMILIES", "SEED_CFG0", "SEED_CFG1", "SEED_CFG2", "SEED_CFG3",
     "SEED_CFG4",
 ]
 
@@ -249,6 +249,24 @@ def edge_values(kind: str, m: int, seed: int, tag: int = 0, lo: int = 1, hi: int
     if kind == "bool":
         return np.ones(m, dtype=np.uint8)
     raise ValueError(kind)
+
+
+def dense_graph(n: int, seed: int, lo: int = 1, hi: int = None, tag: int = 0):
+    """Complete directed graph on n vertices (every ordered pair u != v) with
+    integer weights uniform in [lo, hi] (hi defaults to n^2): the dense APSP
+    workload of the paper's path-doubling experiment (Section 6).  Returns
+    int64 (src, dst) in row-major slot order and int32 weights."""
+    if hi is None:
+        hi = max(lo, n * n)
+    if n <= 1:
+        z = np.zeros(0, dtype=np.int64)
+        return z, z.copy(), np.zeros(0, dtype=np.int32)
+    s = np.arange(n * (n - 1), dtype=np.int64)
+    src = s // (n - 1)
+    r = s % (n - 1)
+    dst = r + (r >= src)
+    w = randint(stream_key(seed, 1100 + tag), s.size, lo, hi).astype(np.int32)
+    return src, dst, w
 
 
 def er_batch_params(count: int, seed: int, nmin: float = 1e3, nmax: float = 1e5,

@@ -88,7 +88,13 @@ typedef enum srtc_dtype {
   SRTC_F32 = 1,
   SRTC_I32 = 2,
   SRTC_BOOL8 = 3,  /* uint8 0/1 */
-  SRTC_BITS64 = 4  /* dense boolean frontier: bit s of word v = source s */
+  SRTC_BITS64 = 4, /* dense boolean frontier: bit s of word v = source s */
+  SRTC_PATH64 = 5  /* a path as one uint64: weight (bits 32..63, >= 0) and
+                      hop count (bits 0..31); with MIN_PLUS the additive op
+                      keeps the lighter path, the one with fewer hops on a
+                      tie, and the product adds weights and hops (the
+                      hop-carrying tropical semiring of Section 4.2's path
+                      doubling); identity = weight INT32_MAX/2, 0 hops */
 } srtc_dtype;
 
 typedef enum srtc_format {
@@ -251,6 +257,34 @@ srtc_status srtc_fixpoint_ex(srtc_ctx *ctx, srtc_semiring sr, const void *add_id
  * level.  Synchronizes once per level. */
 srtc_status srtc_bfs_levels(srtc_ctx *ctx, const srtc_tensor *A, const int64_t *sources,
                             int32_t nsrc, int32_t *levels, int32_t *depth_out, void *stream);
+
+/* ---------------------------------------------------------------- apsp -- */
+
+/* All-pairs shortest paths by Tiskin's path doubling (Section 4.2, the
+ * sparsified doubling that forms P <- P (+) P_l (x) P with P_l the paths of
+ * exactly l hops, l = 1, 2, 4, ... < n).  Paths are carried as SRTC_PATH64
+ * values, so among equally light paths the one with fewer hops is kept.
+ *   A        n x n int32 (min,+) matrix, COO or CSR; entry (i, j) is the
+ *            weight of edge j -> i (repeated entries: the lightest counts).
+ *            Weights must be >= 0 (SRTC_ERR_ARG otherwise); entries >= the
+ *            identity are no edge.
+ *   add_id   host int32 identity (NULL: INT32_MAX / 2): no path; every
+ *            shortest-path weight must stay below it.
+ *   D        device n x n int32, row-major: D[i, j] = weight of the lightest
+ *            path j -> i (the closure of A: 0 on the diagonal), the identity
+ *            where there is none.
+ *   H        device n x n int32 or NULL: hops of that path, -1 where there
+ *            is none (0 on the diagonal).
+ *   *rounds_out (host, may be NULL) = products formed; the loop stops early
+ *            once no path of exactly l hops is left.
+ *   round_nnz (host, 64 slots, may be NULL): round_nnz[r] = entries of the
+ *            sparse factor P_l of product r (the product forms
+ *            round_nnz[r] * n path sums); unused slots are 0.
+ * A's structure is always checked (SRTC_ERR_FORMAT on a malformed operand).
+ * Needs 16 n^2 bytes of scratch for the two path matrices and one
+ * device-to-host read per round. */
+srtc_status srtc_apsp_tiskin(srtc_ctx *ctx, const void *add_id, const srtc_tensor *A, int32_t *D, int32_t *H,
+                             int32_t *rounds_out, int64_t *round_nnz, void *stream);
 
 /* -------------------------------------------------------------- batch -- */
 

@@ -78,8 +78,9 @@ def lib():
         L.orc_bfs.argtypes = [I64, P, P, P, I64, P]
         L.orc_dijkstra.argtypes = [I64, P, P, P, P, I64, I64, P]
         L.orc_floyd_warshall.argtypes = [I64, P, I64]
+        L.orc_apsp_tiskin.argtypes = [I64, P, P, P, I64, P, P, P, P]
         for f in ("orc_fold", "orc_spgemm_rows", "orc_spmm", "orc_bellman_ford", "orc_bfs",
-                  "orc_dijkstra", "orc_floyd_warshall"):
+                  "orc_dijkstra", "orc_floyd_warshall", "orc_apsp_tiskin"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -296,3 +297,55 @@ def floyd_warshall(D, inf_value=INT_INF):
     D = np.array(D, dtype=np.int64, copy=True, order="C")
     lib().orc_floyd_warshall(D.shape[0], _p(D), int(inf_value))
     return D
+
+
+def apsp_tiskin(A: CSR, inf_value=INT_INF):
+    """Tiskin's path doubling over (weight, hops) paths (Section 4.2): P
+    starts as I (+) A with every edge a 1-hop path; round l = 1, 2, 4, ...
+    (l < n) forms P <- P (+) P_l (x) P with P_l the paths of exactly l hops.
+    Equal weights keep the path with fewer hops.  Returns (D, H, rounds,
+    pl_nnz): D[i, j] = weight of the lightest path j -> i (inf_value where
+    none), H = its hops (-1 where none), rounds = rounds whose P_l had
+    entries, pl_nnz = entries of P_l per round of the loop."""
+    n = int(A.nrows)
+    w = np.ascontiguousarray(A.val, dtype=np.int32)
+    rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(A.col, dtype=np.int32)
+    D = np.zeros((n, n), dtype=np.int64)
+    H = np.zeros((n, n), dtype=np.int64)
+    r = np.zeros(1, dtype=np.int32)
+    pl = np.zeros(64, dtype=np.int64)
+    rc = lib().orc_apsp_tiskin(n, _p(rp), _p(col), _p(w), int(inf_value), _p(D), _p(H), _p(r), _p(pl))
+    if rc < 0:
+        raise ValueError("negative edge weight")
+    nr = 0
+    l = 1
+    while l < n:
+        nr += 1
+        l <<= 1
+    return D, H, int(r[0]), pl[:nr].tolist()
+
+
+def path_product(Aw, Ah, Bw, Bh, inf_value=INT_INF):
+    """Dense product over (weight, hops) paths: C[i, j] = the lightest of
+    A[i, k] (x) B[k, j] (weights and hops added), fewer hops on equal
+    weights; operand entries with weight >= inf_value are absent, and so are
+    products that reach it.  Returns (Cw, Ch): inf_value / -1 where none."""
+    Aw = np.asarray(Aw, dtype=np.int64)
+    Ah = np.asarray(Ah, dtype=np.int64)
+    Bw = np.asarray(Bw, dtype=np.int64)
+    Bh = np.asarray(Bh, dtype=np.int64)
+    m, kk = Aw.shape
+    n = Bw.shape[1]
+    Cw = np.full((m, n), inf_value, dtype=np.int64)
+    Ch = np.full((m, n), -1, dtype=np.int64)
+    for k in range(kk):
+        a_ok = Aw[:, k] < inf_value
+        b_ok = Bw[k, :] < inf_value
+        cw = Aw[:, k][:, None] + Bw[k, :][None, :]
+        ch = Ah[:, k][:, None] + Bh[k, :][None, :]
+        ok = a_ok[:, None] & b_ok[None, :] & (cw < inf_value)
+        better = ok & ((cw < Cw) | ((cw == Cw) & (ch < Ch)))
+        Cw = np.where(better, cw, Cw)
+        Ch = np.where(better, ch, Ch)
+    return Cw, Ch

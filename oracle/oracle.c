@@ -559,3 +559,70 @@ int orc_floyd_warshall(int64_t n, int64_t *d, int64_t inf_value) {
     }
   return 0;
 }
+
+/* Tiskin's path doubling for all-pairs shortest paths (Section 4.2).
+ * A path is a (weight, hops) pair; of two paths the lighter is kept, and of
+ * two equally light ones the one with fewer hops.  P starts as the identity
+ * (weight 0, 0 hops on the diagonal) joined with the edges (weight, 1 hop).
+ * Round l, for l = 1, 2, 4, ... while l < n: P_l = the entries of P with
+ * exactly l hops, and P <- P (+) P_l (x) P, where (x) adds weights and hops
+ * and both factors are the P from before the round.  Paths whose weight
+ * reaches inf_value count as no path.  Orientation as A: row i, column j =
+ * path j -> i.
+ * d: n x n weights (inf_value where no path); h: n x n hops (-1 where none);
+ * *rounds = rounds whose P_l had entries; pl_nnz[r] = entries of P_l in
+ * round r (as many slots as rounds of the loop, at most 64).  Returns -1 on
+ * a negative weight. */
+int orc_apsp_tiskin(int64_t n, const int64_t *rowptr, const int32_t *col, const int32_t *w, int64_t inf_value,
+                    int64_t *d, int64_t *h, int32_t *rounds, int64_t *pl_nnz) {
+  const int64_t nn = n * n;
+  for (int64_t e = 0; e < nn; e++) {
+    const int diag = (e / n) == (e % n);
+    d[e] = diag ? 0 : inf_value;
+    h[e] = diag ? 0 : -1;
+  }
+  for (int64_t i = 0; i < n; i++)
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
+      const int64_t x = w[p];
+      if (x < 0) return -1;
+      if (x >= inf_value) continue;
+      const int64_t e = i * n + col[p];
+      if (x < d[e] || (x == d[e] && 1 < h[e])) {
+        d[e] = x;
+        h[e] = 1;
+      }
+    }
+  int64_t *nd = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nn > 0 ? nn : 1));
+  int64_t *nh = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nn > 0 ? nn : 1));
+  int32_t r = 0;
+  for (int64_t l = 1; l < n; l <<= 1) {
+    int64_t cnt = 0;
+    for (int64_t e = 0; e < nn; e++) cnt += (h[e] == l);
+    if (pl_nnz && r < 64) pl_nnz[r] = cnt;
+    memcpy(nd, d, sizeof(int64_t) * (size_t)nn);
+    memcpy(nh, h, sizeof(int64_t) * (size_t)nn);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; i++)
+      for (int64_t k = 0; k < n; k++) {
+        if (h[i * n + k] != l) continue;  /* P_l (i, k) */
+        const int64_t wik = d[i * n + k], hik = h[i * n + k];
+        for (int64_t j = 0; j < n; j++) {
+          if (h[k * n + j] < 0) continue;
+          const int64_t cw = wik + d[k * n + j], ch = hik + h[k * n + j];
+          if (cw >= inf_value) continue;
+          const int64_t e = i * n + j;
+          if (cw < nd[e] || (cw == nd[e] && ch < nh[e])) {
+            nd[e] = cw;
+            nh[e] = ch;
+          }
+        }
+      }
+    memcpy(d, nd, sizeof(int64_t) * (size_t)nn);
+    memcpy(h, nh, sizeof(int64_t) * (size_t)nn);
+    if (cnt > 0) r++;
+  }
+  free(nd);
+  free(nh);
+  *rounds = r;
+  return 0;
+}

@@ -25,14 +25,17 @@ LIB_PATH = os.path.join(_HERE, "libsrtc.so")
 # ------------------------------------------------------------------ enums --
 PLUS_TIMES, MIN_PLUS, OR_AND, MAX_TIMES = 0, 1, 2, 3
 SEMIRINGS = {"plus_times": PLUS_TIMES, "min_plus": MIN_PLUS, "or_and": OR_AND, "max_times": MAX_TIMES}
-F64, F32, I32, BOOL8, BITS64 = 0, 1, 2, 3, 4
+F64, F32, I32, BOOL8, BITS64, PATH64 = 0, 1, 2, 3, 4, 5
 DENSE, COO_FMT, CSR_FMT = 0, 1, 2
 NUM_SCHEDULES = 8
 NUM_FEATURES = 32
 
-_TORCH_TO_DT = {torch.float64: F64, torch.float32: F32, torch.int32: I32, torch.uint8: BOOL8}
-_DT_TO_TORCH = {F64: torch.float64, F32: torch.float32, I32: torch.int32, BOOL8: torch.uint8, BITS64: torch.int64}
-_DT_CTYPE = {F64: ctypes.c_double, F32: ctypes.c_float, I32: ctypes.c_int32, BOOL8: ctypes.c_uint8}
+# int64 values are packed paths (weight << 32 | hops) for the (min,+) semiring
+_TORCH_TO_DT = {torch.float64: F64, torch.float32: F32, torch.int32: I32, torch.uint8: BOOL8, torch.int64: PATH64}
+_DT_TO_TORCH = {F64: torch.float64, F32: torch.float32, I32: torch.int32, BOOL8: torch.uint8, BITS64: torch.int64,
+                PATH64: torch.int64}
+_DT_CTYPE = {F64: ctypes.c_double, F32: ctypes.c_float, I32: ctypes.c_int32, BOOL8: ctypes.c_uint8,
+             PATH64: ctypes.c_uint64}
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "invalid index string", -3: "dimension mismatch",
           -4: "value type not defined for the semiring", -5: "malformed sparse operand",
@@ -99,6 +102,7 @@ def lib():
             "srtc_fixpoint_ex": ([P, ctypes.c_int, P, T, T, I64_, I32_, I32_, ctypes.POINTER(I64_), P], ctypes.c_int),
             "srtc_contract_masked": ([P, ctypes.c_int, P, S, T, S, T, S, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
             "srtc_bfs_levels": ([P, T, ctypes.POINTER(I64_), I32_, P, ctypes.POINTER(I32_), P], ctypes.c_int),
+            "srtc_apsp_tiskin": ([P, P, T, P, P, ctypes.POINTER(I32_), ctypes.POINTER(I64_), P], ctypes.c_int),
             "srtc_batch_contract": ([P, ctypes.c_int, P, I32_, T, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
             "srtc_batch_fixpoint": ([P, ctypes.c_int, P, I32_, T, T, I64_, I32_, ctypes.POINTER(I64_), P],
                                     ctypes.c_int),
@@ -214,6 +218,18 @@ def _add_id(add_id, dtype):
     if add_id is None:
         return None
     return ctypes.byref(_DT_CTYPE[dtype](add_id))
+
+
+def pack_path(weight, hops):
+    """Packed (min,+) path values (int64): weight << 32 | hops."""
+    w = torch.as_tensor(weight).to(torch.int64)
+    h = torch.as_tensor(hops).to(torch.int64)
+    return (w << 32) | h
+
+
+def unpack_path(p: torch.Tensor):
+    """(weight, hops) of packed path values."""
+    return (p >> 32).to(torch.int32), (p & 0xFFFFFFFF).to(torch.int32)
 
 
 def _sr(semiring) -> int:
@@ -374,6 +390,26 @@ class Context:
                                    int(src.size), _ptr(levels), ctypes.byref(depth), self._stream())
         self._check(st)
         return levels, depth.value
+
+    def apsp_tiskin(self, A, add_id=None, hops: bool = True, round_nnz: Optional[list] = None):
+        """All-pairs lightest paths by path doubling: (D, H or None, rounds).
+        A: n x n int32 COO or CSR, entry (i, j) = weight of edge j -> i;
+        D[i, j] = weight of the lightest path j -> i (add_id, default
+        INT32_MAX // 2, where none), H[i, j] = its hop count (-1 where none).
+        round_nnz (a list, optional) receives the sparse factor's entries per
+        product."""
+        ad = _desc(A)
+        n = int(A.dims[0])
+        D = torch.empty((n, n), dtype=torch.int32, device=self.device)
+        H = torch.empty((n, n), dtype=torch.int32, device=self.device) if hops else None
+        r = ctypes.c_int32(0)
+        rn = (ctypes.c_int64 * 64)()
+        st = lib().srtc_apsp_tiskin(self._h, _add_id(add_id, I32), ctypes.byref(ad), _ptr(D), _ptr(H),
+                                    ctypes.byref(r), rn, self._stream())
+        self._check(st)
+        if round_nnz is not None:
+            round_nnz[:] = [int(x) for x in rn[:r.value]]
+        return D, H, r.value
 
     def batch_contract(self, semiring, As: List[CSR], Bs: List[CSR], add_id=None, schedule: int = -1,
                        sorted: bool = True) -> List[CSR]:

@@ -180,7 +180,7 @@ namespace {
 bool semiring_ok(int sr, int dt) {
   switch (sr) {
     case SRTC_PLUS_TIMES: return dt == SRTC_F64 || dt == SRTC_F32;
-    case SRTC_MIN_PLUS: return dt == SRTC_I32 || dt == SRTC_F32;
+    case SRTC_MIN_PLUS: return dt == SRTC_I32 || dt == SRTC_F32 || dt == SRTC_PATH64;
     case SRTC_OR_AND: return dt == SRTC_BOOL8;
     case SRTC_MAX_TIMES: return dt == SRTC_F32 || dt == SRTC_F64;
   }
@@ -203,6 +203,12 @@ IdVal make_id(int sr, int dt, const void *add_id) {
       if (dt == SRTC_I32) {
         v.i = add_id ? *(const int32_t *)add_id : (int32_t)(INT32_MAX / 2);
         if (v.i <= 0) fail(SRTC_ERR_ARG, "(min,+) int identity must be positive");
+      } else if (dt == SRTC_PATH64) {
+        // a packed path: the identity's weight (its hop count must be 0)
+        const uint64_t pv = add_id ? *(const uint64_t *)add_id : (uint64_t)(INT32_MAX / 2) << 32;
+        if ((pv & 0xffffffffull) != 0 || (pv >> 32) == 0 || (pv >> 32) > (uint64_t)(INT32_MAX / 2))
+          fail(SRTC_ERR_ARG, "(min,+) path identity must be (weight in 1..INT32_MAX/2, 0 hops)");
+        v.i = (int64_t)(pv >> 32);
       } else {
         v.f = add_id ? (double)*(const float *)add_id : (double)std::numeric_limits<float>::infinity();
       }
@@ -841,6 +847,28 @@ srtc_status srtc_bfs_levels(srtc_ctx *ctx, const srtc_tensor *A, const int64_t *
       std::swap(cur, nxt);
     }
     if (depth_out) *depth_out = depth;
+  });
+}
+
+srtc_status srtc_apsp_tiskin(srtc_ctx *ctx, const void *add_id, const srtc_tensor *A, int32_t *D, int32_t *H,
+                             int32_t *rounds_out, int64_t *round_nnz, void *stream) {
+  return guard(ctx, [&] {
+    check_tensor(A, "A");
+    if (A->order != 2 || A->format == SRTC_DENSE) fail(SRTC_ERR_FORMAT, "A must be a sparse matrix (COO or CSR)");
+    if (A->dtype != SRTC_I32) fail(SRTC_ERR_DTYPE, "apsp weights must be int32");
+    const IdVal id = make_id(SRTC_MIN_PLUS, SRTC_I32, add_id);
+    const int64_t n = A->dims[0];
+    if (A->dims[1] != n) fail(SRTC_ERR_DIM, "A must be square");
+    if (n > 0 && !D) fail(SRTC_ERR_ARG, "null D");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    Ctx *c = &ctx->c;
+    validate_operand(c, SRTC_MIN_PLUS, A, "A", s);  // O(nnz), small beside the n^2 path matrix
+    Folded fa;
+    fold_sparse(c, SRTC_MIN_PLUS, id, A, "ij", "i", "j", &fa, s);
+    int32_t r = 0;
+    apsp_tiskin(c, fa.view, (int32_t)id.i, D, H, &r, round_nnz, s);
+    if (rounds_out) *rounds_out = r;
   });
 }
 

@@ -199,6 +199,23 @@ struct OrAnd {
   __device__ static val_t out(acc_t v) { return (val_t)(v != 0); }
 };
 
+// (min,+) on paths packed as (weight << 32) | hops: the unsigned minimum is
+// the lexicographic one (lighter path first, fewer hops on a tie) and the
+// product adds weights and hops without a carry between the halves.  A
+// weight at or above the identity's is the absent path.
+struct MinPlusPath {
+  using val_t = uint64_t;
+  using acc_t = uint64_t;
+  static constexpr int SR = SRTC_MIN_PLUS;
+  static constexpr bool HAS_VALS = true;
+  __device__ static acc_t mul(val_t a, val_t b) { return a + b; }
+  __device__ static acc_t add(acc_t a, acc_t b) { return a < b ? a : b; }
+  __device__ static void lds_add(acc_t *p, acc_t v) { atomicMin((unsigned long long *)p, (unsigned long long)v); }
+  __device__ static bool absent(val_t v, acc_t id) { return (v >> 32) >= (id >> 32); }
+  __device__ static bool acc_absent(acc_t v, acc_t id) { return (v >> 32) >= (id >> 32); }
+  __device__ static val_t out(acc_t v) { return v; }
+};
+
 template <class T> struct MaxTimes {
   using val_t = T;
   using acc_t = T;
@@ -226,6 +243,7 @@ template <> inline float id_as<MinPlus<float>>(const IdVal &v) { return (float)v
 template <> inline uint32_t id_as<OrAnd>(const IdVal &) { return 0u; }
 template <> inline float id_as<MaxTimes<float>>(const IdVal &v) { return (float)v.f; }
 template <> inline double id_as<MaxTimes<double>>(const IdVal &v) { return v.f; }
+template <> inline uint64_t id_as<MinPlusPath>(const IdVal &v) { return (uint64_t)v.i << 32; }
 
 // Dispatch a functor template over the (semiring, dtype) pairs.
 #define SRTC_DISPATCH_SR(sr, dt, F, ...)                                                 \
@@ -234,6 +252,7 @@ template <> inline double id_as<MaxTimes<double>>(const IdVal &v) { return v.f; 
     else if ((sr) == SRTC_PLUS_TIMES && (dt) == SRTC_F32) F<::srtc::PlusTimes<float>>(__VA_ARGS__); \
     else if ((sr) == SRTC_MIN_PLUS && (dt) == SRTC_I32) F<::srtc::MinPlus<int32_t>>(__VA_ARGS__); \
     else if ((sr) == SRTC_MIN_PLUS && (dt) == SRTC_F32) F<::srtc::MinPlus<float>>(__VA_ARGS__); \
+    else if ((sr) == SRTC_MIN_PLUS && (dt) == SRTC_PATH64) F<::srtc::MinPlusPath>(__VA_ARGS__); \
     else if ((sr) == SRTC_OR_AND && (dt) == SRTC_BOOL8) F<::srtc::OrAnd>(__VA_ARGS__);      \
     else if ((sr) == SRTC_MAX_TIMES && (dt) == SRTC_F32) F<::srtc::MaxTimes<float>>(__VA_ARGS__); \
     else if ((sr) == SRTC_MAX_TIMES && (dt) == SRTC_F64) F<::srtc::MaxTimes<double>>(__VA_ARGS__); \
@@ -247,6 +266,7 @@ inline size_t dtype_size(int dt) {
     case SRTC_I32: return 4;
     case SRTC_BOOL8: return 1;
     case SRTC_BITS64: return 8;
+    case SRTC_PATH64: return 8;
   }
   fail(SRTC_ERR_DTYPE, "unknown dtype");
 }

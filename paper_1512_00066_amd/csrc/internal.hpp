@@ -164,6 +164,14 @@ void bf_step(int sr, int dt, IdVal id, const CsrView &A, const void *X, void *Y,
 void bfs_step(const CsrView &A, const uint64_t *front, uint64_t *visited, uint64_t *next,
               int32_t *levels, int nsrc, int level, int32_t *changed, hipStream_t s);
 
+// ----------------------------------------------------------------- apsp --
+// Tiskin's path doubling over packed (weight, hops) paths: D = closure of A
+// (dense n x n int32, idw where unreachable), H = hops of the kept path
+// (optional, -1 where unreachable), *rounds = products formed, round_nnz
+// (host, 64 slots, optional) = entries of each round's sparse factor.
+void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, int32_t *rounds, int64_t *round_nnz,
+                 hipStream_t s);
+
 // --------------------------------------------------------------- dense --
 void dense_gemm_plus_times(Ctx *c, int dt, const void *A, const void *B, void *C, int64_t M,
                            int64_t N, int64_t K, int accumulate, hipStream_t s);

@@ -124,6 +124,7 @@ void fill_bytes_value(void *p, int64_t n, int dtype, IdVal v, hipStream_t s) {
     case SRTC_I32: fill_any<int32_t>((int32_t *)p, n, (int32_t)v.i, s); break;
     case SRTC_BOOL8: fill_any<uint8_t>((uint8_t *)p, n, (uint8_t)v.i, s); break;
     case SRTC_BITS64: fill_any<uint64_t>((uint64_t *)p, n, (uint64_t)v.i, s); break;
+    case SRTC_PATH64: fill_any<uint64_t>((uint64_t *)p, n, (uint64_t)v.i << 32, s); break;
     default: fail(SRTC_ERR_DTYPE, "fill: dtype");
   }
 }

@@ -145,3 +145,34 @@ def test_batch512_matches_per_instance_and_oracle():
         exp, it_exp, conv = oracle.bellman_ford("min_plus", "i32", O, X0s[b])
         assert conv and its[b] == it_exp
         assert np.array_equal(Xs[b].cpu().numpy(), exp)
+
+
+def test_apsp_tiskin_dense2048_sampled():
+    """The dense APSP workload (n = 2,048, weights U[1, n^2]) in the bench's
+    call: distance columns of sampled sources against the oracle's Dijkstra;
+    every hop count is one more than the fewest hops of a predecessor on a
+    lightest path (and 0 on the diagonal)."""
+    n = 2048
+    say("apsp dense", n)
+    src, dst, w = synth.dense_graph(n, synth.SEED_CFG0)
+    ctx = srtc.Context(0)
+    coo = srtc.COO(torch.as_tensor(dst * n + src, device="cuda"), torch.as_tensor(w, device="cuda"), (n, n))
+    rn = []
+    D, H, rounds = ctx.apsp_tiskin(coo, round_nnz=rn)
+    D = D.cpu().numpy().astype(np.int64)
+    H = H.cpu().numpy().astype(np.int64)
+    say("rounds", rounds, rn)
+    O = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+    cols = synth.permutation(synth.stream_key(synth.SEED_CFG0, 77), n)[:8]
+    ref = oracle.dijkstra(O, cols)
+    assert np.array_equal(D[:, cols], ref)
+    W = np.full((n, n), np.iinfo(np.int64).max // 4, np.int64)
+    W[dst, src] = w
+    for j in cols:
+        cand = W + D[:, j][None, :]              # cand[i, k] = A[i, k] + D[k, j]
+        on = cand == D[:, j][:, None]
+        hk = np.where(on, H[:, j][None, :], np.iinfo(np.int64).max)
+        exp = 1 + hk.min(axis=1)
+        exp[j] = 0
+        assert np.array_equal(H[:, j], exp)
+    assert rounds == len(rn) and rn[0] == n * (n - 1) and 1 << (rounds - 1) <= H.max() <= 1 << rounds

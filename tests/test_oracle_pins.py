@@ -442,3 +442,134 @@ def test_spgemm_masked_pins(semiring, dtype):
     again = oracle.spgemm_masked(semiring, dtype, sq, sq, cover)
     assert np.array_equal(again.rowptr, full.rowptr) and np.array_equal(again.col, full.col)
     assert np.array_equal(again.val, full.val)
+
+
+# ------------------------------------------------- Tiskin path doubling --
+
+def hop_layered_distances(A, n, inf=INT_INF):
+    """Lightest path weights with at most h hops for h = 0 .. n-1 (textbook
+    hop-bounded Bellman-Ford on a dense matrix; orientation as A)."""
+    W = np.full((n, n), np.inf)
+    for i in range(n):
+        c, v = A.row(i)
+        W[i, c] = np.minimum(W[i, c], v.astype(np.float64))
+    Dh = np.full((n, n), np.inf)
+    np.fill_diagonal(Dh, 0.0)
+    layers = [Dh]
+    for _ in range(1, max(n, 1)):
+        Dh = np.minimum(Dh, (W[:, :, None] + Dh[None, :, :]).min(axis=1))
+        layers.append(Dh)
+    return layers
+
+
+def min_hops_from_layers(layers, D):
+    """H[i, j] = fewest hops of a lightest path = first layer reaching D."""
+    n = D.shape[0]
+    H = np.full((n, n), -1, dtype=np.int64)
+    for h, L in enumerate(layers):
+        hit = (H < 0) & np.isfinite(L) & (L == D)
+        H[hit] = h
+    return H
+
+
+@pytest.mark.parametrize("n,d,lo,hi,seed", [(2, 1, 0, 5, 1), (17, 3, 0, 4, 2), (40, 4, 0, 3, 3), (64, 8, 1, 100, 4),
+                                            (33, 0.5, 1, 9, 5)])
+def test_tiskin_matches_scipy_and_fewest_hops(n, d, lo, hi, seed):
+    src, dst = synth.er_edges(n, d, seed)
+    w = synth.edge_values("i32", src.size, seed, lo=lo, hi=hi)
+    A = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+    D, H, rounds, pl = oracle.apsp_tiskin(A)
+    G = sp.csr_matrix((A.val.astype(np.float64), A.col, A.rowptr), shape=(n, n)).T
+    ref = csg.floyd_warshall(G, directed=True).T
+    fin = np.isfinite(ref)
+    assert np.array_equal(D[fin], ref[fin].astype(np.int64)) and np.all(D[~fin] == INT_INF)
+    layers = hop_layered_distances(A, n)
+    assert np.array_equal(np.where(fin, ref, np.inf), layers[-1])
+    assert np.array_equal(H, min_hops_from_layers(layers, np.where(fin, ref, np.inf)))
+    # rounds with entries are a prefix of the loop, and the last one
+    # reaches the largest hop count
+    assert all(x > 0 for x in pl[:rounds]) and all(x == 0 for x in pl[rounds:])
+    if H.max() > 0:
+        assert 1 << (rounds - 1) <= H.max() <= 1 << rounds
+
+
+def test_tiskin_path_graph_closed_form():
+    n = 37
+    w = synth.randint(synth.stream_key(11, 1), n - 1, 1, 50).astype(np.int32)
+    A = path_graph(n, w)
+    D, H, rounds, pl = oracle.apsp_tiskin(A)
+    cs = np.concatenate([[0], np.cumsum(w)])
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    assert np.array_equal(D, np.where(i >= j, cs[i] - cs[np.minimum(i, j)], INT_INF))
+    assert np.array_equal(H, np.where(i >= j, i - j, -1))
+    # round l keeps the n - l pairs exactly l hops apart
+    assert pl == [n - (1 << r) for r in range(6)] and rounds == 6
+
+
+def test_tiskin_ties_keep_fewer_hops_and_diagonal():
+    # 0 -> 1 (5), 0 -> 2 (5), 2 -> 1 (0), 1 -> 3 (0), 3 -> 1 (0), 2 -> 2 (3),
+    # 3 -> 0 (7); entry (i, j) = edge j -> i
+    edges = [(0, 1, 5), (0, 2, 5), (2, 1, 0), (1, 3, 0), (3, 1, 0), (2, 2, 3), (3, 0, 7)]
+    n = 4
+    src = np.array([e[0] for e in edges])
+    dst = np.array([e[1] for e in edges])
+    w = np.array([e[2] for e in edges], dtype=np.int32)
+    A = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+    D, H, rounds, _ = oracle.apsp_tiskin(A)
+    assert D[1, 0] == 5 and H[1, 0] == 1          # direct edge beats 0 -> 2 -> 1
+    assert D[3, 0] == 5 and H[3, 0] == 2          # 0 -> 1 -> 3
+    assert np.all(np.diag(D) == 0) and np.all(np.diag(H) == 0)   # closure of I (+) A
+    assert D[0, 1] == 7 and H[0, 1] == 2          # 1 -> 3 -> 0
+    assert D[0, 2] == 7 and H[0, 2] == 3          # 2 -> 1 -> 3 -> 0
+
+
+def test_tiskin_degenerate_graphs():
+    for n in (0, 1, 5):
+        A = oracle.fold("min_plus", "i32", np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0, np.int32),
+                        n, n)
+        D, H, rounds, pl = oracle.apsp_tiskin(A)
+        assert rounds == 0 and all(x == 0 for x in pl)
+        assert np.array_equal(D, np.where(np.eye(n, dtype=bool), 0, INT_INF))
+        assert np.array_equal(H, np.where(np.eye(n, dtype=bool), 0, -1))
+    # complete graph of equal weights: every lightest path is one edge
+    n = 9
+    src, dst, _ = synth.dense_graph(n, 1)
+    A = oracle.fold("min_plus", "i32", dst, src, np.full(src.size, 4, np.int32), n, n)
+    D, H, rounds, pl = oracle.apsp_tiskin(A)
+    assert rounds == 1 and pl[0] == n * (n - 1)
+    assert np.array_equal(H, 1 - np.eye(n, dtype=np.int64)) and np.array_equal(D, 4 * H)
+    with pytest.raises(ValueError):
+        oracle.apsp_tiskin(oracle.fold("min_plus", "i32", np.array([1]), np.array([0]), np.array([-1], np.int32), 2, 2))
+
+
+def test_tiskin_dense_workload_shape():
+    n = 48
+    src, dst, w = synth.dense_graph(n, 7)
+    assert w.min() >= 1 and w.max() <= n * n and src.size == n * (n - 1)
+    A = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+    D, H, rounds, pl = oracle.apsp_tiskin(A)
+    G = sp.csr_matrix((A.val.astype(np.float64), A.col, A.rowptr), shape=(n, n)).T
+    assert np.array_equal(D, csg.floyd_warshall(G, directed=True).T.astype(np.int64))
+    # the sparsified products do less work than dense doubling's n^3 per round
+    assert pl[0] == n * (n - 1) and sum(pl) * n < rounds * n ** 3
+
+
+def test_path_product_pins():
+    inf = INT_INF
+    # 1 x 1: a single product adds weights and hops
+    Cw, Ch = oracle.path_product([[3]], [[2]], [[4]], [[5]])
+    assert Cw.tolist() == [[7]] and Ch.tolist() == [[7]]
+    # equal weights: fewer hops wins, whatever the order of k
+    Cw, Ch = oracle.path_product([[2, 1]], [[4, 1]], [[3], [4]], [[0], [1]])
+    assert Cw.tolist() == [[5]] and Ch.tolist() == [[2]]
+    Cw, Ch = oracle.path_product([[1, 2]], [[1, 4]], [[4], [3]], [[1], [0]])
+    assert Cw.tolist() == [[5]] and Ch.tolist() == [[2]]
+    # absent operands and products that reach the identity are no path
+    Cw, Ch = oracle.path_product([[inf, inf - 1]], [[0, 1]], [[1], [1]], [[1], [1]])
+    assert Cw.tolist() == [[inf]] and Ch.tolist() == [[-1]]
+    # with every hop count 0 the weights are the plain (min,+) product
+    rng = np.random.default_rng(3)
+    Aw = rng.integers(0, 50, (7, 5))
+    Bw = rng.integers(0, 50, (5, 6))
+    Cw, Ch = oracle.path_product(Aw, 0 * Aw, Bw, 0 * Bw)
+    assert np.array_equal(Cw, (Aw[:, :, None] + Bw[None, :, :]).min(axis=1)) and np.all(Ch == 0)
