@@ -37,12 +37,14 @@ __global__ void apsp_init(uint64_t *__restrict__ P, int64_t n, uint64_t idv) {
     P[e] = (e / n == e % n) ? 0ull : idv;  // zero-hop paths on the diagonal
 }
 
-// One thread per row, so repeated entries of a row combine without atomics.
+// A wave per row; repeated entries of a row meet in a 64-bit atomic min.
 __global__ void apsp_edges(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                            const int32_t *__restrict__ w, int64_t n, int32_t idw, uint64_t *__restrict__ P,
                            int32_t *bad) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  for (int64_t i = wid; i < n; i += nw) {
+    for (int64_t p = rp[i] + lane_id(); p < rp[i + 1]; p += WAVE) {
       const int32_t x = w[p];
       if (x < 0) {
         atomicOr(bad, 1);
@@ -50,25 +52,42 @@ __global__ void apsp_edges(const int64_t *__restrict__ rp, const int32_t *__rest
       }
       if (x >= idw) continue;
       const uint64_t v = ((uint64_t)(uint32_t)x << 32) | 1ull;
-      uint64_t *cell = P + i * n + col[p];
-      if (v < *cell) *cell = v;
+      atomicMin((unsigned long long *)(P + i * n + col[p]), (unsigned long long)v);
     }
   }
 }
 
-// Entries of row i whose path has exactly l hops (wave per row).
+// Entries of row i whose path has exactly l hops (wave per row); also the
+// largest weight and hop count of any path in P (rng[0], rng[1]), which
+// bound the values a round can form.
 __global__ void hops_count(const uint64_t *__restrict__ P, int64_t n, uint32_t l, uint32_t idw,
-                           int64_t *__restrict__ cnt) {
+                           int64_t *__restrict__ cnt, uint32_t *__restrict__ rng) {
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  uint32_t wmax = 0, hmax = 0;
   for (int64_t i = wid; i < n; i += nw) {
     int64_t c = 0;
     for (int64_t j = lane_id(); j < n; j += WAVE) {
       const uint64_t v = P[i * n + j];
-      c += ((uint32_t)v == l && (uint32_t)(v >> 32) < idw) ? 1 : 0;
+      const uint32_t w = (uint32_t)(v >> 32), h = (uint32_t)v;
+      const bool present = w < idw;
+      c += (present && h == l) ? 1 : 0;
+      if (present) {
+        wmax = w > wmax ? w : wmax;
+        hmax = h > hmax ? h : hmax;
+      }
     }
     c = wave_sum(c);
     if (lane_id() == 0) cnt[i] = c;
+  }
+  for (int d = WAVE / 2; d >= 1; d >>= 1) {
+    const uint32_t ow = __shfl_xor(wmax, d, WAVE), oh = __shfl_xor(hmax, d, WAVE);
+    wmax = ow > wmax ? ow : wmax;
+    hmax = oh > hmax ? oh : hmax;
+  }
+  if (lane_id() == 0) {
+    atomicMax(rng, wmax);
+    atomicMax(rng + 1, hmax);
   }
 }
 
@@ -94,6 +113,133 @@ __global__ void hops_fill(const uint64_t *__restrict__ P, int64_t n, uint32_t l,
   }
 }
 
+// One round on dense tiles, for rounds whose sparse factor is dense enough:
+//   Pn[i, j] = P[i, j] (+) (+)_k L[i, k] (x) P[k, j]
+// with L[i, k] = P[i, k] where that path has exactly l hops, the identity
+// elsewhere (masked while the tile is staged, so P_l is never built).  A
+// block owns a TM x TN tile of Pn; 256 threads as 16 x 16, each holding
+// RM x RN accumulators at rows ty + 16 m and columns tx + 16 q, so the LDS
+// reads of a k step are broadcasts (L) and 16 consecutive words (P).  The
+// next k-tile is fetched into registers while the current one is used.
+// An identity operand needs no test: its weight alone reaches the identity,
+// which no accumulator exceeds (they start from P), so min() ignores it.
+// k-tiles whose L part holds no l-hop entry are skipped.
+//
+// Values in the tiles (Enc):
+//   Wide:   the packed path itself (64-bit add and compare per sum).
+//   Narrow: (weight << hb) | hops in 32 bits with the identity 2^30, usable
+//           when every path of the round fits: with W the largest weight
+//           and H the largest hop count in P, sums have weight <= 2W and
+//           hops <= l + H < 2^hb, and (2W + 1) << hb <= 2^30.  The map keeps
+//           the order of paths and turns the path sum into one 32-bit add
+//           (no carry out of the hop field) and the choice into one min.
+struct Wide {
+  using T = uint64_t;
+  uint64_t idv;
+  __device__ T enc(uint64_t x) const { return x; }
+  __device__ T id() const { return idv; }
+  __device__ uint64_t dec(T v) const { return v; }
+};
+struct Narrow {
+  using T = uint32_t;
+  uint32_t idw;
+  int hb;
+  __device__ T enc(uint64_t x) const {
+    const uint32_t w = (uint32_t)(x >> 32);
+    return w < idw ? ((w << hb) | (uint32_t)x) : (1u << 30);
+  }
+  __device__ T id() const { return 1u << 30; }
+  // a sum may reach the identity weight when that is below 2^30 >> hb:
+  // it is no path, as in the 64-bit form
+  __device__ uint64_t dec(T v) const {
+    return (v >= (1u << 30) || (v >> hb) >= idw)
+               ? ((uint64_t)idw << 32)
+               : (((uint64_t)(v >> hb) << 32) | (uint64_t)(v & ((1u << hb) - 1)));
+  }
+};
+
+template <class E, int TM, int TN, int TK>
+__global__ void __launch_bounds__(256) apsp_dense_round(const uint64_t *__restrict__ P, uint64_t *__restrict__ Pn,
+                                                        int64_t n, uint32_t l, uint32_t idw, E enc) {
+  using T = typename E::T;
+  constexpr int RM = TM / 16, RN = TN / 16;
+  constexpr int LA = TM * TK / 256, LB = TK * TN / 256;  // staged words per thread
+  static_assert(LA * 256 == TM * TK && LB * 256 == TK * TN, "tile must split over 256 threads");
+  __shared__ T Ls[TK][TM + 1];
+  __shared__ T Bs[TK][TN];
+  const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+  const int64_t row0 = (int64_t)blockIdx.y * TM, col0 = (int64_t)blockIdx.x * TN;
+  T acc[RM][RN];
+#pragma unroll
+  for (int m = 0; m < RM; m++)
+#pragma unroll
+    for (int q = 0; q < RN; q++) {
+      const int64_t i = row0 + ty + 16 * m, j = col0 + tx + 16 * q;
+      acc[m][q] = (i < n && j < n) ? enc.enc(P[i * n + j]) : enc.id();
+    }
+  // raw words of the next k-tile (identity pattern where out of range)
+  uint64_t ra[LA], rb[LB];
+  const uint64_t idv = (uint64_t)idw << 32;
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int t = 0; t < LA; t++) {
+      const int e = t * 256 + tid, r = e / TK, c = e % TK;
+      const int64_t i = row0 + r, k = k0 + c;
+      ra[t] = (i < n && k < n) ? P[i * n + k] : idv;
+    }
+#pragma unroll
+    for (int t = 0; t < LB; t++) {
+      const int e = t * 256 + tid, r = e / TN, c = e % TN;
+      const int64_t k = k0 + r, j = col0 + c;
+      rb[t] = (k < n && j < n) ? P[k * n + j] : idv;
+    }
+  };
+  fetch(0);
+  for (int64_t k0 = 0; k0 < n; k0 += TK) {
+    int any = 0;
+#pragma unroll
+    for (int t = 0; t < LA; t++) {
+      const int e = t * 256 + tid, r = e / TK, c = e % TK;
+      const uint64_t x = ra[t];
+      const bool keep = (uint32_t)x == l && (uint32_t)(x >> 32) < idw;
+      any |= keep ? 1 : 0;
+      Ls[c][r] = keep ? enc.enc(x) : enc.id();
+    }
+#pragma unroll
+    for (int t = 0; t < LB; t++) {
+      const int e = t * 256 + tid, r = e / TN, c = e % TN;
+      Bs[r][c] = enc.enc(rb[t]);
+    }
+    const int live = __syncthreads_or(any);
+    if (k0 + TK < n) fetch(k0 + TK);
+    if (live) {
+#pragma unroll 4
+      for (int kk = 0; kk < TK; kk++) {
+        T a[RM], b[RN];
+#pragma unroll
+        for (int m = 0; m < RM; m++) a[m] = Ls[kk][ty + 16 * m];
+#pragma unroll
+        for (int q = 0; q < RN; q++) b[q] = Bs[kk][tx + 16 * q];
+#pragma unroll
+        for (int m = 0; m < RM; m++)
+#pragma unroll
+          for (int q = 0; q < RN; q++) {
+            const T c = a[m] + b[q];
+            acc[m][q] = c < acc[m][q] ? c : acc[m][q];
+          }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < RM; m++)
+#pragma unroll
+    for (int q = 0; q < RN; q++) {
+      const int64_t i = row0 + ty + 16 * m, j = col0 + tx + 16 * q;
+      if (i < n && j < n) Pn[i * n + j] = enc.dec(acc[m][q]);
+    }
+}
+
 __global__ void apsp_out(const uint64_t *__restrict__ P, int64_t total, uint32_t idw, int32_t *__restrict__ D,
                          int32_t *__restrict__ H) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -108,6 +254,13 @@ __global__ void apsp_out(const uint64_t *__restrict__ P, int64_t total, uint32_t
 }  // namespace
 
 // Declared in internal.hpp (used by the C entry point in capi.cpp).
+// Rounds whose sparse factor holds at least this fraction of the n^2
+// entries run on dense tiles; sparser ones as a CSR x dense product.  The
+// crossover follows the measured rates: a 32-bit dense round forms its n^3
+// sums about 18x faster per sum than the CSR product forms nnz * n, a
+// 64-bit round about 7x.
+constexpr double kDenseFracNarrow = 0.05, kDenseFracWide = 0.14;
+
 void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, int32_t *rounds, int64_t *round_nnz,
                  hipStream_t s) {
   const int64_t n = A.m;
@@ -120,10 +273,15 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
   Buf bad(c, 64);
   fill_i32(bad.as<int32_t>(), 1, 0, s);
   uint64_t *P = pa.as<uint64_t>(), *Pn = pb.as<uint64_t>();
-  apsp_init<<<grid_of(total), 256, 0, s>>>(P, n, idv);
+  {
+    ProfScope ps(c, "apsp.init", 8.0 * (double)total, s);
+    apsp_init<<<grid_of(total), 256, 0, s>>>(P, n, idv);
+  }
   SRTC_LAUNCH_CHECK("apsp_init");
   if (A.nnz > 0) {
-    apsp_edges<<<grid_of(n), 256, 0, s>>>(A.rowptr, A.col, (const int32_t *)A.val, n, idw, P, bad.as<int32_t>());
+    ProfScope ps(c, "apsp.edges", 12.0 * (double)A.nnz + 8.0 * (double)(n + 1), s);
+    apsp_edges<<<grid_of(n * WAVE), 256, 0, s>>>(A.rowptr, A.col, (const int32_t *)A.val, n, idw, P,
+                                                 bad.as<int32_t>());
     SRTC_LAUNCH_CHECK("apsp_edges");
   }
   int32_t neg = 0;
@@ -131,19 +289,55 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
   if (neg) fail(SRTC_ERR_ARG, "apsp: negative edge weight");
   const IdVal id{0.0, (int64_t)idw};
   Buf cnt(c, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)), rp(c, sizeof(int64_t) * (size_t)(n + 1));
+  Buf rng(c, 64);
   int32_t r = 0;
   if (round_nnz) std::fill(round_nnz, round_nnz + 64, (int64_t)0);
   for (int64_t l = 1; l < n; l <<= 1) {
-    hops_count<<<grid_of(n * WAVE), 256, 0, s>>>(P, n, (uint32_t)l, (uint32_t)idw, cnt.as<int64_t>());
+    fill_i32(rng.as<int32_t>(), 2, 0, s);
+    {
+      ProfScope ps(c, "apsp.hops_count", 8.0 * (double)total + 8.0 * (double)n, s);
+      hops_count<<<grid_of(n * WAVE), 256, 0, s>>>(P, n, (uint32_t)l, (uint32_t)idw, cnt.as<int64_t>(),
+                                                    rng.as<uint32_t>());
+    }
     SRTC_LAUNCH_CHECK("hops_count");
     excl_scan_i64(c, cnt.as<int64_t>(), rp.as<int64_t>(), n, s);
-    const int64_t nnz = read_i64(c, rp.as<int64_t>() + n, s);
+    // one read per round: the count of l-hop paths and the value range
+    SRTC_HIP(hipMemcpyAsync(rng.as<int64_t>() + 1, rp.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    int64_t info[2];
+    read_to_host(c, info, rng.p, sizeof(info), s);
+    const int64_t nnz = info[1];
+    const uint32_t wmax = (uint32_t)info[0], hmax = (uint32_t)((uint64_t)info[0] >> 32);
     c->tracef("apsp: round %d, %lld paths of %lld hops", r, (long long)nnz, (long long)l);
     if (round_nnz && r < 64) round_nnz[r] = nnz;
     if (nnz == 0) break;  // no path has more than l hops
+    const uint64_t hsum = (uint64_t)l + hmax;
+    int hb = 1;
+    while (hb < 31 && (1ull << hb) <= hsum) hb++;
+    const bool narrow = hb < 31 && ((2ull * wmax + 1) << hb) <= (1ull << 30);
+    if ((double)nnz >= (narrow ? kDenseFracNarrow : kDenseFracWide) * (double)total) {
+      ProfScope ps(c, narrow ? "apsp.dense_round.u32" : "apsp.dense_round.u64", 8.0 * 3.0 * (double)total, s);
+      if (narrow) {
+        constexpr int TM = 128, TN = 128, TK = 32;
+        const dim3 grid((unsigned)((n + TN - 1) / TN), (unsigned)((n + TM - 1) / TM));
+        apsp_dense_round<Narrow, TM, TN, TK><<<grid, 256, 0, s>>>(P, Pn, n, (uint32_t)l, (uint32_t)idw,
+                                                                   Narrow{(uint32_t)idw, hb});
+      } else {
+        constexpr int TM = 128, TN = 128, TK = 16;
+        const dim3 grid((unsigned)((n + TN - 1) / TN), (unsigned)((n + TM - 1) / TM));
+        apsp_dense_round<Wide, TM, TN, TK><<<grid, 256, 0, s>>>(P, Pn, n, (uint32_t)l, (uint32_t)idw, Wide{idv});
+      }
+      SRTC_LAUNCH_CHECK("apsp_dense_round");
+      c->tracef("apsp: dense round, %s values (hop bits %d)", narrow ? "32-bit" : "64-bit", hb);
+      std::swap(P, Pn);
+      r++;
+      continue;
+    }
     Buf pc(c, sizeof(int32_t) * (size_t)nnz), pv(c, sizeof(uint64_t) * (size_t)nnz);
-    hops_fill<<<grid_of(n * WAVE), 256, 0, s>>>(P, n, (uint32_t)l, (uint32_t)idw, rp.as<int64_t>(), pc.as<int32_t>(),
-                                                 pv.as<uint64_t>());
+    {
+      ProfScope ps(c, "apsp.hops_fill", 8.0 * (double)total + 12.0 * (double)nnz, s);
+      hops_fill<<<grid_of(n * WAVE), 256, 0, s>>>(P, n, (uint32_t)l, (uint32_t)idw, rp.as<int64_t>(),
+                                                   pc.as<int32_t>(), pv.as<uint64_t>());
+    }
     SRTC_LAUNCH_CHECK("hops_fill");
     CsrView pl;
     pl.m = n;
@@ -158,6 +352,7 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
     r++;
   }
   if (total > 0) {
+    ProfScope ps(c, "apsp.out", (H ? 16.0 : 12.0) * (double)total, s);
     apsp_out<<<grid_of(total), 256, 0, s>>>(P, total, (uint32_t)idw, D, H);
     SRTC_LAUNCH_CHECK("apsp_out");
   }

@@ -48,11 +48,32 @@ def test_tiskin_er_graphs(ctx, n, d, lo, hi, seed):
     check_apsp(ctx, n, src, dst, w, what=f"er d={d} w=[{lo},{hi}]")
 
 
-def test_tiskin_dense_graph(ctx):
-    n = 200
+@pytest.mark.parametrize("n", [200, 257, 384])
+def test_tiskin_dense_graph(ctx, n):
+    # rounds whose sparse factor is dense run on dense tiles (ragged edges
+    # at 200 and 257)
     src, dst, w = synth.dense_graph(n, 8)
     _, _, rounds = check_apsp(ctx, n, src, dst, w, what="dense")
     assert rounds >= 2
+
+
+def test_tiskin_dense_rounds_value_widths(ctx):
+    # heavy weights leave no room for the 32-bit tile form (64-bit dense
+    # rounds); a small identity cuts sums off inside a 32-bit round
+    n = 260
+    src, dst, _ = synth.dense_graph(n, 9)
+    w = synth.randint(synth.stream_key(9, 5), src.size, 1, 1 << 28).astype(np.int32)
+    check_apsp(ctx, n, src, dst, w, add_id=(1 << 30) - 1, what="dense wide weights")
+    w = synth.randint(synth.stream_key(9, 6), src.size, 1, 90).astype(np.int32)
+    check_apsp(ctx, n, src, dst, w, add_id=100, what="dense small identity")
+
+
+def test_tiskin_dense_rounds_with_ties(ctx):
+    # many equal weights: the fewest-hops rule decides most entries
+    n = 333
+    src, dst = synth.er_edges(n, 120, 13)
+    w = synth.edge_values("i32", src.size, 13, lo=0, hi=3)
+    check_apsp(ctx, n, src, dst, w, what="dense ties")
 
 
 def test_tiskin_path_graph_and_unreachable(ctx):
