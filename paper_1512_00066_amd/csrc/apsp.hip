@@ -57,16 +57,43 @@ __global__ void apsp_edges(const int64_t *__restrict__ rp, const int32_t *__rest
   }
 }
 
-// Entries of row i whose path has exactly l hops (wave per row); also the
-// largest weight and hop count of any path in P (rng[0], rng[1]), which
-// bound the values a round can form.
-__global__ void hops_count(const uint64_t *__restrict__ P, int64_t n, uint32_t l, uint32_t idw,
-                           int64_t *__restrict__ cnt, uint32_t *__restrict__ rng) {
+// Largest weight and hop count over the 256 threads of a block, written
+// to part[2 * blk] and part[2 * blk + 1] by thread 0 (all threads call it).
+__device__ __forceinline__ void block_range(uint32_t wmax, uint32_t hmax, uint32_t *part, int64_t blk) {
+  __shared__ uint32_t sw[4], sh[4];
+  for (int d = WAVE / 2; d >= 1; d >>= 1) {
+    const uint32_t ow = __shfl_xor(wmax, d, WAVE), oh = __shfl_xor(hmax, d, WAVE);
+    wmax = ow > wmax ? ow : wmax;
+    hmax = oh > hmax ? oh : hmax;
+  }
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    sw[w] = wmax;
+    sh[w] = hmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = sw[0], b = sh[0];
+    for (int k = 1; k < 4; k++) {
+      a = sw[k] > a ? sw[k] : a;
+      b = sh[k] > b ? sh[k] : b;
+    }
+    part[2 * blk] = a;
+    part[2 * blk + 1] = b;
+  }
+}
+
+// Entries of row i whose path has exactly l hops (wave per row), and per
+// block the largest weight and hop count of any path in P, which bound the
+// values a round can form.  256 threads per block.
+__global__ void __launch_bounds__(256) hops_count(const uint64_t *__restrict__ P, int64_t n, uint32_t l, uint32_t idw,
+                                                  int64_t *__restrict__ cnt, uint32_t *__restrict__ part) {
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
   uint32_t wmax = 0, hmax = 0;
   for (int64_t i = wid; i < n; i += nw) {
     int64_t c = 0;
+#pragma unroll 8
     for (int64_t j = lane_id(); j < n; j += WAVE) {
       const uint64_t v = P[i * n + j];
       const uint32_t w = (uint32_t)(v >> 32), h = (uint32_t)v;
@@ -80,15 +107,21 @@ __global__ void hops_count(const uint64_t *__restrict__ P, int64_t n, uint32_t l
     c = wave_sum(c);
     if (lane_id() == 0) cnt[i] = c;
   }
-  for (int d = WAVE / 2; d >= 1; d >>= 1) {
-    const uint32_t ow = __shfl_xor(wmax, d, WAVE), oh = __shfl_xor(hmax, d, WAVE);
-    wmax = ow > wmax ? ow : wmax;
-    hmax = oh > hmax ? oh : hmax;
+  block_range(wmax, hmax, part, blockIdx.x);
+}
+
+// info[0] = largest weight | largest hops << 32 over nb block partials,
+// info[1] = *total (the count of l-hop paths).  One block of 256 threads.
+__global__ void __launch_bounds__(256) range_reduce(const uint32_t *__restrict__ part, int64_t nb,
+                                                    const int64_t *__restrict__ total, int64_t *__restrict__ info) {
+  uint32_t wmax = 0, hmax = 0;
+  for (int64_t b = threadIdx.x; b < nb; b += 256) {
+    wmax = part[2 * b] > wmax ? part[2 * b] : wmax;
+    hmax = part[2 * b + 1] > hmax ? part[2 * b + 1] : hmax;
   }
-  if (lane_id() == 0) {
-    atomicMax(rng, wmax);
-    atomicMax(rng + 1, hmax);
-  }
+  uint32_t *res = reinterpret_cast<uint32_t *>(info);
+  block_range(wmax, hmax, res, 0);
+  if (threadIdx.x == 0) info[1] = *total;
 }
 
 __global__ void hops_fill(const uint64_t *__restrict__ P, int64_t n, uint32_t l, uint32_t idw,
@@ -158,13 +191,21 @@ struct Narrow {
   }
 };
 
-template <class E, int TM, int TN, int TK>
-__global__ void __launch_bounds__(256) apsp_dense_round(const uint64_t *__restrict__ P, uint64_t *__restrict__ Pn,
-                                                        int64_t n, uint32_t l, uint32_t idw, E enc) {
+//
+// With cnt given, the epilogue also counts for the next round (l2 = 2l):
+// cnt[i] += entries of row i of Pn with exactly l2 hops (cnt zeroed by the
+// caller), and part[2 b], part[2 b + 1] = largest weight and hop count in
+// block b's tile, so the next round needs no separate pass over P.
+template <class E, int TM, int TN, int TK, int MINB>
+__global__ void __launch_bounds__(256, MINB) apsp_dense_round(const uint64_t *__restrict__ P, uint64_t *__restrict__ Pn,
+                                                              int64_t n, uint32_t l, uint32_t idw, E enc,
+                                                              int64_t *__restrict__ cnt, uint32_t l2,
+                                                              uint32_t *__restrict__ part) {
   using T = typename E::T;
   constexpr int RM = TM / 16, RN = TN / 16;
   constexpr int LA = TM * TK / 256, LB = TK * TN / 256;  // staged words per thread
   static_assert(LA * 256 == TM * TK && LB * 256 == TK * TN, "tile must split over 256 threads");
+  static_assert(256 % TK == 0 && 256 % TN == 0, "a thread keeps one column of each staged tile");
   __shared__ T Ls[TK][TM + 1];
   __shared__ T Bs[TK][TN];
   const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
@@ -177,21 +218,30 @@ __global__ void __launch_bounds__(256) apsp_dense_round(const uint64_t *__restri
       const int64_t i = row0 + ty + 16 * m, j = col0 + tx + 16 * q;
       acc[m][q] = (i < n && j < n) ? enc.enc(P[i * n + j]) : enc.id();
     }
-  // raw words of the next k-tile (identity pattern where out of range)
+  // raw words of the next k-tile (identity pattern where out of range).
+  // Thread tid stages column tid % TK of the L tile (rows tid / TK + t *
+  // 256 / TK) and column tid % TN of the P tile (rows tid / TN + t * 256 /
+  // TN), so each staged word is one running pointer plus a fixed stride.
   uint64_t ra[LA], rb[LB];
   const uint64_t idv = (uint64_t)idw << 32;
+  const int ca = tid % TK, ra0 = tid / TK, cb = tid % TN, rb0 = tid / TN;
+  const bool rows_in = row0 + TM <= n, cols_in = col0 + TN <= n;
   auto fetch = [&](int64_t k0) {
+    const uint64_t *pa = P + (row0 + ra0) * n + k0 + ca;
+    const uint64_t *pb = P + (k0 + rb0) * n + col0 + cb;
+    const int64_t sa = (int64_t)(256 / TK) * n, sb = (int64_t)(256 / TN) * n;
+    if (rows_in && cols_in && k0 + TK <= n) {
 #pragma unroll
-    for (int t = 0; t < LA; t++) {
-      const int e = t * 256 + tid, r = e / TK, c = e % TK;
-      const int64_t i = row0 + r, k = k0 + c;
-      ra[t] = (i < n && k < n) ? P[i * n + k] : idv;
-    }
+      for (int t = 0; t < LA; t++) ra[t] = pa[t * sa];
 #pragma unroll
-    for (int t = 0; t < LB; t++) {
-      const int e = t * 256 + tid, r = e / TN, c = e % TN;
-      const int64_t k = k0 + r, j = col0 + c;
-      rb[t] = (k < n && j < n) ? P[k * n + j] : idv;
+      for (int t = 0; t < LB; t++) rb[t] = pb[t * sb];
+    } else {
+#pragma unroll
+      for (int t = 0; t < LA; t++)
+        ra[t] = (row0 + ra0 + t * (256 / TK) < n && k0 + ca < n) ? pa[t * sa] : idv;
+#pragma unroll
+      for (int t = 0; t < LB; t++)
+        rb[t] = (k0 + rb0 + t * (256 / TN) < n && col0 + cb < n) ? pb[t * sb] : idv;
     }
   };
   fetch(0);
@@ -199,17 +249,13 @@ __global__ void __launch_bounds__(256) apsp_dense_round(const uint64_t *__restri
     int any = 0;
 #pragma unroll
     for (int t = 0; t < LA; t++) {
-      const int e = t * 256 + tid, r = e / TK, c = e % TK;
       const uint64_t x = ra[t];
       const bool keep = (uint32_t)x == l && (uint32_t)(x >> 32) < idw;
       any |= keep ? 1 : 0;
-      Ls[c][r] = keep ? enc.enc(x) : enc.id();
+      Ls[ca][ra0 + t * (256 / TK)] = keep ? enc.enc(x) : enc.id();
     }
 #pragma unroll
-    for (int t = 0; t < LB; t++) {
-      const int e = t * 256 + tid, r = e / TN, c = e % TN;
-      Bs[r][c] = enc.enc(rb[t]);
-    }
+    for (int t = 0; t < LB; t++) Bs[rb0 + t * (256 / TN)][cb] = enc.enc(rb[t]);
     const int live = __syncthreads_or(any);
     if (k0 + TK < n) fetch(k0 + TK);
     if (live) {
@@ -231,13 +277,32 @@ __global__ void __launch_bounds__(256) apsp_dense_round(const uint64_t *__restri
     }
     __syncthreads();
   }
+  uint32_t wmax = 0, hmax = 0;
 #pragma unroll
-  for (int m = 0; m < RM; m++)
+  for (int m = 0; m < RM; m++) {
+    const int64_t i = row0 + ty + 16 * m;
+    int c = 0;
 #pragma unroll
     for (int q = 0; q < RN; q++) {
-      const int64_t i = row0 + ty + 16 * m, j = col0 + tx + 16 * q;
-      if (i < n && j < n) Pn[i * n + j] = enc.dec(acc[m][q]);
+      const int64_t j = col0 + tx + 16 * q;
+      if (i < n && j < n) {
+        const uint64_t o = enc.dec(acc[m][q]);
+        Pn[i * n + j] = o;
+        const uint32_t w = (uint32_t)(o >> 32), h = (uint32_t)o;
+        if (w < idw) {
+          c += h == l2 ? 1 : 0;
+          wmax = w > wmax ? w : wmax;
+          hmax = h > hmax ? h : hmax;
+        }
+      }
     }
+    if (cnt) {
+      // the 16 threads of a tile row are 16 consecutive lanes
+      for (int d = 8; d >= 1; d >>= 1) c += __shfl_xor(c, d, WAVE);
+      if (tx == 0 && i < n && c > 0) atomicAdd((unsigned long long *)(cnt + i), (unsigned long long)c);
+    }
+  }
+  if (cnt) block_range(wmax, hmax, part, (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 __global__ void apsp_out(const uint64_t *__restrict__ P, int64_t total, uint32_t idw, int32_t *__restrict__ D,
@@ -289,22 +354,30 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
   if (neg) fail(SRTC_ERR_ARG, "apsp: negative edge weight");
   const IdVal id{0.0, (int64_t)idw};
   Buf cnt(c, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)), rp(c, sizeof(int64_t) * (size_t)(n + 1));
-  Buf rng(c, 64);
+  // per-block ranges (hops_count's grid or a dense round's tiles) and the
+  // reduced {range, count} the host reads once per round
+  constexpr int DTM = 64, DTN = 64, DTK = 32;
+  const int64_t cnt_blocks = std::min<int64_t>(grid_of(n * WAVE), 1024);
+  const int64_t tiles = ((n + DTM - 1) / DTM) * ((n + DTN - 1) / DTN);
+  Buf part(c, 8 * (size_t)std::max<int64_t>({cnt_blocks, tiles, 1})), info_b(c, 64);
+  bool counted = false;  // the previous dense round already counted this round's paths
   int32_t r = 0;
   if (round_nnz) std::fill(round_nnz, round_nnz + 64, (int64_t)0);
   for (int64_t l = 1; l < n; l <<= 1) {
-    fill_i32(rng.as<int32_t>(), 2, 0, s);
-    {
+    int64_t nparts = tiles;
+    if (!counted) {
+      nparts = cnt_blocks;
       ProfScope ps(c, "apsp.hops_count", 8.0 * (double)total + 8.0 * (double)n, s);
-      hops_count<<<grid_of(n * WAVE), 256, 0, s>>>(P, n, (uint32_t)l, (uint32_t)idw, cnt.as<int64_t>(),
-                                                    rng.as<uint32_t>());
+      hops_count<<<(unsigned)cnt_blocks, 256, 0, s>>>(P, n, (uint32_t)l, (uint32_t)idw, cnt.as<int64_t>(),
+                                                      part.as<uint32_t>());
+      SRTC_LAUNCH_CHECK("hops_count");
     }
-    SRTC_LAUNCH_CHECK("hops_count");
     excl_scan_i64(c, cnt.as<int64_t>(), rp.as<int64_t>(), n, s);
-    // one read per round: the count of l-hop paths and the value range
-    SRTC_HIP(hipMemcpyAsync(rng.as<int64_t>() + 1, rp.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    // one read per round: the value range and the count of l-hop paths
+    range_reduce<<<1, 256, 0, s>>>(part.as<uint32_t>(), nparts, rp.as<int64_t>() + n, info_b.as<int64_t>());
+    SRTC_LAUNCH_CHECK("range_reduce");
     int64_t info[2];
-    read_to_host(c, info, rng.p, sizeof(info), s);
+    read_to_host(c, info, info_b.p, sizeof(info), s);
     const int64_t nnz = info[1];
     const uint32_t wmax = (uint32_t)info[0], hmax = (uint32_t)((uint64_t)info[0] >> 32);
     c->tracef("apsp: round %d, %lld paths of %lld hops", r, (long long)nnz, (long long)l);
@@ -316,16 +389,20 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
     const bool narrow = hb < 31 && ((2ull * wmax + 1) << hb) <= (1ull << 30);
     if ((double)nnz >= (narrow ? kDenseFracNarrow : kDenseFracWide) * (double)total) {
       ProfScope ps(c, narrow ? "apsp.dense_round.u32" : "apsp.dense_round.u64", 8.0 * 3.0 * (double)total, s);
+      const uint32_t l2 = (uint32_t)std::min<int64_t>(2 * l, 0xffffffffll);
+      int64_t *nc = 2 * l < n ? cnt.as<int64_t>() : nullptr;  // counts for the next round
+      if (nc) fill_i64(nc, n, 0, s);
+      const dim3 grid((unsigned)((n + DTN - 1) / DTN), (unsigned)((n + DTM - 1) / DTM));
       if (narrow) {
-        constexpr int TM = 128, TN = 128, TK = 32;
-        const dim3 grid((unsigned)((n + TN - 1) / TN), (unsigned)((n + TM - 1) / TM));
-        apsp_dense_round<Narrow, TM, TN, TK><<<grid, 256, 0, s>>>(P, Pn, n, (uint32_t)l, (uint32_t)idw,
-                                                                   Narrow{(uint32_t)idw, hb});
+        // 64 x 64 tiles, 3 blocks per CU: measured best at n = 2048 of
+        // 128x128 (k 16/32), 128x64, 64x128 (k 32/64) and 64x64 (k 32/64)
+        apsp_dense_round<Narrow, DTM, DTN, DTK, 3><<<grid, 256, 0, s>>>(
+            P, Pn, n, (uint32_t)l, (uint32_t)idw, Narrow{(uint32_t)idw, hb}, nc, l2, part.as<uint32_t>());
       } else {
-        constexpr int TM = 128, TN = 128, TK = 16;
-        const dim3 grid((unsigned)((n + TN - 1) / TN), (unsigned)((n + TM - 1) / TM));
-        apsp_dense_round<Wide, TM, TN, TK><<<grid, 256, 0, s>>>(P, Pn, n, (uint32_t)l, (uint32_t)idw, Wide{idv});
+        apsp_dense_round<Wide, DTM, DTN, 16, 2><<<grid, 256, 0, s>>>(P, Pn, n, (uint32_t)l, (uint32_t)idw,
+                                                                      Wide{idv}, nc, l2, part.as<uint32_t>());
       }
+      counted = nc != nullptr;
       SRTC_LAUNCH_CHECK("apsp_dense_round");
       c->tracef("apsp: dense round, %s values (hop bits %d)", narrow ? "32-bit" : "64-bit", hb);
       std::swap(P, Pn);
@@ -349,6 +426,7 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
     SRTC_HIP(hipMemcpyAsync(Pn, P, sizeof(uint64_t) * (size_t)total, hipMemcpyDeviceToDevice, s));
     spmm(c, SRTC_MIN_PLUS, SRTC_PATH64, id, pl, P, n, Pn, 1, s);  // Pn = P (+) Pl (x) P
     std::swap(P, Pn);
+    counted = false;
     r++;
   }
   if (total > 0) {

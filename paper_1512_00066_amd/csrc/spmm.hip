@@ -10,7 +10,8 @@
 // Work is cut into items of at most T nonzeros of one row, so a row of any
 // length costs at most T sequential gathers per lane group; G lanes (G = a
 // power of two >= the dense width, up to 64) share an item, one lane per
-// dense column.  A row split into several items writes partial sums that a
+// dense column; a wider operand is cut into chunks of 64 columns and every
+// (item, chunk) pair is a unit of work of its own.  A row split into several items writes partial sums that a
 // second kernel combines in item order, which keeps every semiring,
 // including fp (+), deterministic.
 #include <algorithm>
@@ -76,12 +77,17 @@ __global__ void __launch_bounds__(256) spmm_items(const int32_t *__restrict__ ir
   const int grp = lane / G, c = lane % G;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
-  for (int64_t it = wave * PER_WAVE + grp; it < nitems; it += nwaves * PER_WAVE) {
+  // work units: (item, chunk of G columns); wider than G only when G = 64,
+  // so each wave then takes one chunk of one item at a time
+  const int64_t nch = (s + G - 1) / G;
+  for (int64_t u = wave * PER_WAVE + grp; u < nitems * nch; u += nwaves * PER_WAVE) {
+    const int64_t it = nch == 1 ? u : u / nch;
     const int64_t row = irow[it];
     if (MODE == 1 && row_inst && !inst_active[row_inst[row]]) continue;
     const int64_t b = ibeg[it], e = iend[it];
     const int64_t pi = ipidx[it];
-    for (int64_t c0 = 0; c0 < s; c0 += G) {
+    {
+      const int64_t c0 = (u - it * nch) * G;
       const int64_t col = c0 + c;
       const bool on = col < s;
       A acc = id;
@@ -217,7 +223,9 @@ void run_items(const SpmmPlan &pl, const CsrView &A, const void *X, int64_t s, v
   using V = typename SR::val_t;
   using Acc = typename SR::acc_t;
   const Acc id = id_as<SR>(idv);
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(pl.max_items * G / 256 + 1, pl.grid_cap));
+  const int64_t nch = (s + G - 1) / G;
+  const unsigned grid =
+      (unsigned)std::max<int64_t>(1, std::min<int64_t>(pl.max_items * nch * G / 256 + 1, pl.grid_cap));
   spmm_items<SR, G, MODE, ACC><<<grid, 256, 0, st>>>(pl.irow, pl.ibeg, pl.iend, pl.ipidx, pl.nitems, A.col,
                                                       (const V *)A.val, (const V *)X, s, Y, (Acc *)pl.partial, id,
                                                       changed, row_inst, inst_active, inst_changed, rin, rout);
@@ -313,7 +321,9 @@ void SpmmPlan::build(Ctx *c, const CsrView &A, int64_t s_width, hipStream_t st) 
   int g = 1;
   while (g < s_width && g < WAVE) g <<= 1;
   G = g;
-  T = G >= 64 ? 256 : (G >= 8 ? 64 : 32);
+  // a work unit is one item times one chunk of G columns: wider operands
+  // have more chunks per item, so shorter items keep the units short
+  T = s_width > 128 ? 64 : (G >= 64 ? 256 : (G >= 8 ? 64 : 32));
   const int64_t m = A.m;
   max_items = m + A.nnz / T + 1;
   cnt = Buf(c, sizeof(int64_t) * (size_t)std::max<int64_t>(m, 1));

@@ -242,7 +242,7 @@ def test_er4096_tropical_square_and_bellman_ford(ctx):
 
 # ------------------------------------------------------------------ SpMM --
 @pytest.mark.parametrize("semiring,dtype", PAIRS)
-@pytest.mark.parametrize("width", [1, 8, 64, 100])
+@pytest.mark.parametrize("width", [1, 8, 64, 100, 300])
 def test_spmm_parity(ctx, semiring, dtype, width):
     say("spmm", semiring, dtype, width)
     src, dst = synth.rmat_edges(12, 16, 0.57, 0.19, 0.19, seed=77)   # rows up to ~1k nonzeros (split items)
