@@ -192,12 +192,19 @@ srtc_status srtc_fold(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const
  *       previous C joins the sum and is replaced by new arrays -- the old
  *       arrays stay the caller's).  Synchronizes once (output size).
  *   sparse A x dense B  -> dense C (caller-allocated, fully asynchronous).
- *   dense A x dense B   -> dense C, (+,x) only, on the matrix cores.
+ *   dense A x dense B   -> dense C, (+,x) only, on the matrix cores (a
+ *       letter in all three tensors makes it a strided batch of GEMMs).
  * Index rules: each letter appears at most once per tensor and in at least
- * two tensors; in C all column letters (those of B only) follow all row
- * letters.  Sparse operands may be COO (folded on the fly) or CSR whose
- * split matches the fold.  Right-hand sides are read before C is written
- * (out-of-place); C may not share storage with A or B (SRTC_ERR_ALIAS). */
+ * two tensors.  Letters may come in any order in every tensor (Section
+ * 5.1's folding): operands are folded or permuted to (rows, inner) and
+ * (inner, columns) form, and when C's order interleaves its row letters
+ * (those of A) with its column letters (those of B only) the product is
+ * formed in (rows, columns) order and folded back into C's order (a dense
+ * permutation through scratch of C's size; for a sparse C a re-fold whose
+ * CSR rows are C's first |row letters| letters).  Sparse operands may be
+ * COO (folded on the fly) or CSR whose split matches the fold.
+ * Right-hand sides are read before C is written (out-of-place); C may not
+ * share storage with A or B (SRTC_ERR_ALIAS). */
 srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int accumulate,
                           const char *ia, const srtc_tensor *A, const char *ib,
                           const srtc_tensor *B, const char *ic, srtc_tensor *C,

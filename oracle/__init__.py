@@ -349,3 +349,58 @@ def path_product(Aw, Ah, Bw, Bh, inf_value=INT_INF):
         Cw = np.where(better, cw, Cw)
         Ch = np.where(better, ch, Ch)
     return Cw, Ch
+
+
+_NP_SEMIRING = {
+    # (multiply, add reduction) of each semiring over numpy arrays
+    "plus_times": (np.multiply, np.add.reduce),
+    "min_plus": (np.add, np.minimum.reduce),
+    "or_and": (np.bitwise_and, np.bitwise_or.reduce),
+    "max_times": (np.multiply, np.maximum.reduce),
+}
+
+
+def contract(semiring, dtype, ia: str, A, ib: str, B, ic: str, add_id=None):
+    """C[ic] = (+) over the letters not in ic of A[ia] (x) B[ib], written out
+    on dense operands (Section 3.3.1): both operands are broadcast over every
+    letter and the letters outside C are reduced.  Entries equal to the
+    additive identity are absent (their products are the identity).  (+,x)
+    runs in fp64 with numpy's einsum (the same sum of products); (min,+)
+    int32 sums in int64 and clamps results at the identity (Section 3.1).
+    Returns a dense array in C's letter order."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    if semiring == "plus_times":
+        return np.einsum(f"{ia},{ib}->{ic}", A.astype(np.float64), B.astype(np.float64))
+    ident = default_add_id(semiring, dtype) if add_id is None else add_id
+    extra = []
+    for ch in ia + ib:
+        if ch not in ic and ch not in extra:
+            extra.append(ch)
+    full = ic + "".join(extra)
+    ext = {}
+    for s_, T in ((ia, A), (ib, B)):
+        for ch, e in zip(s_, T.shape):
+            ext[ch] = e
+
+    def spread(T, idx):
+        # T's axes moved to their places in `full`, size 1 elsewhere
+        T = np.transpose(T, [idx.index(ch) for ch in full if ch in idx])
+        return T.reshape([ext[ch] if ch in idx else 1 for ch in full])
+
+    mul, red = _NP_SEMIRING[semiring]
+    wide = np.int64 if dtype == "i32" else NP_DTYPES[dtype]
+    a = spread(A, ia).astype(wide)
+    b = spread(B, ib).astype(wide)
+    absent = (spread(A, ia) == ident) | (spread(B, ib) == ident)
+    if semiring == "min_plus" and dtype == "i32":
+        p = np.minimum(mul(a, b), ident)
+    else:
+        p = mul(a, b)
+    p = np.where(absent, np.asarray(ident, dtype=p.dtype), p)
+    p = np.broadcast_to(p, [ext[ch] for ch in full])
+    axes = tuple(range(len(ic), len(full)))
+    out = red(p, axis=axes) if axes else np.array(p)
+    if semiring == "min_plus" and dtype == "i32":
+        out = np.minimum(out, ident)
+    return out.astype(NP_DTYPES[dtype])

@@ -382,14 +382,6 @@ Plan plan_contraction(const std::string &a, const srtc_tensor *A, const std::str
   for (char ch : b)
     if (a.find(ch) == std::string::npos && cidx.find(ch) == std::string::npos)
       fail(SRTC_ERR_INDEX, std::string("index '") + ch + "' appears only in B (reduction)");
-  // C: every column letter after every row letter
-  size_t last_row = 0, first_col = cidx.size();
-  for (size_t i = 0; i < cidx.size(); i++) {
-    if (p.N.find(cidx[i]) != std::string::npos) first_col = std::min(first_col, i);
-    else last_row = i + 1;
-  }
-  if (!p.N.empty() && first_col < last_row)
-    fail(SRTC_ERR_UNSUPPORTED, "output index order interleaves row and column indices");
   return p;
 }
 
@@ -595,6 +587,28 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
         SRTC_LAUNCH_CHECK("col_mod_kernel");
       }
       t.n = extent(p, p.N);
+      if (crow + p.N != cidx && t.nnz > 0) {
+        // fold back: the product's (C's row letters) x (C's column letters)
+        // entries become C in its own index order, rows = C's first
+        // |rows| letters (a permutation of keys, so nothing combines)
+        const std::string from = crow + p.N;
+        std::vector<int64_t> fd(from.size());
+        for (size_t q = 0; q < from.size(); q++) fd[q] = p.dim.at(from[q]);
+        std::vector<int> rm, cm;
+        for (size_t q = 0; q < cidx.size(); q++)
+          (q < crow.size() ? rm : cm).push_back((int)from.find(cidx[q]));
+        CsrView tv{t.m, t.n, t.nnz, t.rowptr.as<int64_t>(), t.col.as<int32_t>(), t.val.p};
+        Buf k0(c, sizeof(int64_t) * (size_t)t.nnz), k1(c, sizeof(int64_t) * (size_t)t.nnz);
+        csr_to_keys(tv, k0.as<int64_t>(), s);
+        remap_keys(c, k0.as<int64_t>(), t.nnz, (int)from.size(), fd.data(), (int)rm.size(), rm.data(), (int)cm.size(),
+                   cm.data(), k1.as<int64_t>(), s);
+        int64_t nr = 1, nc = 1;
+        for (int q : rm) nr *= fd[q];
+        for (int q : cm) nc *= fd[q];
+        CsrOut u;
+        fold_keys_to_csr(c, sr, dt, id, k1.as<int64_t>(), t.val.p, t.nnz, nr, nc, &u, s);
+        t = std::move(u);
+      }
       if (accumulate && C->format == SRTC_CSR && C->nnz > 0) {
         // previous C joins the sum: C_new = C_old (+) T (old entries first)
         if (C->split != (int)crow.size()) fail(SRTC_ERR_FORMAT, "C: split differs from the row indices");
@@ -626,27 +640,49 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
       dense_permute(T->vals, tmp->p, (int)dtype_size(dt), T->order, T->dims, perm.data(), s);
       return tmp->p;
     };
+    // The product is formed in the order `from` of its own rows and
+    // columns; when that is not C's order it goes to a scratch tensor and
+    // is folded back (permuted, the old C joining by (+) with accumulate).
+    auto product_into_c = [&](const std::string &from, auto &&form) {
+      if (from == cidx) {
+        form(C->vals, accumulate);
+        return;
+      }
+      Buf tc(c, cbytes);
+      form(tc.p, 0);
+      std::vector<int64_t> fd(from.size());
+      for (size_t q = 0; q < from.size(); q++) fd[q] = p.dim.at(from[q]);
+      std::vector<int> perm;
+      for (char ch : cidx) perm.push_back((int)from.find(ch));
+      ProfScope ps(c, "dense.fold_back", (accumulate ? 3.0 : 2.0) * (double)cbytes, s);
+      if (accumulate)
+        dense_permute_combine(sr, dt, id, tc.p, C->vals, (int)from.size(), fd.data(), perm.data(), s);
+      else
+        dense_permute(tc.p, C->vals, (int)dtype_size(dt), (int)from.size(), fd.data(), perm.data(), s);
+    };
     if (a_sparse && !b_sparse) {
       Folded fa;
       fold_sparse(c, sr, id, A, a, crow, acol, &fa, s);
       Buf tb;
       const void *Bd = dense_in_order(B, b, brow + p.N, &tb);
-      spmm(c, sr, dt, id, fa.view, Bd, extent(p, p.N), C->vals, accumulate, s);
+      product_into_c(crow + p.N, [&](void *out, int acc) {
+        spmm(c, sr, dt, id, fa.view, Bd, extent(p, p.N), out, acc, s);
+      });
       return;
     }
     if (!a_sparse && !b_sparse) {
       if (sr != SRTC_PLUS_TIMES) fail(SRTC_ERR_UNSUPPORTED, "dense x dense is defined for (+,x) only");
-      if (!p.batch.empty()) fail(SRTC_ERR_UNSUPPORTED, "dense x dense with a batch index");
+      // batched GEMM over (batch, M, K) x (batch, K, N) -> (batch, M, N)
       Buf ta, tb;
-      const void *Ad = dense_in_order(A, a, p.M + p.K, &ta);
-      const void *Bd = dense_in_order(B, b, p.K + p.N, &tb);
-      if (crow != p.M) fail(SRTC_ERR_UNSUPPORTED, "dense output row order");
-      {
+      const void *Ad = dense_in_order(A, a, p.batch + p.M + p.K, &ta);
+      const void *Bd = dense_in_order(B, b, p.batch + p.K + p.N, &tb);
+      const int64_t M_ = extent(p, p.M), N_ = extent(p, p.N), K_ = extent(p, p.K), Z_ = extent(p, p.batch);
+      product_into_c(p.batch + p.M + p.N, [&](void *out, int acc) {
         const double es = (double)dtype_size(dt);
-        const double M_ = (double)extent(p, p.M), N_ = (double)extent(p, p.N), K_ = (double)extent(p, p.K);
-        ProfScope ps(c, "dense.gemm_mfma", es * (M_ * K_ + K_ * N_ + M_ * N_ * (accumulate ? 2 : 1)), s);
-        dense_gemm_plus_times(c, dt, Ad, Bd, C->vals, extent(p, p.M), extent(p, p.N), extent(p, p.K), accumulate, s);
-      }
+        ProfScope ps(c, "dense.gemm_mfma",
+                     es * (double)Z_ * ((double)M_ * K_ + (double)K_ * N_ + (double)M_ * N_ * (acc ? 2 : 1)), s);
+        dense_gemm_plus_times(c, dt, Ad, Bd, out, M_, N_, K_, acc, s, Z_);
+      });
       return;
     }
     fail(SRTC_ERR_UNSUPPORTED, "dense A with sparse B: swap the operands");
@@ -671,6 +707,8 @@ srtc_status srtc_contract_masked(srtc_ctx *ctx, srtc_semiring sr, const void *ad
     const IdVal id = make_id(sr, dt, add_id);
     const Plan p = plan_contraction(a, A, b, B, cidx, C);
     if (!p.batch.empty()) fail(SRTC_ERR_UNSUPPORTED, "masked contraction: no index may appear in A, B and C");
+    if (rows_of_c(cidx, p) + p.N != cidx)
+      fail(SRTC_ERR_UNSUPPORTED, "masked contraction: C's index order interleaves row and column indices");
     for (size_t q = 0; q < cidx.size(); q++)
       if (M->dims[q] != p.dim.at(cidx[q])) fail(SRTC_ERR_DIM, "M: extents differ from C's");
     srtc_opts o{-1, 1, 0, 0};

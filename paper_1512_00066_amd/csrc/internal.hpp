@@ -173,10 +173,16 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
                  hipStream_t s);
 
 // --------------------------------------------------------------- dense --
+// C_z = A_z B_z (+ C_z with accumulate) for z < batch, each row-major and
+// the batches contiguous (strides MK, KN, MN).
 void dense_gemm_plus_times(Ctx *c, int dt, const void *A, const void *B, void *C, int64_t M,
-                           int64_t N, int64_t K, int accumulate, hipStream_t s);
+                           int64_t N, int64_t K, int accumulate, hipStream_t s, int64_t batch = 1);
+// dst mode q = src mode perm[q] (dims: src extents, last mode fastest).
 void dense_permute(const void *src, void *dst, int esize, int order, const int64_t *dims,
                    const int *perm, hipStream_t s);
+// The same with dst's previous values joining by the semiring's (+).
+void dense_permute_combine(int sr, int dt, IdVal id, const void *src, void *dst, int order,
+                           const int64_t *dims, const int *perm, hipStream_t s);
 
 // ------------------------------------------------------------- features --
 void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B, float *out,

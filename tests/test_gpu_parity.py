@@ -442,12 +442,18 @@ def test_error_statuses(ctx):
         (dict(ia="ik", ib="kj", ic="ixj"), -2),           # length / index only in output
         (dict(ia="ik", ib="lj", ic="ij"), -2),            # index only in one operand (reduction)
         (dict(ia="ik", ib="jk", ic="ij"), -3),            # extents of k differ
-        (dict(ia="ik", ib="kj", ic="ji"), -9),            # output interleaves... column before row
     ]
     for kw, st in cases:
         with pytest.raises(srtc.SrtcError) as e:
             ctx.contract("min_plus", kw["ia"], A, kw["ib"], B, kw["ic"])
         assert e.value.status == st, kw
+    # a column letter before a row letter in C is folded back, not refused
+    Ct = ctx.contract("min_plus", "ik", A, "kj", B, "ji")
+    assert tuple(Ct.dims) == (5, 3) and Ct.nnz == ctx.contract("min_plus", "ik", A, "kj", B, "ij").nnz
+    # ... but the masked form keeps C's rows first
+    with pytest.raises(srtc.SrtcError) as e:
+        ctx.contract_masked("min_plus", "ik", A, "kj", B, "ji", Ct)
+    assert e.value.status == -9
     F = gpu_fold(ctx, "plus_times", "f32", [0], [1], np.array([1], np.float32), 3, 4)
     with pytest.raises(srtc.SrtcError) as e:
         ctx.contract("min_plus", "ik", F, "kj", B, "ij")  # mixed value types

@@ -573,3 +573,57 @@ def test_path_product_pins():
     Bw = rng.integers(0, 50, (5, 6))
     Cw, Ch = oracle.path_product(Aw, 0 * Aw, Bw, 0 * Bw)
     assert np.array_equal(Cw, (Aw[:, :, None] + Bw[None, :, :]).min(axis=1)) and np.all(Ch == 0)
+
+
+# ------------------------------------------------------ tensor contraction --
+
+def dense_of_csr(M: "oracle.CSR", fill):
+    D = np.full((M.nrows, M.ncols), fill, dtype=np.asarray(M.val).dtype)
+    for i in range(M.nrows):
+        c, v = M.row(i)
+        D[i, c] = v
+    return D
+
+
+@pytest.mark.parametrize("semiring,dtype", [("plus_times", "f64"), ("min_plus", "i32"), ("or_and", "bool"),
+                                            ("max_times", "f64")])
+def test_contract_matrix_case_matches_spgemm(semiring, dtype):
+    # C["ij"] = A["ik"] B["kj"] is the matrix product of the oracle's SpGEMM
+    A = rand_matrix(semiring, dtype, 13, 9, 0.3, 5, 1)
+    B = rand_matrix(semiring, dtype, 9, 11, 0.3, 5, 2)
+    fill = identity_fill(semiring, dtype)
+    Ad, Bd = dense_of_csr(A, fill), dense_of_csr(B, fill)
+    C = oracle.contract(semiring, dtype, "ik", Ad, "kj", Bd, "ij")
+    ref = dense_of_csr(oracle.spgemm(semiring, dtype, A, B), fill)
+    if semiring == "plus_times":
+        assert np.allclose(C, ref, rtol=1e-14, atol=0)
+    else:
+        assert np.array_equal(C, ref)
+    # letter order is notation only: the transposed form gives C^T
+    Ct = oracle.contract(semiring, dtype, "kj", Bd, "ik", Ad, "ji")
+    assert np.array_equal(Ct, C.T) if semiring != "plus_times" else np.allclose(Ct, C.T, rtol=1e-14, atol=0)
+
+
+def test_contract_tensor_forms():
+    rng = np.random.default_rng(11)
+    V = rng.random((3, 4, 5, 2))
+    T = rng.random((5, 4, 4, 3))
+    # an interleaved output order, brute force over every index
+    Z = oracle.contract("plus_times", "f64", "amei", V, "ebmj", T, "abij")
+    ref = np.zeros((3, 4, 2, 3))
+    for a in range(3):
+        for b in range(4):
+            for i in range(2):
+                for j in range(3):
+                    ref[a, b, i, j] = sum(V[a, m, e, i] * T[e, b, m, j] for m in range(4) for e in range(5))
+    assert np.allclose(Z, ref, rtol=1e-14, atol=0)
+    # a letter in all three tensors is a batch: the Hadamard product
+    H = oracle.contract("plus_times", "f64", "abij", V[:, :, :2, :2], "abij", T[:3, :, :2, :2], "abij")
+    assert np.array_equal(H, V[:, :, :2, :2] * T[:3, :, :2, :2])
+    # no letter in C: the full contraction (a scalar)
+    E = oracle.contract("plus_times", "f64", "abcd", V, "abcd", V, "")
+    assert E.shape == () and np.isclose(E, (V * V).sum(), rtol=1e-14)
+    # (min,+) int32 with absent entries and clamping at the identity
+    W = np.array([[1, INT_INF], [INT_INF - 1, 2]], dtype=np.int32)
+    P = oracle.contract("min_plus", "i32", "ik", W, "kj", W, "ij")
+    assert P.tolist() == [[2, INT_INF], [INT_INF, 4]]
