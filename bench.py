@@ -685,6 +685,120 @@ def run_apsp2048(args):
     return out
 
 
+def run_mp3(args):
+    """The MP3 energy of Section 4.3 on a synthetic system (Section 6's MP3
+    experiment): m occupied and n virtual orbitals, the five integral
+    tensors 1% sparse (fp64, Bernoulli pattern), Fock blocks and amplitudes
+    dense.  A step = every contraction of the MP3 listing: T = V (.) D, Z =
+    Fab.T - Fij.T + Vabcd.T/2 + Vijkl.T/2 - Vaibj.T (three of them with their
+    outputs folded back, the last with T permuted), T += Z (.) D, and the
+    energy T.V.  The listing's scalar factors are folded into the synthetic
+    inputs; the copy Z = Vijab and the denominator D (broadcast sums and a
+    reciprocal) are inputs.  Ops = multiply-adds: nonzeros x dense extent
+    for sparse terms, M N K for dense ones, one per entry for elementwise."""
+    import torch
+    import oracle
+    import paper_1512_00066_amd as srtc
+    from gen import synth
+
+    ctx = srtc.Context(0)
+    m, n = args.mp3_m, args.mp3_n
+    seed = synth.SEED_CFG1
+    dens = 0.01
+
+    def sparse(dims, tag, scale=1.0):
+        keys = synth.bernoulli_keys(dims, dens, seed=seed, tag=tag)
+        vals = synth.edge_values("f64", keys.size, seed, tag) * scale
+        return srtc.COO(torch.as_tensor(keys, device="cuda"), torch.as_tensor(vals, device="cuda"), dims), keys, vals
+
+    def dense(dims, tag, lo=0.0, hi=1.0):
+        v = lo + (hi - lo) * synth.uniform_f64(synth.stream_key(seed, 200 + tag), int(np.prod(dims)))
+        return torch.as_tensor(v.reshape(dims), device="cuda")
+
+    log(f"generating MP3 tensors m={m} n={n} ...")
+    Vabij, _, _ = sparse((n, n, m, m), 1)
+    Vabcd, kabcd, vabcd = sparse((n, n, n, n), 2, 0.5)
+    Vijkl, _, _ = sparse((m, m, m, m), 3, 0.5)
+    Vaibj, _, _ = sparse((n, m, n, m), 4, -1.0)          # letters a m e i
+    Fab = dense((n, n), 5, -0.1, 0.1)
+    Fij = dense((m, m), 6, -0.1, 0.1)                    # -Fij folded in
+    ea = synth.uniform_f64(synth.stream_key(seed, 7), n) + 1.0    # virtual energies in [1, 2)
+    ei = synth.uniform_f64(synth.stream_key(seed, 8), m) - 2.0    # occupied energies in [-2, -1)
+    den = -ea[:, None, None, None] - ea[None, :, None, None] + ei[None, None, :, None] + ei[None, None, None, :]
+    D = torch.as_tensor(1.0 / den, device="cuda")
+    T = torch.empty((n, n, m, m), dtype=torch.float64, device="cuda")
+    Z = torch.empty_like(T)
+    E = torch.zeros((), dtype=torch.float64, device="cuda")
+    terms = []
+
+    def step():
+        ctx.contract("plus_times", "abij", Vabij, "abij", D, "abij", C=T)
+        ctx.contract("plus_times", "af", Fab, "fbij", T, "abij", C=Z)
+        ctx.contract("plus_times", "ni", Fij, "abnj", T, "abij", C=Z, accumulate=True)
+        ctx.contract("plus_times", "abef", Vabcd, "efij", T, "abij", C=Z, accumulate=True)
+        ctx.contract("plus_times", "mnij", Vijkl, "abmn", T, "abij", C=Z, accumulate=True)
+        ctx.contract("plus_times", "amei", Vaibj, "ebmj", T, "abij", C=Z, accumulate=True)
+        ctx.contract("plus_times", "abij", Z, "abij", D, "abij", C=T, accumulate=True)
+        ctx.contract("plus_times", "abij", Vabij, "abij", T, "", C=E)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    srtc.lib().srtc_profile_enable(ctx._h, 1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = profile_table(ctx)
+    srtc.lib().srtc_profile_enable(ctx._h, 0)
+    ms = (t1 - t0) * 1e3 / args.steps
+    nnz = {k: int(t.keys.numel()) for k, t in (("Vabij", Vabij), ("Vabcd", Vabcd), ("Vijkl", Vijkl),
+                                               ("Vaibj", Vaibj))}
+    dense_t = n * n * m * m
+    ops = (nnz["Vabij"] + n * n * (n * m * m) + m * m * (n * n * m) + nnz["Vabcd"] * m * m + nnz["Vijkl"] * n * n
+           + nnz["Vaibj"] * n * m + dense_t + nnz["Vabij"])
+    for r in prof:
+        log(f"  {r[0]:28s} launches {r[1] // args.steps:3d}/step  {r[2] / args.steps:8.3f} ms/step")
+    nm, cnt, tms, by = max(prof, key=lambda r: r[2])
+    if nm == "dense.gemm_mfma":
+        flops = 2.0 * (n * n * (n * m * m) + m * m * (n * n * m)) * args.steps
+        achieved, peak, unit, bound = flops / (tms / 1e3) / 1e12, 78.6, "TFLOP/s", "mfma"
+    else:
+        achieved, peak, unit, bound = (by / cnt) / (tms / cnt / 1e3) / 1e9, HBM_PEAK_GBS, "GB/s", "hbm"
+    log(f"mp3 m={m} n={n}: nnz {nnz}, E = {float(E.item()):.6e}, {ms:.2f} ms/step")
+    out = {"metric": METRIC, "value": ops / (ms / 1e3), "unit": "semiring-ops/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"mp3_m{m}_n{n}_1pct", "m": m, "n": n, "density": dens, "nnz": nnz,
+                      "ops_per_step": ops, "energy": float(E.item()),
+                      "kernels_ms_per_step": {r[0]: round(r[2] / args.steps, 4) for r in prof}},
+           "roofline": {"bound": bound, "kernel": nm, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                        "frac": round(achieved / peak, 4), "traffic": None, "avg_launch_ms": round(tms / cnt, 4)}}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        # the largest term, Vabcd["abef"] T["efij"], on random (a, b) rows
+        O = oracle.fold_tensor("plus_times", "f64", kabcd, vabcd, (n, n, n, n), "abef", "ab", "ef")
+        Tm = T.cpu().numpy().reshape(n * n, m * m)
+        rno = np.diff(O.rowptr)
+        perm = synth.permutation(synth.stream_key(seed, 79), n * n)
+        k, t_o, ops_o = 256, 0.0, 0.0
+        while t_o < args.cpu_seconds / 2 and k <= n * n:
+            rows = np.sort(perm[:k])
+            sub = oracle.CSR(np.concatenate([[0], np.cumsum(rno[rows])]),
+                             np.concatenate([O.col[O.rowptr[r]:O.rowptr[r + 1]] for r in rows]),
+                             np.concatenate([O.val[O.rowptr[r]:O.rowptr[r + 1]] for r in rows]), k, n * n)
+            t2 = time.perf_counter()
+            oracle.spmm("plus_times", "f64", sub, Tm)
+            t_o = time.perf_counter() - t2
+            ops_o = float(sub.nnz) * m * m
+            k *= 2
+        out["cpu_baseline"] = {"value": ops_o / t_o, "unit": "semiring-ops/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"Vabcd.T on {k // 2} random (a,b) rows "
+                               f"({int(ops_o)} multiply-adds); {t_o:.1f} s"}
+    return out
+
+
 def copy_calibration(args):
     """A plain device copy of known size (1 GiB read, 1 GiB written per
     launch), run under the same HBM counters as the kernels, to scale
@@ -706,7 +820,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512", "selector", "masked18",
-                                                               "apsp2048"])
+                                                               "apsp2048", "mp3"])
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
     ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -715,6 +829,8 @@ def main():
     ap.add_argument("--selector-matrices", type=int, default=2000)
     ap.add_argument("--selector-epochs", type=int, default=400)
     ap.add_argument("--apsp-n", type=int, default=2048, help="apsp2048: vertices of the dense graph")
+    ap.add_argument("--mp3-m", type=int, default=32, help="mp3: occupied orbitals")
+    ap.add_argument("--mp3-n", type=int, default=128, help="mp3: virtual orbitals")
     ap.add_argument("--changed-rows", action="store_true",
                     help="rmat20_sssp: fixpoint steps gather only from rows changed in the previous step")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -728,7 +844,8 @@ def main():
         copy_calibration(args)
         return
     out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512,
-           "selector": run_selector, "masked18": run_masked18, "apsp2048": run_apsp2048}[args.workload](args)
+           "selector": run_selector, "masked18": run_masked18, "apsp2048": run_apsp2048,
+           "mp3": run_mp3}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

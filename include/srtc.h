@@ -193,7 +193,9 @@ srtc_status srtc_fold(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const
  *       arrays stay the caller's).  Synchronizes once (output size).
  *   sparse A x dense B  -> dense C (caller-allocated, fully asynchronous).
  *   dense A x dense B   -> dense C, (+,x) only, on the matrix cores (a
- *       letter in all three tensors makes it a strided batch of GEMMs).
+ *       letter in all three tensors makes it a strided batch of GEMMs);
+ *       when every letter is in all three tensors, the elementwise
+ *       product, for any semiring.
  * Index rules: each letter appears at most once per tensor and in at least
  * two tensors.  Letters may come in any order in every tensor (Section
  * 5.1's folding): operands are folded or permuted to (rows, inner) and

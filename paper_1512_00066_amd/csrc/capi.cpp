@@ -670,6 +670,15 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
       });
       return;
     }
+    if (!a_sparse && !b_sparse && p.M.empty() && p.N.empty() && p.K.empty()) {
+      // every letter in all three tensors: the elementwise product, any semiring
+      Buf ta, tb;
+      const void *Ad = dense_in_order(A, a, cidx, &ta);
+      const void *Bd = dense_in_order(B, b, cidx, &tb);
+      ProfScope ps(c, "dense.hadamard", (accumulate ? 4.0 : 3.0) * (double)cbytes, s);
+      dense_hadamard(sr, dt, id, Ad, Bd, C->vals, prod_dims(C), accumulate, s);
+      return;
+    }
     if (!a_sparse && !b_sparse) {
       if (sr != SRTC_PLUS_TIMES) fail(SRTC_ERR_UNSUPPORTED, "dense x dense is defined for (+,x) only");
       // batched GEMM over (batch, M, K) x (batch, K, N) -> (batch, M, N)

@@ -205,7 +205,50 @@ template <class SR> void permute_combine_typed(const CombineCall &q) {
   SRTC_LAUNCH_CHECK("permute_combine_kernel");
 }
 
+// C = A (x) B elementwise, combined with C's previous value by (+) when
+// accumulating; identity operands give the identity.
+template <class SR>
+__global__ void hadamard_kernel(const typename SR::val_t *__restrict__ A, const typename SR::val_t *__restrict__ B,
+                                typename SR::val_t *__restrict__ C, int64_t n, int accumulate,
+                                typename SR::acc_t id) {
+  using Acc = typename SR::acc_t;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const auto a = A[e], b = B[e];
+    Acc acc = id;
+    if (!SR::absent(a, id) && !SR::absent(b, id)) acc = SR::mul(a, b);
+    if (accumulate) {
+      const auto y = C[e];
+      if (!SR::absent(y, id)) acc = SR::add(acc, (Acc)y);
+    }
+    C[e] = SR::out(acc);
+  }
+}
+
+struct HadamardCall {
+  IdVal id;
+  const void *A, *B;
+  void *C;
+  int64_t n;
+  int accumulate;
+  hipStream_t s;
+};
+
+template <class SR> void hadamard_typed(const HadamardCall &q) {
+  using V = typename SR::val_t;
+  const unsigned grid = (unsigned)std::min<int64_t>((q.n + 255) / 256, 65536);
+  hadamard_kernel<SR><<<grid, 256, 0, q.s>>>((const V *)q.A, (const V *)q.B, (V *)q.C, q.n, q.accumulate,
+                                             id_as<SR>(q.id));
+  SRTC_LAUNCH_CHECK("hadamard_kernel");
+}
+
 }  // namespace
+
+void dense_hadamard(int sr, int dt, IdVal id, const void *A, const void *B, void *C, int64_t n, int accumulate,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  HadamardCall q{id, A, B, C, n, accumulate, s};
+  SRTC_DISPATCH_SR(sr, dt, hadamard_typed, q);
+}
 
 void dense_permute_combine(int sr, int dt, IdVal id, const void *src, void *dst, int order, const int64_t *dims,
                            const int *perm, hipStream_t s) {

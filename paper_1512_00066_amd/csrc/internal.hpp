@@ -180,6 +180,10 @@ void dense_gemm_plus_times(Ctx *c, int dt, const void *A, const void *B, void *C
 // dst mode q = src mode perm[q] (dims: src extents, last mode fastest).
 void dense_permute(const void *src, void *dst, int esize, int order, const int64_t *dims,
                    const int *perm, hipStream_t s);
+// C = A (x) B elementwise over n entries ((+) with C's old values when
+// accumulating).
+void dense_hadamard(int sr, int dt, IdVal id, const void *A, const void *B, void *C, int64_t n, int accumulate,
+                    hipStream_t s);
 // The same with dst's previous values joining by the semiring's (+).
 void dense_permute_combine(int sr, int dt, IdVal id, const void *src, void *dst, int order,
                            const int64_t *dims, const int *perm, hipStream_t s);

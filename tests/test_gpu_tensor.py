@@ -176,3 +176,18 @@ def test_sparse_output_folded_back(ctx, semiring, dtype):
         check(got2, 2 * exp, dtype)
     else:
         assert np.array_equal(got2, exp)
+
+
+@pytest.mark.parametrize("semiring,dtype", [("plus_times", "f64"), ("plus_times", "f32"), ("min_plus", "i32")])
+def test_dense_elementwise_product(ctx, semiring, dtype):
+    """Every letter in all three dense tensors: the elementwise product
+    (the MP3 update T += Z (.) D), operands in other letter orders."""
+    say("dense hadamard", semiring, dtype)
+    Zt, Z_d = dense_tensor(semiring, dtype, (9, 11, 3, 5), 81, 1, absent=0.2 if semiring == "min_plus" else 0.0)
+    Dt, D_d = dense_tensor(semiring, dtype, (5, 3, 9, 11), 81, 2, absent=0.2 if semiring == "min_plus" else 0.0)
+    C0, C0_d = dense_tensor(semiring, dtype, (9, 11, 3, 5), 81, 3, absent=0.3 if semiring == "min_plus" else 0.0)
+    C = C0.clone()
+    ctx.contract(semiring, "abij", Zt, "jiab", Dt, "abij", C=C, accumulate=True)
+    P = oracle.contract(semiring, dtype, "abij", Z_d, "jiab", D_d, "abij")
+    exp = np.minimum(C0_d, P) if semiring == "min_plus" else C0_d.astype(np.float64) + P
+    check(C, exp, dtype)
