@@ -799,6 +799,88 @@ def run_mp3(args):
     return out
 
 
+def run_jacobi(args):
+    """Jacobi iteration (Section 4.1) on the 27-point stencil of a g^3 grid
+    (g = 128: 2.1M unknowns, 55.9M nonzeros, fp64; diagonal 27, neighbours
+    -1, so strictly diagonally dominant) with b uniform in [0, 1): a step =
+    fold of the COO matrix + the whole solve from x = 0 to |b - A x| <= 1e-8.
+    Ops = nonzeros per update (one multiply-add each)."""
+    import torch
+    import oracle
+    import paper_1512_00066_amd as srtc
+    from gen import synth
+
+    ctx = srtc.Context(0)
+    g = args.jacobi_g
+    n = g ** 3
+    log(f"generating the 27-point stencil g={g} ...")
+    src, dst = synth.stencil27_edges(g)
+    vals = np.where(src == dst, 27.0, -1.0)
+    b = synth.uniform_f64(synth.stream_key(synth.SEED_CFG4, 31), n)
+    coo = srtc.COO(torch.as_tensor(dst * n + src, device="cuda"), torch.as_tensor(vals, device="cuda"), (n, n))
+    bd = torch.as_tensor(b, device="cuda")
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    tol = 1e-8
+
+    def step():
+        x.zero_()
+        return ctx.jacobi(coo, bd, x, tol=tol, steps_per_check=32)
+
+    for _ in range(args.warmup):
+        it, r = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        it, r = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    # time per update from two capped solves (the difference cancels the
+    # fold and set-up)
+    A = ctx.fold("plus_times", coo, "ij", "i", "j")
+
+    def capped(cap):
+        x.zero_()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        try:
+            ctx.jacobi(A, bd, x, tol=0.0, max_iters=cap, steps_per_check=32)
+        except srtc.NotConverged:
+            pass
+        torch.cuda.synchronize()
+        return time.perf_counter() - ta
+
+    capped(64)
+    t_lo, t_hi = min(capped(64) for _ in range(3)), min(capped(576) for _ in range(3))
+    step_ms = (t_hi - t_lo) * 1e3 / 512
+    nnz = A.nnz
+    step_bytes = 12.0 * nnz + 8.0 * (n + 1) + 32.0 * n
+    achieved = step_bytes / (step_ms / 1e3) / 1e9
+    log(f"jacobi g={g}: n={n} nnz={nnz}, {it} updates to |r| = {r:.3e}, {ms:.2f} ms/solve, {step_ms * 1e3:.1f} us/update")
+    out = {"metric": METRIC, "value": float(it) * nnz / (ms / 1e3), "unit": "semiring-ops/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"jacobi_stencil27_g{g}", "n": n, "nnz": nnz, "tol": tol, "updates": it,
+                      "residual": r, "us_per_update": step_ms * 1e3},
+           "roofline": {"bound": "hbm", "kernel": "jacobi_step (graph-captured; from the time of 512 extra updates)",
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(step_ms, 4), "algorithmic_bytes_per_launch": round(step_bytes)}}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        O = oracle.fold("plus_times", "f64", dst, src, vals, n, n)
+        k, t_o = 2, 0.0
+        while t_o < args.cpu_seconds / 2:
+            t2 = time.perf_counter()
+            oracle.jacobi(O, b, np.zeros(n), 0.0, max_iters=k)
+            t_o = time.perf_counter() - t2
+            k *= 2
+        out["cpu_baseline"] = {"value": float(k // 2) * O.nnz / t_o, "unit": "semiring-ops/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"{k // 2} updates of the full system; {t_o:.1f} s"}
+    return out
+
+
 def copy_calibration(args):
     """A plain device copy of known size (1 GiB read, 1 GiB written per
     launch), run under the same HBM counters as the kernels, to scale
@@ -820,7 +902,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512", "selector", "masked18",
-                                                               "apsp2048", "mp3"])
+                                                               "apsp2048", "mp3", "jacobi"])
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
     ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -830,6 +912,7 @@ def main():
     ap.add_argument("--selector-epochs", type=int, default=400)
     ap.add_argument("--apsp-n", type=int, default=2048, help="apsp2048: vertices of the dense graph")
     ap.add_argument("--mp3-m", type=int, default=32, help="mp3: occupied orbitals")
+    ap.add_argument("--jacobi-g", type=int, default=128, help="jacobi: grid side of the 27-point stencil")
     ap.add_argument("--mp3-n", type=int, default=128, help="mp3: virtual orbitals")
     ap.add_argument("--changed-rows", action="store_true",
                     help="rmat20_sssp: fixpoint steps gather only from rows changed in the previous step")
@@ -845,7 +928,7 @@ def main():
         return
     out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512,
            "selector": run_selector, "masked18": run_masked18, "apsp2048": run_apsp2048,
-           "mp3": run_mp3}[args.workload](args)
+           "mp3": run_mp3, "jacobi": run_jacobi}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

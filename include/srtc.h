@@ -267,6 +267,54 @@ srtc_status srtc_fixpoint_ex(srtc_ctx *ctx, srtc_semiring sr, const void *add_id
 srtc_status srtc_bfs_levels(srtc_ctx *ctx, const srtc_tensor *A, const int64_t *sources,
                             int32_t nsrc, int32_t *levels, int32_t *depth_out, void *stream);
 
+/* ----------------------------------------------------------- transform -- */
+
+/* Elementwise transforms (Section 3.4's user-defined transforms, as a fixed
+ * set compiled into the library).  For every element c of C:
+ *   SRTC_TF_RECIP    c = alpha / c
+ *   SRTC_TF_SCALE    c = alpha * c
+ *   SRTC_TF_ADD      c = c + alpha * a
+ *   SRTC_TF_FMA      c = c + alpha * a * b
+ *   SRTC_TF_DIV_SUM  c = c / (a + b)     (the section's nested-loop example)
+ * where a = A[ia] and b = B[ib] at C's letters; A's and B's letters must be
+ * letters of C (each at most once; the same extents), and a letter of C
+ * missing from A or B broadcasts that operand along it, e.g.
+ * D["abij"] += Ei["i"] is (SRTC_TF_ADD, alpha = 1, "i", Ei, -, -, "abij", D).
+ * A and B are dense (NULL / index string ignored when the op does not use
+ * them).  C is dense, or, for RECIP and SCALE only, sparse (COO or CSR: its
+ * stored values are transformed, its pattern kept).  All of one value type,
+ * F64 or F32; arithmetic in that type.  C is updated in place; it may not
+ * overlap A or B.  Fully asynchronous. */
+typedef enum srtc_transform_op {
+  SRTC_TF_RECIP = 0,
+  SRTC_TF_SCALE = 1,
+  SRTC_TF_ADD = 2,
+  SRTC_TF_FMA = 3,
+  SRTC_TF_DIV_SUM = 4
+} srtc_transform_op;
+srtc_status srtc_transform(srtc_ctx *ctx, srtc_transform_op op, double alpha, const char *ia, const srtc_tensor *A,
+                           const char *ib, const srtc_tensor *B, const char *ic, srtc_tensor *C, void *stream);
+
+/* ------------------------------------------------------------- Jacobi -- */
+
+/* Jacobi iteration for A x = b (Section 4.1, with the listing's slips read
+ * as intended: the row sum skips the diagonal, the residual is b - A x):
+ *   x^{l+1}_i = (b_i - sum_{j != i} A_ij x^l_j) / A_ii
+ * from the caller's x^0 until |b - A x^l|_2 <= tol for some l >= 1 (at
+ * least one update, as the listing's do-while).  A: n x n CSR (split 1) or
+ * COO, F64 or F32; b, x: dense length-n vectors of the same type (device);
+ * x is overwritten with that x^l.  Each step is one fused kernel (row sum,
+ * update and the residual of the incoming iterate) plus a fixed-order
+ * reduction; steps are replayed as captured HIP graphs of
+ * `steps_per_check` steps and the host reads that many residual norms per
+ * replay.  *iters_out = l, *resid_out = |b - A x^l|_2 (host, may be NULL).
+ * Errors: SRTC_ERR_ARG if a row has no nonzero diagonal entry,
+ * SRTC_ERR_NOT_CONVERGED if no l <= max_iters (<= 0: 10,000) qualifies (x
+ * then holds x^max_iters).  Needs 3n values of scratch. */
+srtc_status srtc_jacobi(srtc_ctx *ctx, const srtc_tensor *A, const srtc_tensor *b, srtc_tensor *x, double tol,
+                        int64_t max_iters, int32_t steps_per_check, int64_t *iters_out, double *resid_out,
+                        void *stream);
+
 /* ---------------------------------------------------------------- apsp -- */
 
 /* All-pairs shortest paths by Tiskin's path doubling (Section 4.2, the

@@ -404,3 +404,57 @@ def contract(semiring, dtype, ia: str, A, ib: str, B, ic: str, add_id=None):
     if semiring == "min_plus" and dtype == "i32":
         out = np.minimum(out, ident)
     return out.astype(NP_DTYPES[dtype])
+
+
+def jacobi(A: CSR, b, x0, tol, max_iters=10000, dtype="f64"):
+    """Jacobi iteration for A x = b (Section 4.1, the listing read as
+    intended: the row sum skips the diagonal and the residual is b - A x):
+    x^{l+1} = (b - (A - diag) x^l) / diag, stored in the value type, until
+    |b - A x^l|_2 <= tol for some l >= 1.  Returns (x^l, l, |r|, converged);
+    without convergence x^max_iters and its residual."""
+    npt = NP_DTYPES[dtype]
+    b = np.asarray(b, dtype=npt)
+    x = np.array(x0, dtype=npt, copy=True)
+    n = A.nrows
+    rows = np.repeat(np.arange(n), np.diff(A.rowptr))
+    d = np.zeros(n, dtype=np.float64)
+    np.add.at(d, rows[A.col == rows], np.asarray(A.val, dtype=np.float64)[A.col == rows])
+    if np.any(d == 0):
+        raise ValueError("a row has no nonzero diagonal entry")
+    for l in range(1, max_iters + 1):
+        Ax, _ = spmm("plus_times", dtype, A, x[:, None])
+        s = Ax[:, 0] - d * x.astype(np.float64)
+        x = ((b.astype(np.float64) - s) / d).astype(npt)
+        Ax, _ = spmm("plus_times", dtype, A, x[:, None])
+        r = float(np.sqrt(np.sum((b.astype(np.float64) - Ax[:, 0]) ** 2)))
+        if r <= tol:
+            return x, l, r, True
+    return x, max_iters, r, False
+
+
+TRANSFORMS = ("recip", "scale", "add", "fma", "div_sum")
+
+
+def transform(op, alpha, ia, A, ib, B, ic, C):
+    """Elementwise transform of dense C (returns the new C): recip c =
+    alpha / c, scale c = alpha c, add c = c + alpha a, fma c = c + alpha a b,
+    div_sum c = c / (a + b), with a = A[ia] and b = B[ib] read at C's letters
+    (broadcast along letters they lack), Section 3.4."""
+    C = np.array(C, copy=True)
+
+    def at_c(T, idx):
+        T = np.asarray(T)
+        T = np.transpose(T, [idx.index(ch) for ch in ic if ch in idx])
+        return T.reshape([C.shape[q] if ch in idx else 1 for q, ch in enumerate(ic)])
+
+    if op == "recip":
+        return (C.dtype.type(alpha) / C).astype(C.dtype)
+    if op == "scale":
+        return (C.dtype.type(alpha) * C).astype(C.dtype)
+    a = at_c(A, ia).astype(C.dtype)
+    if op == "add":
+        return (C + C.dtype.type(alpha) * a).astype(C.dtype)
+    b = at_c(B, ib).astype(C.dtype)
+    if op == "fma":
+        return (C + C.dtype.type(alpha) * a * b).astype(C.dtype)
+    return (C / (a + b)).astype(C.dtype)

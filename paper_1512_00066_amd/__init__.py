@@ -28,6 +28,7 @@ SEMIRINGS = {"plus_times": PLUS_TIMES, "min_plus": MIN_PLUS, "or_and": OR_AND, "
 F64, F32, I32, BOOL8, BITS64, PATH64 = 0, 1, 2, 3, 4, 5
 DENSE, COO_FMT, CSR_FMT = 0, 1, 2
 NUM_SCHEDULES = 8
+TRANSFORMS = {"recip": 0, "scale": 1, "add": 2, "fma": 3, "div_sum": 4}
 NUM_FEATURES = 32
 
 # int64 values are packed paths (weight << 32 | hops) for the (min,+) semiring
@@ -103,6 +104,9 @@ def lib():
             "srtc_contract_masked": ([P, ctypes.c_int, P, S, T, S, T, S, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
             "srtc_bfs_levels": ([P, T, ctypes.POINTER(I64_), I32_, P, ctypes.POINTER(I32_), P], ctypes.c_int),
             "srtc_apsp_tiskin": ([P, P, T, P, P, ctypes.POINTER(I32_), ctypes.POINTER(I64_), P], ctypes.c_int),
+            "srtc_transform": ([P, ctypes.c_int, ctypes.c_double, S, T, S, T, S, T, P], ctypes.c_int),
+            "srtc_jacobi": ([P, T, T, T, ctypes.c_double, I64_, I32_, ctypes.POINTER(I64_),
+                             ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
             "srtc_batch_contract": ([P, ctypes.c_int, P, I32_, T, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
             "srtc_batch_fixpoint": ([P, ctypes.c_int, P, I32_, T, T, I64_, I32_, ctypes.POINTER(I64_), P],
                                     ctypes.c_int),
@@ -390,6 +394,35 @@ class Context:
                                    int(src.size), _ptr(levels), ctypes.byref(depth), self._stream())
         self._check(st)
         return levels, depth.value
+
+    def transform(self, op: str, C, A=None, ia: str = "", B=None, ib: str = "", ic: Optional[str] = None,
+                  alpha: float = 1.0):
+        """Elementwise transform of C in place (op: recip, scale, add, fma,
+        div_sum; see srtc_transform); A and B broadcast over C's letters."""
+        cd = _desc(C)
+        ad = _desc(A) if A is not None else None
+        bd = _desc(B) if B is not None else None
+        if ic is None:
+            ic = "abcdefgh"[:cd.order]
+        st = lib().srtc_transform(self._h, TRANSFORMS[op], float(alpha), ia.encode(),
+                                  ctypes.byref(ad) if ad is not None else None, ib.encode(),
+                                  ctypes.byref(bd) if bd is not None else None, ic.encode(), ctypes.byref(cd),
+                                  self._stream())
+        self._check(st)
+        return C
+
+    def jacobi(self, A, b: torch.Tensor, x: torch.Tensor, tol: float = 1e-6, max_iters: int = 0,
+               steps_per_check: int = 8):
+        """Jacobi iteration for A x = b from x (updated in place); returns
+        (updates, residual norm)."""
+        ad, bd, xd = _desc(A), _desc(b), _desc(x)
+        it = ctypes.c_int64(0)
+        rr = ctypes.c_double(0.0)
+        st = lib().srtc_jacobi(self._h, ctypes.byref(ad), ctypes.byref(bd), ctypes.byref(xd), float(tol),
+                               int(max_iters), int(steps_per_check), ctypes.byref(it), ctypes.byref(rr),
+                               self._stream())
+        self._check(st, it.value)
+        return it.value, rr.value
 
     def apsp_tiskin(self, A, add_id=None, hops: bool = True, round_nnz: Optional[list] = None):
         """All-pairs lightest paths by path doubling: (D, H or None, rounds).

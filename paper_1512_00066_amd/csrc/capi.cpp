@@ -897,6 +897,139 @@ srtc_status srtc_bfs_levels(srtc_ctx *ctx, const srtc_tensor *A, const int64_t *
   });
 }
 
+srtc_status srtc_transform(srtc_ctx *ctx, srtc_transform_op op, double alpha, const char *ia, const srtc_tensor *A,
+                           const char *ib, const srtc_tensor *B, const char *ic, srtc_tensor *C, void *stream) {
+  return guard(ctx, [&] {
+    if (op < SRTC_TF_RECIP || op > SRTC_TF_DIV_SUM) fail(SRTC_ERR_ARG, "unknown transform");
+    check_tensor(C, "C");
+    if (C->dtype != SRTC_F64 && C->dtype != SRTC_F32) fail(SRTC_ERR_DTYPE, "transforms are defined for F64 and F32");
+    const bool need_a = op == SRTC_TF_ADD || op == SRTC_TF_FMA || op == SRTC_TF_DIV_SUM;
+    const bool need_b = op == SRTC_TF_FMA || op == SRTC_TF_DIV_SUM;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    const std::string cidx = letters(ic, C, "C");
+    int64_t zero = 0;
+    if (C->format != SRTC_DENSE) {
+      if (need_a || need_b) fail(SRTC_ERR_UNSUPPORTED, "a sparse C takes RECIP and SCALE only");
+      int64_t nv = C->nnz;
+      transform_dense_call(op, C->dtype, alpha, &nv, 1, nullptr, &zero, nullptr, &zero, C->vals, s);
+      return;
+    }
+    const int order = C->order;
+    std::vector<int64_t> ext(std::max(order, 1), 1), sa(std::max(order, 1), 0), sb(std::max(order, 1), 0);
+    for (int q = 0; q < order; q++) ext[q] = C->dims[q];
+    const size_t cbytes = tensor_value_bytes(C);
+    auto strides = [&](const srtc_tensor *T, const char *idx, const char *name, std::vector<int64_t> &st) {
+      check_tensor(T, name);
+      if (T->format != SRTC_DENSE) fail(SRTC_ERR_FORMAT, std::string(name) + ": must be dense");
+      if (T->dtype != C->dtype) fail(SRTC_ERR_DTYPE, std::string(name) + ": value type differs from C's");
+      const std::string l = letters(idx, T, name);
+      std::vector<int64_t> ts(T->order);
+      int64_t acc = 1;
+      for (int q = T->order - 1; q >= 0; q--) {
+        ts[q] = acc;
+        acc *= T->dims[q];
+      }
+      for (size_t q = 0; q < l.size(); q++) {
+        const size_t pos = cidx.find(l[q]);
+        if (pos == std::string::npos) fail(SRTC_ERR_INDEX, std::string(name) + ": a letter missing from C");
+        if (T->dims[q] != C->dims[pos]) fail(SRTC_ERR_DIM, std::string(name) + ": extent differs from C's");
+        st[pos] = ts[q];
+      }
+      if (overlaps(C->vals, cbytes, T->vals, tensor_value_bytes(T))) fail(SRTC_ERR_ALIAS, "C overlaps an operand");
+      return (const void *)T->vals;
+    };
+    const void *Ap = need_a ? strides(A, ia, "A", sa) : nullptr;
+    const void *Bp = need_b ? strides(B, ib, "B", sb) : nullptr;
+    ProfScope ps(&ctx->c, "transform", 2.0 * (double)cbytes, s);
+    transform_dense_call(op, C->dtype, alpha, ext.data(), order, Ap, sa.data(), Bp, sb.data(), C->vals, s);
+  });
+}
+
+srtc_status srtc_jacobi(srtc_ctx *ctx, const srtc_tensor *A, const srtc_tensor *b, srtc_tensor *x, double tol,
+                        int64_t max_iters, int32_t steps_per_check, int64_t *iters_out, double *resid_out,
+                        void *stream) {
+  return guard(ctx, [&] {
+    check_tensor(A, "A");
+    check_tensor(b, "b");
+    check_tensor(x, "x");
+    if (A->order != 2 || A->format == SRTC_DENSE) fail(SRTC_ERR_FORMAT, "A must be a sparse matrix (COO or CSR)");
+    const int64_t n = A->dims[0];
+    if (A->dims[1] != n) fail(SRTC_ERR_DIM, "A must be square");
+    const int dt = A->dtype;
+    if (dt != SRTC_F64 && dt != SRTC_F32) fail(SRTC_ERR_DTYPE, "Jacobi is defined for F64 and F32");
+    for (const srtc_tensor *v : {b, (const srtc_tensor *)x}) {
+      if (v->format != SRTC_DENSE || v->order != 1) fail(SRTC_ERR_FORMAT, "b and x must be dense vectors");
+      if (v->dims[0] != n) fail(SRTC_ERR_DIM, "b and x must have n entries");
+      if (v->dtype != dt) fail(SRTC_ERR_DTYPE, "b and x must have A's value type");
+    }
+    if (!(tol >= 0.0)) fail(SRTC_ERR_ARG, "tol must be >= 0");
+    if (overlaps(x->vals, tensor_value_bytes(x), b->vals, tensor_value_bytes(b))) fail(SRTC_ERR_ALIAS, "x overlaps b");
+    if (max_iters <= 0) max_iters = 10000;
+    int k = std::max(2, (int)steps_per_check);
+    if (k % 2) k++;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    Ctx *c = &ctx->c;
+    Folded fa;
+    fold_sparse(c, SRTC_PLUS_TIMES, IdVal{0.0, 0}, A, "ij", "i", "j", &fa, s);
+    JacobiPlan pl;
+    pl.build(c, dt, fa.view, s);
+    const size_t bytes = dtype_size(dt) * (size_t)std::max<int64_t>(n, 1);
+    Buf xb(c, bytes), stb(c, 64);
+    fill_i32(stb.as<int32_t>(), 16, 0, s);  // iter = 0, not done
+    JacobiState *st = reinterpret_cast<JacobiState *>(stb.p);
+    void *bufs[2] = {x->vals, xb.p};
+    const double tol2 = tol * tol;
+    auto step = [&](int t, hipStream_t q) { jacobi_step_call(pl, b->vals, bufs[t & 1], bufs[(t & 1) ^ 1], st, tol2, q); };
+    JacobiState hs{};
+    if (n > 0) {
+      // k steps per replay; after the stopping step the rest do nothing,
+      // so x^l stays in buffer l & 1 (each replay has an even count)
+      hipStream_t cap;
+      SRTC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      struct Cleanup {
+        hipStream_t *cap;
+        hipGraph_t *g;
+        hipGraphExec_t *e;
+        ~Cleanup() {
+          if (*e) (void)hipGraphExecDestroy(*e);
+          if (*g) (void)hipGraphDestroy(*g);
+          (void)hipStreamDestroy(*cap);
+        }
+      } cleanup{&cap, &graph, &exec};
+      SRTC_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      for (int t = 0; t < k; t++) step(t, cap);
+      SRTC_HIP(hipStreamEndCapture(cap, &graph));
+      SRTC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      int64_t ran = 0;  // steps issued; the last one checks x^{ran-1}
+      while (true) {
+        if (ran + k <= max_iters + 1) {
+          SRTC_HIP(hipGraphLaunch(exec, s));
+          ran += k;
+        } else {
+          // the remaining steps one by one, parity continuing from `ran`
+          const int64_t left = max_iters + 1 - ran;
+          for (int64_t t = 0; t < left; t++) step((int)((ran + t) & 1), s);
+          ran += left;
+        }
+        read_to_host(c, &hs, st, sizeof(hs), s);
+        if (hs.done || ran >= max_iters + 1) break;
+      }
+      const int64_t l = hs.done ? hs.iter : max_iters;
+      if (l & 1) SRTC_HIP(hipMemcpyAsync(x->vals, xb.p, bytes, hipMemcpyDeviceToDevice, s));
+      if (iters_out) *iters_out = l;
+      if (resid_out) *resid_out = std::sqrt(hs.rsq);
+      if (!hs.done) fail(SRTC_ERR_NOT_CONVERGED, "residual above tol after max_iters updates");
+    } else {
+      if (iters_out) *iters_out = 0;
+      if (resid_out) *resid_out = 0.0;
+    }
+  });
+}
+
 srtc_status srtc_apsp_tiskin(srtc_ctx *ctx, const void *add_id, const srtc_tensor *A, int32_t *D, int32_t *H,
                              int32_t *rounds_out, int64_t *round_nnz, void *stream) {
   return guard(ctx, [&] {

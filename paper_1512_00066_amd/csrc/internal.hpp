@@ -188,6 +188,40 @@ void dense_hadamard(int sr, int dt, IdVal id, const void *A, const void *B, void
 void dense_permute_combine(int sr, int dt, IdVal id, const void *src, void *dst, int order,
                            const int64_t *dims, const int *perm, hipStream_t s);
 
+// ------------------------------------------------------------ transform --
+// C (dense, order `order`, extents cext) updated elementwise by transform
+// `op` (srtc_transform_op) with A and B read at stride sa[q] / sb[q] along
+// C's mode q (0 broadcasts; A or B may be null when the op ignores it).
+void transform_dense_call(int op, int dt, double alpha, const int64_t *cext, int order, const void *A,
+                          const int64_t *sa, const void *B, const int64_t *sb, void *C, hipStream_t s);
+
+// Jacobi iteration on an n x n CSR A: the inverse-free diagonal d, the
+// lanes per row and the fixed grid whose per-block residual partials are
+// summed in a fixed order.
+struct JacobiPlan {
+  Ctx *ctx = nullptr;
+  int dt = SRTC_F64;
+  CsrView A;
+  int G = 32;
+  int grid = 1;
+  Buf dbuf, part;
+  // fails with SRTC_ERR_ARG when a row has no nonzero diagonal entry
+  void build(Ctx *c, int dt, const CsrView &A, hipStream_t s);
+};
+// Device state of a Jacobi solve: iter = l of the current iterate x^l,
+// done = 1 once |b - A x^l|^2 <= tol^2 with l >= 1 (rsq = that value; while
+// running, the last residual formed).
+struct JacobiState {
+  int64_t iter;
+  int32_t done;
+  int32_t pad;
+  double rsq;
+};
+// Unless st->done: x_out = (b - (A - diag) x_in) / diag, then the residual
+// of x_in decides whether to stop (x_in kept) or advance st->iter.
+void jacobi_step_call(const JacobiPlan &pl, const void *b, const void *x_in, void *x_out, JacobiState *st,
+                      double tol2, hipStream_t s);
+
 // ------------------------------------------------------------- features --
 void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B, float *out,
                      hipStream_t s);

@@ -627,3 +627,61 @@ def test_contract_tensor_forms():
     W = np.array([[1, INT_INF], [INT_INF - 1, 2]], dtype=np.int32)
     P = oracle.contract("min_plus", "i32", "ik", W, "kj", W, "ij")
     assert P.tolist() == [[2, INT_INF], [INT_INF, 4]]
+
+
+# ------------------------------------------------- Jacobi and transforms --
+
+def test_jacobi_closed_forms():
+    # diagonal A: one update solves it exactly
+    n = 5
+    d = np.arange(1, n + 1, dtype=np.float64)
+    A = oracle.fold("plus_times", "f64", np.arange(n), np.arange(n), d, n, n)
+    x, l, r, ok = oracle.jacobi(A, np.ones(n), np.zeros(n), 1e-14)
+    assert ok and l == 1 and r == 0.0 and np.array_equal(x, 1.0 / d)
+    # 2 x 2 by hand: A = [[4, 1], [2, 5]], b = [1, 2], x0 = 0
+    A = oracle.fold("plus_times", "f64", [0, 0, 1, 1], [0, 1, 0, 1], np.array([4.0, 1, 2, 5]), 2, 2)
+    x1, l1, _, ok1 = oracle.jacobi(A, [1.0, 2.0], [0.0, 0.0], 0.0, max_iters=1)
+    x2, l2, _, ok2 = oracle.jacobi(A, [1.0, 2.0], [0.0, 0.0], 0.0, max_iters=2)
+    assert not ok1 and not ok2 and l1 == 1 and l2 == 2
+    assert np.allclose(x1, [0.25, 0.4], rtol=1e-15) and np.allclose(x2, [0.15, 0.3], rtol=1e-15)
+    with pytest.raises(ValueError):
+        oracle.jacobi(oracle.fold("plus_times", "f64", [0], [1], np.array([1.0]), 2, 2), [1.0, 1.0], [0.0, 0.0], 1e-6)
+
+
+def test_jacobi_converges_to_the_solution():
+    g = 6
+    src, dst = synth.stencil27_edges(g)
+    n = g ** 3
+    vals = np.where(src == dst, 27.0, -1.0)
+    A = oracle.fold("plus_times", "f64", dst, src, vals, n, n)
+    b = synth.uniform_f64(synth.stream_key(3, 1), n)
+    x, l, r, ok = oracle.jacobi(A, b, np.zeros(n), 1e-10)
+    Ad = np.zeros((n, n))
+    Ad[dst, src] = vals
+    assert ok and r <= 1e-10 and np.allclose(x, np.linalg.solve(Ad, b), rtol=0, atol=1e-10)
+    # the residual decreases by at most the Jacobi iteration's contraction
+    assert l > 1
+
+
+def test_transform_pins():
+    rng = np.random.default_rng(5)
+    C = rng.random((3, 4, 2, 5)) + 1.0
+    Ei = rng.random(2)
+    Ea = rng.random(3)
+    # D["abij"] += Ei["i"]; D["abij"] -= Ea["a"] as nested loops
+    D1 = oracle.transform("add", 1.0, "i", Ei, "", None, "abij", C)
+    D2 = oracle.transform("add", -1.0, "a", Ea, "", None, "abij", D1)
+    ref = C.copy()
+    for a in range(3):
+        for bb in range(4):
+            for i in range(2):
+                for j in range(5):
+                    ref[a, bb, i, j] = C[a, bb, i, j] + Ei[i] - Ea[a]
+    assert np.allclose(D2, ref, rtol=1e-15)
+    # C["ij"] = C["ij"] / (A["i"] + B["j"])
+    M = rng.random((4, 6)) + 1
+    va, vb = rng.random(4), rng.random(6)
+    out = oracle.transform("div_sum", 0.0, "i", va, "j", vb, "ij", M)
+    assert np.array_equal(out, M / (va[:, None] + vb[None, :]))
+    assert np.array_equal(oracle.transform("recip", 2.0, "", None, "", None, "ij", M), 2.0 / M)
+    assert np.array_equal(oracle.transform("fma", 0.5, "ji", M.T, "ij", M, "ij", M), M + 0.5 * M * M)
