@@ -106,17 +106,33 @@ __global__ void __launch_bounds__(256) jacobi_step(const int64_t *__restrict__ r
   // the G lanes of a row are one aligned lane group, so the shuffles below
   // stay inside lanes that take the same trips
   for (int64_t i = grp; i < n; i += ngrp) {
+    // the row's own terms first, so their loads overlap the row sum
+    const double bi = sub == 0 ? (double)b[i] : 0.0, di = sub == 0 ? (double)d[i] : 0.0;
+    const double xi = sub == 0 ? (double)x_in[i] : 0.0;
+    const int64_t p1 = rp[i + 1];
     double s = 0.0;
-    for (int64_t p = rp[i] + sub; p < rp[i + 1]; p += G) {
-      const int32_t j = col[p];
-      if (j != i) s += (double)val[p] * (double)x_in[j];
+    // four entries per lane per pass, all loads issued before the sums;
+    // padding uses column i, which the diagonal test skips
+    for (int64_t p = rp[i] + sub; p < p1; p += 4 * G) {
+      int32_t j[4];
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const bool ok = p + u * G < p1;
+        j[u] = ok ? col[p + u * G] : (int32_t)i;
+        v[u] = ok ? val[p + u * G] : (T)0;
+      }
+      double xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) xv[u] = j[u] != i ? (double)x_in[j[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; u++) s += (double)v[u] * xv[u];
     }
 #pragma unroll
     for (int w = G / 2; w >= 1; w >>= 1) s += __shfl_xor(s, w, G);
     if (sub == 0) {
-      const double bi = (double)b[i], di = (double)d[i];
       x_out[i] = (T)((bi - s) / di);
-      const double r = bi - s - di * (double)x_in[i];
+      const double r = bi - s - di * xi;
       rr += r * r;
     }
   }
@@ -176,9 +192,11 @@ void JacobiPlan::build(Ctx *c, int dt_, const CsrView &A_, hipStream_t s) {
   A = A_;
   const int64_t n = A.m;
   const double avg = n > 0 ? (double)A.nnz / (double)n : 1.0;
+  // about four nonzeros per lane: more rows in flight per wave hides the
+  // dependent loads of a row (row pointer, then columns, then x)
   G = 4;
-  while (G < 64 && G < avg) G <<= 1;
-  grid = (int)std::max<int64_t>(1, std::min<int64_t>((n * G + 255) / 256, 2048));
+  while (G < 64 && 4 * G < avg) G <<= 1;
+  grid = (int)std::max<int64_t>(1, std::min<int64_t>((n * G + 255) / 256, 16384));
   const size_t es = dtype_size(dt);
   dbuf = Buf(c, es * (size_t)std::max<int64_t>(n, 1));
   part = Buf(c, sizeof(double) * (size_t)grid);
