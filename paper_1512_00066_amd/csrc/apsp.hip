@@ -335,8 +335,11 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
   const uint64_t idv = (uint64_t)(uint32_t)idw << 32;
   const int64_t total = n * n;
   Buf pa(c, sizeof(uint64_t) * (size_t)std::max<int64_t>(total, 1)), pb(c, sizeof(uint64_t) * (size_t)std::max<int64_t>(total, 1));
-  Buf bad(c, 64);
-  fill_i32(bad.as<int32_t>(), 1, 0, s);
+  // info[0] = value range, info[1] = count of l-hop paths (both per round),
+  // info[2] = negative-weight flag (read with the first round's info)
+  Buf info_b(c, 64);
+  fill_i32(info_b.as<int32_t>(), 16, 0, s);
+  int32_t *bad = reinterpret_cast<int32_t *>(info_b.as<int64_t>() + 2);
   uint64_t *P = pa.as<uint64_t>(), *Pn = pb.as<uint64_t>();
   {
     ProfScope ps(c, "apsp.init", 8.0 * (double)total, s);
@@ -345,13 +348,15 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
   SRTC_LAUNCH_CHECK("apsp_init");
   if (A.nnz > 0) {
     ProfScope ps(c, "apsp.edges", 12.0 * (double)A.nnz + 8.0 * (double)(n + 1), s);
-    apsp_edges<<<grid_of(n * WAVE), 256, 0, s>>>(A.rowptr, A.col, (const int32_t *)A.val, n, idw, P,
-                                                 bad.as<int32_t>());
+    apsp_edges<<<grid_of(n * WAVE), 256, 0, s>>>(A.rowptr, A.col, (const int32_t *)A.val, n, idw, P, bad);
     SRTC_LAUNCH_CHECK("apsp_edges");
   }
-  int32_t neg = 0;
-  read_to_host(c, &neg, bad.p, sizeof(neg), s);
-  if (neg) fail(SRTC_ERR_ARG, "apsp: negative edge weight");
+  if (n < 2) {
+    // no round runs: check the weights here
+    int32_t neg = 0;
+    read_to_host(c, &neg, bad, sizeof(neg), s);
+    if (neg) fail(SRTC_ERR_ARG, "apsp: negative edge weight");
+  }
   const IdVal id{0.0, (int64_t)idw};
   Buf cnt(c, sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)), rp(c, sizeof(int64_t) * (size_t)(n + 1));
   // per-block ranges (hops_count's grid or a dense round's tiles) and the
@@ -359,7 +364,7 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
   constexpr int DTM = 64, DTN = 64, DTK = 32;
   const int64_t cnt_blocks = std::min<int64_t>(grid_of(n * WAVE), 1024);
   const int64_t tiles = ((n + DTM - 1) / DTM) * ((n + DTN - 1) / DTN);
-  Buf part(c, 8 * (size_t)std::max<int64_t>({cnt_blocks, tiles, 1})), info_b(c, 64);
+  Buf part(c, 8 * (size_t)std::max<int64_t>({cnt_blocks, tiles, 1}));
   bool counted = false;  // the previous dense round already counted this round's paths
   int32_t r = 0;
   if (round_nnz) std::fill(round_nnz, round_nnz + 64, (int64_t)0);
@@ -376,8 +381,9 @@ void apsp_tiskin(Ctx *c, const CsrView &A, int32_t idw, int32_t *D, int32_t *H, 
     // one read per round: the value range and the count of l-hop paths
     range_reduce<<<1, 256, 0, s>>>(part.as<uint32_t>(), nparts, rp.as<int64_t>() + n, info_b.as<int64_t>());
     SRTC_LAUNCH_CHECK("range_reduce");
-    int64_t info[2];
+    int64_t info[3];
     read_to_host(c, info, info_b.p, sizeof(info), s);
+    if (r == 0 && (int32_t)info[2]) fail(SRTC_ERR_ARG, "apsp: negative edge weight");
     const int64_t nnz = info[1];
     const uint32_t wmax = (uint32_t)info[0], hmax = (uint32_t)((uint64_t)info[0] >> 32);
     c->tracef("apsp: round %d, %lld paths of %lld hops", r, (long long)nnz, (long long)l);
