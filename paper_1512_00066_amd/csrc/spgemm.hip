@@ -353,6 +353,7 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
                                                  int bin, const int64_t *__restrict__ rpA,
                                                  const int32_t *__restrict__ cA, const int64_t *__restrict__ rpB,
                                                  const int32_t *__restrict__ cB, int64_t ncols, int32_t wwords,
+                                                 const int32_t *__restrict__ woff, int nwin,
                                                  int64_t *__restrict__ nnz_row, int64_t *ctr) {
   extern __shared__ uint32_t bits[];
   __shared__ Chunk<BS, uint8_t> L;
@@ -363,11 +364,13 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
   for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
     const int64_t i = rows[r];
     int64_t mine = 0;
-    for (int64_t w0 = 0; w0 < ncols; w0 += wcols) {
+    for (int64_t w0 = 0, wi = 0; w0 < ncols; w0 += wcols, wi++) {
       for (int s = threadIdx.x; s < wwords; s += BS) bits[s] = 0;
       __syncthreads();
+      // with several windows, the window table limits each pass to its own
+      // products (each product is walked once over all passes)
       for_products<BS, false, uint8_t>(rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr, i,
-                                       nullptr, 0, 0, L, [&](int32_t j, uint8_t, uint8_t) {
+                                       nwin > 1 ? woff : nullptr, nwin, (int)wi, L, [&](int32_t j, uint8_t, uint8_t) {
         const int64_t jj = (int64_t)j - w0;
         if (jj >= 0 && jj < wcols) atomicOr(&bits[jj >> 5], 1u << (jj & 31));
       });
@@ -986,11 +989,20 @@ int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, cons
     constexpr int BS = 256;
     const int stat = (int)sizeof(Chunk<BS, uint8_t>) + 64;
     const int32_t ww = bitmap_words(n, BS, LDS_BYTES - stat - 1024);
+    const int64_t wcols = (int64_t)ww * 32;
+    const int nwin = (int)((n + wcols - 1) / wcols);
+    Buf woff;
+    if (nwin > 1) {
+      woff = Buf(L.c, sizeof(int32_t) * (size_t)(Bm.m * (nwin + 1)));
+      build_woff<<<gridn(Bm.m * (nwin + 1)), 256, 0, s>>>(Bm.rowptr, Bm.col, Bm.m, nwin, wcols, woff.as<int32_t>());
+      SRTC_LAUNCH_CHECK("build_woff");
+    }
     auto kern = sym_bitmap<BS>;
     if (ww * 4 > 64 * 1024)
       SRTC_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, ww * 4));
     kern<<<L.grid(hinfo[5], stat + ww * 4, BS), BS, (size_t)ww * 4, s>>>(list, info1, 5, Am.rowptr, Am.col,
-                                                                      Bm.rowptr, Bm.col, n, ww, nnz_row, ctr1 + 5);
+                                                                      Bm.rowptr, Bm.col, n, ww, woff.as<int32_t>(),
+                                                                      nwin, nnz_row, ctr1 + 5);
     SRTC_LAUNCH_CHECK("sym_bitmap");
   }
   return hinfo[4 * NBIN];

@@ -176,3 +176,28 @@ def test_apsp_tiskin_dense2048_sampled():
         exp[j] = 0
         assert np.array_equal(H[:, j], exp)
     assert rounds == len(rn) and rn[0] == n * (n - 1) and 1 << (rounds - 1) <= H.max() <= 1 << rounds
+
+
+@pytest.mark.parametrize("semiring,dtype", [("min_plus", "i32"), ("plus_times", "f64")])
+def test_spgemm_wide_matrix_multiwindow_symbolic(semiring, dtype):
+    """2.5M columns: heavy rows count their outputs over several LDS bitmap
+    windows (each walking only its own products through the window table)
+    and accumulate over several dense windows; every schedule, all rows."""
+    n, m = 2_500_000, 48
+    say("wide spgemm", semiring, dtype)
+    src, dst = synth.er_edges(n, 4, seed=88)
+    wB = synth.edge_values("i32" if dtype == "i32" else dtype, src.size, 88, lo=1, hi=100)
+    ka = synth.bernoulli_keys((m, n), 3000 / n, seed=89)
+    wA = synth.edge_values("i32" if dtype == "i32" else dtype, ka.size, 89, lo=1, hi=100)
+    ctx = srtc.Context(0)
+    B = ctx.fold(semiring, srtc.COO(torch.as_tensor(dst * n + src, device="cuda"), torch.as_tensor(wB, device="cuda"),
+                                    (n, n)), "ij", "i", "j")
+    A = ctx.fold(semiring, srtc.COO(torch.as_tensor(ka, device="cuda"), torch.as_tensor(wA, device="cuda"), (m, n)),
+                 "ij", "i", "j")
+    Bo = oracle.fold(semiring, dtype, dst, src, wB, n, n)
+    Ao = oracle.fold(semiring, dtype, ka // n, ka % n, wA, m, n)
+    exp = oracle.spgemm(semiring, dtype, Ao, Bo)
+    for sched in range(srtc.NUM_SCHEDULES):
+        say("  schedule", sched)
+        C = ctx.contract(semiring, "ik", A, "kj", B, "ij", schedule=sched)
+        check_csr(C, exp, semiring, dtype)
