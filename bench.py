@@ -418,8 +418,10 @@ def run_batch512(args):
 def run_selector(args):
     """Learned schedule selection.  Training set: ``--selector-matrices``
     generated matrices (ER, R-MAT, 27-point stencil, power-law rows), each as
-    (+,x) fp32 and (min,+) int32 A.A, every schedule timed by the exhaustive
-    tuner; the MLP is trained on the GPU.  Held out: a row panel of R-MAT
+    (+,x) fp32 and (min,+) int32 A.A, plus ``--selector-panels`` row panels
+    (2^10-2^14 random rows) of R-MAT graphs of scales 17-20 times the whole
+    graph, every schedule timed by the exhaustive tuner; the MLP is trained
+    on the GPU.  Held out: a row panel of R-MAT
     scale 21 (edge factor 16, default a,b,c,d; rows 0..2^18-1 of the
     relabelled graph, i.e. a random eighth) times the whole matrix, in both
     semirings.  The step timed is the held-out panel product with the
@@ -447,6 +449,30 @@ def run_selector(args):
             del A
         if i % 200 == 0:
             log(f"  training matrix {i}: {time.perf_counter() - t0:.1f} s")
+    # wide matrices: row panels of R-MAT graphs of scales 17-20 times the
+    # whole graph (up to 2^20 columns; the held-out panel below is of a
+    # larger graph and a larger panel)
+    for scale in args.selector_panel_scales:
+        n = 1 << scale
+        src, dst = synth.rmat_edges(scale, 16, 0.57, 0.19, 0.19, synth.SEED_CFG4, tag=300 + scale)
+        keys_b = torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda")
+        for sr, dt in pairs:
+            v = synth.edge_values(dt, src.size, synth.SEED_CFG4, tag=300 + scale, lo=1, hi=100)
+            B = ctx.fold(sr, srtc.COO(keys_b, torch.as_tensor(v, device="cuda"), (n, n)), "ij", "i", "j")
+            for j in range(args.selector_panels):
+                rows = synth.selector_panel_rows(n, 1000 * scale + j, synth.SEED_CFG4)
+                pos = np.full(n, -1, dtype=np.int64)
+                pos[rows] = np.arange(rows.size)
+                sel = pos[dst] >= 0
+                Ap = ctx.fold(sr, srtc.COO(torch.as_tensor(pos[dst[sel]] * n + src[sel], device="cuda"),
+                                           torch.as_tensor(v[sel], device="cuda"), (rows.size, n)), "ij", "i", "j")
+                f, t = S.collect(ctx, sr, Ap, B, reps=2)
+                X.append(f)
+                T.append(t)
+                fams.append(f"panel{scale}/" + sr)
+                del Ap
+            del B
+        log(f"  panels of R-MAT {scale}: {time.perf_counter() - t0:.1f} s")
     X, T = np.array(X, dtype=np.float32), np.array(T, dtype=np.float64)
     t_collect = time.perf_counter() - t0
     fixed = S.best_fixed(T)
@@ -507,6 +533,7 @@ def run_selector(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+i32", "data": "synthetic",
            "config": {"workload": "rmat21_panel_AxA_learned_schedule", "rmat_scale": 21, "edge_factor": 16,
                       "panel_rows": prow, "training_samples": int(len(X)), "training_matrices": args.selector_matrices,
+                      "training_panels": args.selector_panels * len(args.selector_panel_scales),
                       "fixed_schedule": fixed, "train_loss": loss, "collect_s": t_collect, "train_s": t_train,
                       "in_sample": {k: ins[k] for k in ("mean_regret", "max_regret", "fixed_regret", "total_gain",
                                                          "hits")},
@@ -913,6 +940,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--selector-matrices", type=int, default=2000)
     ap.add_argument("--selector-epochs", type=int, default=400)
+    ap.add_argument("--selector-panels", type=int, default=40, help="selector: wide row panels per R-MAT scale")
+    ap.add_argument("--selector-panel-scales", type=int, nargs="*", default=[17, 18, 19, 20])
     ap.add_argument("--apsp-n", type=int, default=2048, help="apsp2048: vertices of the dense graph")
     ap.add_argument("--mp3-m", type=int, default=32, help="mp3: occupied orbitals")
     ap.add_argument("--jacobi-g", type=int, default=128, help="jacobi: grid side of the 27-point stencil")

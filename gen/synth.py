@@ -26,7 +26,7 @@ __all__ = [
     "GOLDEN", "mix64", "stream_key", "rand_u64", "uniform_f64", "uniform_f32",
     "randint", "permutation", "er_edges", "rmat_edges", "stencil27_edges",
     "powerlaw_edges", "bernoulli_keys", "pick_sources", "edge_values",
-    "er_batch_params", "selector_matrix", "dense_graph", "FAMILIES", "SEED_CFG0", "SEED_CFG1", "SEED_CFG2", "SEED_CFG3",
+    "er_batch_params", "selector_matrix", "selector_panel_rows", "dense_graph", "FAMILIES", "SEED_CFG0", "SEED_CFG1", "SEED_CFG2", "SEED_CFG3",
     "SEED_CFG4",
 ]
 
@@ -249,6 +249,15 @@ def edge_values(kind: str, m: int, seed: int, tag: int = 0, lo: int = 1, hi: int
     if kind == "bool":
         return np.ones(m, dtype=np.uint8)
     raise ValueError(kind)
+
+
+def selector_panel_rows(n: int, j: int, seed: int, lo: int = 10, hi: int = 14):
+    """Row set of panel j of a wide-matrix family in the selector training
+    set: 2^u rows (u uniform in [lo, hi]) drawn without replacement from
+    0..n-1, sorted."""
+    u = uniform_f64(stream_key(seed, 6000 + j), 1)[0]
+    k = min(n, int(2 ** (lo + (hi - lo) * u)))
+    return np.sort(permutation(stream_key(seed, 6100 + j), n)[:k]).astype(np.int64)
 
 
 def dense_graph(n: int, seed: int, lo: int = 1, hi: int = None, tag: int = 0):
