@@ -791,7 +791,7 @@ def run_mp3(args):
     for r in prof:
         log(f"  {r[0]:28s} launches {r[1] // args.steps:3d}/step  {r[2] / args.steps:8.3f} ms/step")
     nm, cnt, tms, by = max(prof, key=lambda r: r[2])
-    if nm == "dense.gemm_mfma":
+    if nm.startswith("dense.gemm_mfma"):
         flops = 2.0 * (n * n * (n * m * m) + m * m * (n * n * m)) * args.steps
         achieved, peak, unit, bound = flops / (tms / 1e3) / 1e12, 78.6, "TFLOP/s", "mfma"
     else:
@@ -911,6 +911,62 @@ def run_jacobi(args):
     return out
 
 
+def run_gemm(args):
+    """The dense (+,x) tile path on its own: C["ij"] = A["ik"] B["kj"] with
+    dense fp64 operands of M = N = K = 8,192 (values uniform in [0,1)) on
+    the matrix cores, plus the same in fp32 (fp64 flushes).  A step = both
+    products.  Ops = multiply-adds (M N K per product)."""
+    import torch
+    import paper_1512_00066_amd as srtc
+    from gen import synth
+
+    ctx = srtc.Context(0)
+    n = args.gemm_n
+    res = {}
+    for dt, tt in (("f64", torch.float64), ("f32", torch.float32)):
+        A = torch.as_tensor(synth.uniform_f64(synth.stream_key(5, 1), n * n).reshape(n, n), device="cuda").to(tt)
+        B = torch.as_tensor(synth.uniform_f64(synth.stream_key(5, 2), n * n).reshape(n, n), device="cuda").to(tt)
+        C = torch.empty((n, n), dtype=tt, device="cuda")
+        res[dt] = (A, B, C)
+
+    def step():
+        for dt in ("f64", "f32"):
+            A, B, C = res[dt]
+            ctx.contract("plus_times", "ik", A, "kj", B, "ij", C=C)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    srtc.lib().srtc_profile_enable(ctx._h, 1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = profile_table(ctx)
+    srtc.lib().srtc_profile_enable(ctx._h, 0)
+    ms = (t1 - t0) * 1e3 / args.steps
+    flops = 2.0 * n ** 3
+    rate = {}
+    for nm, cnt, tms, _ in prof:
+        if nm.startswith("dense.gemm_mfma"):
+            rate[nm] = (tms / cnt, flops / (tms / cnt / 1e3) / 1e12)
+    f64_ms, f64_tf = rate["dense.gemm_mfma.f64"]
+    f32_ms, f32_tf = rate["dense.gemm_mfma.f32"]
+    log(f"gemm n={n}: {ms:.2f} ms/step; fp64 {f64_ms:.3f} ms = {f64_tf:.1f} TFLOP/s, "
+        f"fp32 {f32_ms:.3f} ms = {f32_tf:.1f} TFLOP/s")
+    out = {"metric": METRIC, "value": 2 * n ** 3 / (ms / 1e3), "unit": "semiring-ops/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": f"dense_gemm_{n}_f64_f32", "n": n,
+                      "f32": {"ms_per_launch": round(f32_ms, 4), "tflops": round(f32_tf, 2), "peak": 157.3,
+                              "frac": round(f32_tf / 157.3, 4)}},
+           "roofline": {"bound": "mfma", "kernel": "dense.gemm_mfma.f64", "achieved": round(f64_tf, 2),
+                        "peak": 78.6, "unit": "TFLOP/s", "frac": round(f64_tf / 78.6, 4), "traffic": None,
+                        "avg_launch_ms": round(f64_ms, 4)}}
+    return out
+
+
 def copy_calibration(args):
     """A plain device copy of known size (1 GiB read, 1 GiB written per
     launch), run under the same HBM counters as the kernels, to scale
@@ -932,7 +988,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512", "selector", "masked18",
-                                                               "apsp2048", "mp3", "jacobi"])
+                                                               "apsp2048", "mp3", "jacobi", "gemm"])
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
     ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -945,6 +1001,7 @@ def main():
     ap.add_argument("--apsp-n", type=int, default=2048, help="apsp2048: vertices of the dense graph")
     ap.add_argument("--mp3-m", type=int, default=32, help="mp3: occupied orbitals")
     ap.add_argument("--jacobi-g", type=int, default=128, help="jacobi: grid side of the 27-point stencil")
+    ap.add_argument("--gemm-n", type=int, default=8192, help="gemm: M = N = K of the dense products")
     ap.add_argument("--mp3-n", type=int, default=128, help="mp3: virtual orbitals")
     ap.add_argument("--changed-rows", action="store_true",
                     help="rmat20_sssp: fixpoint steps gather only from rows changed in the previous step")
@@ -960,7 +1017,7 @@ def main():
         return
     out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512,
            "selector": run_selector, "masked18": run_masked18, "apsp2048": run_apsp2048,
-           "mp3": run_mp3, "jacobi": run_jacobi}[args.workload](args)
+           "mp3": run_mp3, "jacobi": run_jacobi, "gemm": run_gemm}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

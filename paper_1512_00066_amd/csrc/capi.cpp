@@ -688,7 +688,7 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
       const int64_t M_ = extent(p, p.M), N_ = extent(p, p.N), K_ = extent(p, p.K), Z_ = extent(p, p.batch);
       product_into_c(p.batch + p.M + p.N, [&](void *out, int acc) {
         const double es = (double)dtype_size(dt);
-        ProfScope ps(c, "dense.gemm_mfma",
+        ProfScope ps(c, dt == SRTC_F64 ? "dense.gemm_mfma.f64" : "dense.gemm_mfma.f32",
                      es * (double)Z_ * ((double)M_ * K_ + (double)K_ * N_ + (double)M_ * N_ * (acc ? 2 : 1)), s);
         dense_gemm_plus_times(c, dt, Ad, Bd, out, M_, N_, K_, acc, s, Z_);
       });

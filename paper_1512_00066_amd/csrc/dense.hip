@@ -127,6 +127,124 @@ __global__ void __launch_bounds__(256) gemm_mfma(const T *__restrict__ A0, const
   }
 }
 
+// Large tiles: 128x128 outputs per 256-thread block, each wave a 64x64
+// quadrant of 4x4 MFMA 16x16 tiles (16 MFMAs per 4-deep k step against 8
+// fragment reads), the next 16-deep k-tile prefetched into registers while
+// the current one is multiplied.  Used when both output sides reach 128.
+constexpr int BM = 128, BN = 128, BK = 16;
+
+template <class T>
+__global__ void __launch_bounds__(256) gemm_mfma_128(const T *__restrict__ A0, const T *__restrict__ B0,
+                                                     T *__restrict__ C0, int64_t M, int64_t N, int64_t K,
+                                                     int accumulate, int64_t batch) {
+  __shared__ T As[BM][BK + 1];
+  __shared__ T Bs[BK][BN + 1];
+  constexpr int LA = BM * BK / 256, LB = BK * BN / 256;  // staged elements per thread
+  const int t = threadIdx.x;
+  const int w = t / WAVE, l = lane_id();
+  const int wm = (w / 2) * 64, wn = (w % 2) * 64;
+  for (int64_t z = blockIdx.z; z < batch; z += gridDim.z) {
+    const T *__restrict__ A = A0 + z * M * K;
+    const T *__restrict__ B = B0 + z * K * N;
+    T *__restrict__ C = C0 + z * M * N;
+    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    v4d accd[4][4];
+    v4f acc32[4][4];
+    double acc64[4][4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        if constexpr (sizeof(T) == 8) {
+          accd[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        } else {
+          acc32[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < 4; q++) acc64[a][b][q] = 0.0;
+        }
+      }
+    T ra[LA], rb[LB];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+      for (int r = 0; r < LA; r++) {
+        const int e = t + r * 256, am = e / BK, ak = e % BK;
+        const int64_t gm = m0 + am, gk = k0 + ak;
+        ra[r] = (gm < M && gk < K) ? A[gm * K + gk] : (T)0;
+      }
+#pragma unroll
+      for (int r = 0; r < LB; r++) {
+        const int e = t + r * 256, bk = e / BN, bn = e % BN;
+        const int64_t gk = k0 + bk, gn = n0 + bn;
+        rb[r] = (gk < K && gn < N) ? B[gk * N + gn] : (T)0;
+      }
+    };
+    fetch(0);
+    int since_flush = 0;
+    for (int64_t k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+      for (int r = 0; r < LA; r++) {
+        const int e = t + r * 256;
+        As[e / BK][e % BK] = ra[r];
+      }
+#pragma unroll
+      for (int r = 0; r < LB; r++) {
+        const int e = t + r * 256;
+        Bs[e / BN][e % BN] = rb[r];
+      }
+      __syncthreads();
+      if (k0 + BK < K) fetch(k0 + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        T av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) av[a] = As[wm + a * 16 + (l % 16)][kk + l / 16];
+#pragma unroll
+        for (int b = 0; b < 4; b++) bv[b] = Bs[kk + l / 16][wn + b * 16 + (l % 16)];
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+          for (int b = 0; b < 4; b++) {
+            if constexpr (sizeof(T) == 8)
+              accd[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], accd[a][b], 0, 0, 0);
+            else
+              acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc32[a][b], 0, 0, 0);
+          }
+      }
+      __syncthreads();
+      if constexpr (sizeof(T) == 4) {
+        since_flush += BK;
+        if (since_flush >= 128) {
+#pragma unroll
+          for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+#pragma unroll
+              for (int q = 0; q < 4; q++) acc64[a][b][q] += (double)acc32[a][b][q];
+              acc32[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+          since_flush = 0;
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          double v;
+          if constexpr (sizeof(T) == 8) v = accd[a][b][q];
+          else v = acc64[a][b][q] + (double)acc32[a][b][q];
+          const int64_t gm = m0 + wm + a * 16 + (sizeof(T) == 8 ? 4 * q + l / 16 : 4 * (l / 16) + q);
+          const int64_t gn = n0 + wn + b * 16 + (l % 16);
+          if (gm < M && gn < N) {
+            if (accumulate) v += (double)C[gm * N + gn];
+            C[gm * N + gn] = (T)v;
+          }
+        }
+  }
+}
+
 struct PermArgs {
   int64_t sdims[SRTC_MAX_ORDER];   // source extents
   int64_t sstride[SRTC_MAX_ORDER]; // source strides
@@ -260,6 +378,20 @@ void dense_permute_combine(int sr, int dt, IdVal id, const void *src, void *dst,
 void dense_gemm_plus_times(Ctx *, int dt, const void *A, const void *B, void *C, int64_t M, int64_t N, int64_t K,
                            int accumulate, hipStream_t s, int64_t batch) {
   if (M == 0 || N == 0 || batch <= 0) return;
+  if (M >= BM && N >= BN) {
+    dim3 g((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)std::min<int64_t>(batch, 65535));
+    if (g.y > 65535) fail(SRTC_ERR_UNSUPPORTED, "dense gemm: too many row tiles");
+    if (dt == SRTC_F64)
+      gemm_mfma_128<double><<<g, 256, 0, s>>>((const double *)A, (const double *)B, (double *)C, M, N, K, accumulate,
+                                               batch);
+    else if (dt == SRTC_F32)
+      gemm_mfma_128<float><<<g, 256, 0, s>>>((const float *)A, (const float *)B, (float *)C, M, N, K, accumulate,
+                                              batch);
+    else
+      fail(SRTC_ERR_DTYPE, "dense (+,x) needs F64 or F32");
+    SRTC_LAUNCH_CHECK("gemm_mfma_128");
+    return;
+  }
   dim3 grid((unsigned)((N + TN - 1) / TN), (unsigned)((M + TM - 1) / TM),
             (unsigned)std::min<int64_t>(batch, 65535));
   if (grid.y > 65535) fail(SRTC_ERR_UNSUPPORTED, "dense gemm: too many row tiles");

@@ -346,7 +346,7 @@ def test_fixpoint_not_converged_and_cap(ctx):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_dense_mfma(ctx, dtype):
     say("dense mfma", dtype)
-    for (M, N, K) in ((16, 16, 4), (100, 70, 300), (257, 129, 1000)):
+    for (M, N, K) in ((16, 16, 4), (100, 70, 300), (257, 129, 1000), (640, 384, 517), (128, 128, 16)):
         a = synth.uniform_f64(synth.stream_key(5, M), M * K).reshape(M, K)
         b = synth.uniform_f64(synth.stream_key(6, N), K * N).reshape(K, N)
         if dtype == "f32":
@@ -357,6 +357,10 @@ def test_dense_mfma(ctx, dtype):
         ref = oracle.dense_plus_times(a, b)   # non-negative terms
         tol = 1e-12 if dtype == "f64" else 1e-5
         assert np.all(np.abs(C.cpu().numpy().astype(np.float64) - ref) <= tol * ref)
+        # accumulate: the old C joins the sum
+        ctx.contract("plus_times", "ik", torch.as_tensor(a, device="cuda"), "kj", torch.as_tensor(b, device="cuda"),
+                     "ij", C=C, accumulate=True)
+        assert np.all(np.abs(C.cpu().numpy().astype(np.float64) - 2 * ref) <= 2 * tol * ref)
 
 
 # ----------------------------------------------------------------- batch --
