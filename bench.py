@@ -709,8 +709,16 @@ def run_apsp2048(args):
             t_o = time.perf_counter() - t2
             ops_o = float(sum(pl)) * m
             m *= 2
+        m //= 2
+        reps = 1
+        while t_o < args.cpu_seconds / 2:   # the whole solve is short: repeat it
+            t2 = time.perf_counter()
+            oracle.apsp_tiskin(O)
+            t_o += time.perf_counter() - t2
+            ops_o += float(sum(pl)) * m
+            reps += 1
         out["cpu_baseline"] = {"value": ops_o / t_o, "unit": "semiring-ops/s", "cores": oracle.num_threads(),
-                               "kind": "oracle", "sample": f"the same recipe at n = {m // 2} "
+                               "kind": "oracle", "sample": f"the same recipe at n = {m}, {reps} solves "
                                f"({int(ops_o)} path sums); {t_o:.1f} s"}
     return out
 
@@ -823,9 +831,16 @@ def run_mp3(args):
             t_o = time.perf_counter() - t2
             ops_o = float(sub.nnz) * m * m
             k *= 2
+        reps = 1
+        while t_o < args.cpu_seconds / 2:   # every row already: repeat
+            t2 = time.perf_counter()
+            oracle.spmm("plus_times", "f64", sub, Tm)
+            t_o += time.perf_counter() - t2
+            ops_o += float(sub.nnz) * m * m
+            reps += 1
         out["cpu_baseline"] = {"value": ops_o / t_o, "unit": "semiring-ops/s", "cores": oracle.num_threads(),
-                               "kind": "oracle", "sample": f"Vabcd.T on {k // 2} random (a,b) rows "
-                               f"({int(ops_o)} multiply-adds); {t_o:.1f} s"}
+                               "kind": "oracle", "sample": f"Vabcd.T on {sub.nrows} random (a,b) rows, {reps} "
+                               f"runs ({int(ops_o)} multiply-adds); {t_o:.1f} s"}
     return out
 
 
