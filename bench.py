@@ -979,6 +979,19 @@ def run_gemm(args):
            "roofline": {"bound": "mfma", "kernel": "dense.gemm_mfma.f64", "achieved": round(f64_tf, 2),
                         "peak": 78.6, "unit": "TFLOP/s", "frac": round(f64_tf / 78.6, 4), "traffic": None,
                         "avg_launch_ms": round(f64_ms, 4)}}
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the oracle on the host ...")
+        k, t_o, ops_o = 1024, 0.0, 0.0
+        while t_o < args.cpu_seconds / 2 and k <= n:
+            a = synth.uniform_f64(synth.stream_key(5, 3), k * k).reshape(k, k)
+            t2 = time.perf_counter()
+            oracle.dense_plus_times(a, a)
+            t_o = time.perf_counter() - t2
+            ops_o = float(k) ** 3
+            k *= 2
+        out["cpu_baseline"] = {"value": ops_o / t_o, "unit": "semiring-ops/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"one fp64 product of size {k // 2}^3; {t_o:.1f} s"}
     return out
 
 
