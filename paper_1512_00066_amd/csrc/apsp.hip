@@ -151,8 +151,9 @@ __global__ void hops_fill(const uint64_t *__restrict__ P, int64_t n, uint32_t l,
 // with L[i, k] = P[i, k] where that path has exactly l hops, the identity
 // elsewhere (masked while the tile is staged, so P_l is never built).  A
 // block owns a TM x TN tile of Pn; 256 threads as 16 x 16, each holding
-// RM x RN accumulators at rows ty + 16 m and columns tx + 16 q, so the LDS
-// reads of a k step are broadcasts (L) and 16 consecutive words (P).  The
+// RM x RN accumulators at rows ty RM + m and columns tx RN + q, so the LDS
+// reads of a k step are one vector read each: a broadcast (L) and 16
+// consecutive lanes' vectors (P).  The
 // next k-tile is fetched into registers while the current one is used.
 // An identity operand needs no test: its weight alone reaches the identity,
 // which no accumulator exceeds (they start from P), so min() ignores it.
@@ -206,8 +207,10 @@ __global__ void __launch_bounds__(256, MINB) apsp_dense_round(const uint64_t *__
   constexpr int LA = TM * TK / 256, LB = TK * TN / 256;  // staged words per thread
   static_assert(LA * 256 == TM * TK && LB * 256 == TK * TN, "tile must split over 256 threads");
   static_assert(256 % TK == 0 && 256 % TN == 0, "a thread keeps one column of each staged tile");
-  __shared__ T Ls[TK][TM + 1];
-  __shared__ T Bs[TK][TN];
+  // rows padded by 16 bytes: staging writes spread over banks and every
+  // thread's RM rows (RN columns) stay one aligned 16-byte-multiple read
+  __shared__ __align__(16) T Ls[TK][TM + 16 / sizeof(T)];
+  __shared__ __align__(16) T Bs[TK][TN];
   const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
   const int64_t row0 = (int64_t)blockIdx.y * TM, col0 = (int64_t)blockIdx.x * TN;
   T acc[RM][RN];
@@ -215,7 +218,7 @@ __global__ void __launch_bounds__(256, MINB) apsp_dense_round(const uint64_t *__
   for (int m = 0; m < RM; m++)
 #pragma unroll
     for (int q = 0; q < RN; q++) {
-      const int64_t i = row0 + ty + 16 * m, j = col0 + tx + 16 * q;
+      const int64_t i = row0 + ty * RM + m, j = col0 + tx * RN + q;
       acc[m][q] = (i < n && j < n) ? enc.enc(P[i * n + j]) : enc.id();
     }
   // raw words of the next k-tile (identity pattern where out of range).
@@ -263,9 +266,9 @@ __global__ void __launch_bounds__(256, MINB) apsp_dense_round(const uint64_t *__
       for (int kk = 0; kk < TK; kk++) {
         T a[RM], b[RN];
 #pragma unroll
-        for (int m = 0; m < RM; m++) a[m] = Ls[kk][ty + 16 * m];
+        for (int m = 0; m < RM; m++) a[m] = Ls[kk][ty * RM + m];
 #pragma unroll
-        for (int q = 0; q < RN; q++) b[q] = Bs[kk][tx + 16 * q];
+        for (int q = 0; q < RN; q++) b[q] = Bs[kk][tx * RN + q];
 #pragma unroll
         for (int m = 0; m < RM; m++)
 #pragma unroll
@@ -280,11 +283,11 @@ __global__ void __launch_bounds__(256, MINB) apsp_dense_round(const uint64_t *__
   uint32_t wmax = 0, hmax = 0;
 #pragma unroll
   for (int m = 0; m < RM; m++) {
-    const int64_t i = row0 + ty + 16 * m;
+    const int64_t i = row0 + ty * RM + m;
     int c = 0;
 #pragma unroll
     for (int q = 0; q < RN; q++) {
-      const int64_t j = col0 + tx + 16 * q;
+      const int64_t j = col0 + tx * RN + q;
       if (i < n && j < n) {
         const uint64_t o = enc.dec(acc[m][q]);
         Pn[i * n + j] = o;
