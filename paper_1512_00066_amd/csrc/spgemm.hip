@@ -246,8 +246,8 @@ __device__ __forceinline__ int32_t layout_chunk(int32_t len, int64_t st, V a, Ch
   return total;
 }
 
-// Visit every product of row i (optionally restricted to column window w of
-// the window table) as f(j, a_ik, b_kj).  A entries are taken BS at a time;
+// Visit every product of row i (optionally restricted to the column windows
+// [w, w_end) of the window table) as f(j, a_ik, b_kj).  A entries are taken BS at a time;
 // their B segments are laid end to end by a block scan and the threads walk
 // that flattened range, so the work per thread is balanced whatever the
 // segment lengths.
@@ -256,7 +256,7 @@ __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, co
                                              const V *__restrict__ vA, const int64_t *__restrict__ rpB,
                                              const int32_t *__restrict__ cB, const V *__restrict__ vB,
                                              int64_t i, const int32_t *__restrict__ woff, int nwin, int w,
-                                             Chunk<BS, V> &L, F &&f) {
+                                             int w_end, Chunk<BS, V> &L, F &&f) {
   const int t = threadIdx.x;
   const int64_t pa = rpA[i], pe = rpA[i + 1];
   for (int64_t p0 = pa; p0 < pe; p0 += BS) {
@@ -268,8 +268,8 @@ __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, co
       const int32_t k = cA[p0 + t];
       st = rpB[k];
       if (woff) {
-        const int32_t *wk = woff + (int64_t)k * (nwin + 1) + w;
-        const int32_t o0 = wk[0], o1 = wk[1];
+        const int32_t *wk = woff + (int64_t)k * (nwin + 1);
+        const int32_t o0 = wk[w], o1 = wk[w_end];
         st += o0;
         len = o1 - o0;
       } else {
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(BS) sym_hash(const int32_t *__restrict__ list,
     __syncthreads();
     int64_t mine = 0;
     for_products<BS, false, uint8_t>(rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr, i,
-                                     nullptr, 0, 0, L, [&](int32_t j, uint8_t, uint8_t) {
+                                     nullptr, 0, 0, 1, L, [&](int32_t j, uint8_t, uint8_t) {
       uint32_t h = hash_slot(j, LG);
       // the table is sized to at least twice the row's products; the probe
       // bound only guards against a broken invariant
@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
       // with several windows, the window table limits each pass to its own
       // products (each product is walked once over all passes)
       for_products<BS, false, uint8_t>(rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr, i,
-                                       nwin > 1 ? woff : nullptr, nwin, (int)wi, L, [&](int32_t j, uint8_t, uint8_t) {
+                                       nwin > 1 ? woff : nullptr, nwin, (int)wi, (int)wi + 1, L, [&](int32_t j, uint8_t, uint8_t) {
         const int64_t jj = (int64_t)j - w0;
         if (jj >= 0 && jj < wcols) atomicOr(&bits[jj >> 5], 1u << (jj & 31));
       });
@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
       if (SR::HAS_VALS) vals[s] = id;
     }
     __syncthreads();
-    for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nullptr, 0, 0, L, [&](int32_t j, V a, V b) {
+    for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nullptr, 0, 0, 1, L, [&](int32_t j, V a, V b) {
       if (SR::HAS_VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
       uint32_t h = hash_slot(j, LG);
       // the table holds at least twice the row's (symbolic) outputs
@@ -636,13 +636,102 @@ __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint
   return tot;
 }
 
-// Dense accumulator windows: W consecutive columns per window held in LDS
-// (values for value semirings, presence bits for the boolean one).  The
-// window table gives, for every row k of B, where each window starts in B_k
-// (B rows have ascending columns), so each product is visited exactly once
-// over all windows.  A rows of at most BS entries keep their entries in
-// registers across the windows and fetch the next window's table entry one
-// window ahead; longer A rows are re-read in chunks for every window.
+// Ranked groups for sparse stretches of a dense row.  A run of consecutive
+// windows whose products together fit one batch per thread (at most CAP) is
+// handled in two passes over the same gathered products, held in registers:
+// the first marks the touched columns in a bitmap over the run, a block scan
+// of the bitmap's popcounts then ranks every touched column (its position in
+// column order), and the second pass adds each product into a compact array
+// at its column's rank.  The array is already in column order, so extraction
+// only drops identity results.  The bitmap, the per-word rank prefixes, the
+// columns and the accumulators share the LDS of the dense window; SPANW (the
+// windows one run may cover) is what the bitmap and prefixes leave room for.
+template <class SR, int BS, int W> struct RankWin {
+  using A = typename SR::acc_t;
+  static constexpr int RB = W * (int)sizeof(A);
+  static constexpr int CAP = BS * WALK_U;
+  static constexpr int WPW = W / 32;
+  static constexpr int FIT = (RB - CAP * (4 + (int)sizeof(A))) / 8 / WPW;
+  static constexpr int SPANW = FIT < 16 ? FIT : 16;
+  static constexpr int NBW = SPANW * WPW;
+  static constexpr bool OK = SR::HAS_VALS && SPANW >= 2;
+  // byte offsets: accumulators, columns, bitmap, prefixes
+  static constexpr int OFF_C = CAP * (int)sizeof(A);
+  static constexpr int OFF_B = OFF_C + CAP * 4;
+  static constexpr int OFF_P = OFF_B + NBW * 4;
+  static_assert(!OK || OFF_P + NBW * 4 <= RB, "ranked group layout");
+};
+constexpr int NWPW = 256;  // most windows a row may split into for ranked groups
+
+// Ranks of a marked run of nbw bitmap words: thread t takes a contiguous run
+// of words, so one block scan of the per-thread popcounts gives every word's
+// prefix; each touched column is listed at its rank with its accumulator
+// reset.  Returns the number of touched columns (the same on every thread).
+template <class SR, int BS>
+__device__ __forceinline__ int32_t rank_run(const uint32_t *rbits, int32_t *rpre, int32_t *rcol,
+                                            typename SR::acc_t *racc, int nbw, typename SR::acc_t id,
+                                            int64_t *red) {
+  const int per = (nbw + BS - 1) / BS;
+  const int u0 = threadIdx.x * per, u1 = min(u0 + per, nbw);
+  int64_t mine = 0;
+  for (int u = u0; u < u1; u++) mine += __popc(rbits[u]);
+  int64_t tot;
+  int32_t r = (int32_t)block_excl_scan<BS, int64_t, false>(mine, red, &tot);
+  for (int u = u0; u < u1; u++) {
+    rpre[u] = r;
+    uint32_t wd = rbits[u];
+    while (wd) {
+      const int b = __ffs(wd) - 1;
+      wd &= wd - 1;
+      rcol[r] = u * 32 + b;
+      racc[r] = id;
+      r++;
+    }
+  }
+  return (int32_t)tot;
+}
+
+// Extraction of a ranked group: the n accumulators are in column order, the
+// ones that are not the identity are written out (thread t takes a
+// contiguous run, ranks from one block scan); the bitmap is cleared.
+// Returns the number written (the same on every thread).
+template <class SR, int BS>
+__device__ __forceinline__ int64_t extract_ranked(const typename SR::acc_t *racc, const int32_t *rcol,
+                                                  uint32_t *rbits, int nbw, int n, typename SR::acc_t id,
+                                                  int64_t col0, int64_t pos0, int32_t *__restrict__ cC,
+                                                  typename SR::val_t *__restrict__ vC, int64_t *red) {
+  const int per = (n + BS - 1) / BS;
+  const int r0 = threadIdx.x * per, r1 = min(r0 + per, n);
+  int64_t mine = 0;
+  for (int r = r0; r < r1; r++) mine += SR::acc_absent(racc[r], id) ? 0 : 1;
+  int64_t tot;
+  int64_t p = pos0 + block_excl_scan<BS, int64_t, false>(mine, red, &tot);
+  for (int r = r0; r < r1; r++) {
+    const typename SR::acc_t v = racc[r];
+    if (SR::acc_absent(v, id)) continue;
+    cC[p] = (int32_t)(col0 + rcol[r]);
+    vC[p] = SR::out(v);
+    p++;
+  }
+  for (int u = threadIdx.x; u < nbw; u += BS) rbits[u] = 0;
+  __syncthreads();
+  return tot;
+}
+
+// Dense rows, window by window: W consecutive columns held in LDS as dense
+// accumulators (values for value semirings, presence bits for the boolean
+// one).  The window table gives, for every row k of B, where each window
+// starts in B_k (B rows have ascending columns), so each product is visited
+// exactly once over all windows.  A rows of at most BS entries keep their
+// entries in registers across the windows and fetch the next group's table
+// entries one group ahead; the next group's layout and first B loads are
+// issued before the current one is written out.  For value semirings and
+// rows of moderate output counts, the row first counts its products per
+// window (one pass over the A row's window-table entries): windows without
+// products are skipped, and runs of sparse windows become ranked groups
+// (above), so a row with few outputs spread over many windows pays for a few
+// passes instead of one per window.  Longer A rows are re-read in chunks for
+// every window.
 template <class SR, int BS, int W>
 __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
                                                 int bin, const int64_t *__restrict__ rpA,
@@ -657,17 +746,27 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
                                                 int64_t *ctr) {
   using V = typename SR::val_t;
   using A = typename SR::acc_t;
+  using R = RankWin<SR, BS, W>;
   constexpr bool VALS = SR::HAS_VALS;
   constexpr int NWORD = W / 32;
   constexpr int NV = VALS ? W : 1;
-  __shared__ A vals[NV];
+  __shared__ __align__(16) A vals[NV];
   __shared__ uint32_t bits[NWORD];
   __shared__ Chunk<BS, V> L;
   __shared__ int64_t red[BS / WAVE + 1];
+  __shared__ unsigned long long pw[R::OK ? NWPW : 1];
+  // the ranked-group view of the accumulator space
+  char *const region = reinterpret_cast<char *>(vals);
+  A *const racc = reinterpret_cast<A *>(region);
+  int32_t *const rcol = reinterpret_cast<int32_t *>(region + R::OFF_C);
+  uint32_t *const rbits = reinterpret_cast<uint32_t *>(region + R::OFF_B);
+  int32_t *const rpre = reinterpret_cast<int32_t *>(region + R::OFF_P);
   const int t = threadIdx.x;
   for (int s = t; s < NV; s += BS) vals[s] = id;
   for (int s = t; s < NWORD; s += BS) bits[s] = 0;
   __syncthreads();
+  bool ranked_ready = false;  // the space holds a cleared ranked-group bitmap (else cleared dense accumulators)
+  const bool can_rank = R::OK && woff != nullptr && nwin > 1 && nwin <= NWPW;
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
   for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
@@ -675,11 +774,70 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
     const int64_t base = rpC[i];
     const int64_t pa = rpA[i], pe = rpA[i + 1];
     int64_t written = 0;
-    // one window: accumulated (already walked); write out and reset
-    auto finish = [&](int64_t w0) {
-      written += extract_window<SR, BS, W>(vals, bits, id, w0, base + written, cC, vC, red);
+    // rows with more than CAP/2 outputs per window on average stay dense
+    const bool use_rank = can_rank && pe - pa <= BS && rpC[i + 1] - base <= (int64_t)nwin * (R::CAP / 2);
+    if (use_rank) {
+      for (int s = t; s < nwin; s += BS) pw[s] = 0;
+      __syncthreads();
+      // products per window: one (A entry, window) pair per thread, four at a time
+      const int np = (int)(pe - pa) * nwin;
+      for (int x0 = t; x0 < np; x0 += 4 * BS) {
+        int32_t d[4];
+        int sw[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int x = x0 + u * BS;
+          d[u] = 0;
+          sw[u] = 0;
+          if (x < np) {
+            const int e = x / nwin;
+            sw[u] = x - e * nwin;
+            const int32_t *wk = woff + (int64_t)cA[pa + e] * (nwin + 1) + sw[u];
+            d[u] = wk[1] - wk[0];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+          if (d[u]) atomicAdd(&pw[sw[u]], (unsigned long long)d[u]);
+      }
+      __syncthreads();
+    }
+    // The group from window wa on: [ga, gb), dense or ranked (the same on
+    // every thread).  Windows without products are skipped; a run with one
+    // non-empty window stays dense.  ga == nwin: no group left.
+    auto next_group = [&](int wa, int &ga, int &gb) -> bool {
+      if (!use_rank) {
+        ga = wa;
+        gb = wa + 1;
+        return true;
+      }
+      while (wa < nwin && pw[wa] == 0) wa++;
+      ga = wa;
+      gb = wa + 1;
+      if (wa >= nwin || pw[wa] > (unsigned long long)R::CAP) return true;
+      unsigned long long sum = pw[wa];
+      int nonempty = 1;
+      while (gb < nwin && gb - wa < R::SPANW) {
+        const unsigned long long x = pw[gb];
+        if (sum + x > (unsigned long long)R::CAP) break;
+        sum += x;
+        nonempty += x > 0;
+        gb++;
+      }
+      return nonempty < 2;
     };
-    auto adder = [&](int64_t w0) {
+    // the accumulator space in the form the next group needs
+    auto ready = [&](bool dense) {
+      if (!R::OK || dense != ranked_ready) return;
+      if (dense) {
+        for (int s = t; s < NV; s += BS) vals[s] = id;
+      } else {
+        for (int s = t; s < R::NBW; s += BS) rbits[s] = 0;
+      }
+      __syncthreads();
+      ranked_ready = !dense;
+    };
+    auto dense_add = [&](int64_t w0) {
       return [&, w0](int32_t j, V a, V b) {
         if (VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
         const int64_t jl = (int64_t)j - w0;
@@ -689,9 +847,37 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
         atomicOr(&bits[jj >> 5], 1u << (jj & 31));
       };
     };
+    // ranked groups: mark, then add at the column's rank
+    auto rank_mark = [&](int64_t c0, int64_t span) {
+      return [&, c0, span](int32_t j, V a, V b) {
+        if constexpr (R::OK) {
+          if (SR::absent(a, id) || SR::absent(b, id)) return;
+          const int64_t jl = (int64_t)j - c0;
+          if (jl < 0 || jl >= span) return;
+          atomicOr(&rbits[jl >> 5], 1u << (jl & 31));
+        }
+      };
+    };
+    auto rank_add = [&](int64_t c0, int64_t span) {
+      return [&, c0, span](int32_t j, V a, V b) {
+        if constexpr (R::OK) {
+          if (SR::absent(a, id) || SR::absent(b, id)) return;
+          const int64_t jl = (int64_t)j - c0;
+          if (jl < 0 || jl >= span) return;
+          const int c = (int)jl;
+          const int q = rpre[c >> 5] + __popc(rbits[c >> 5] & ((1u << (c & 31)) - 1u));
+          SR::lds_add(&racc[q], SR::mul(a, b));
+        }
+      };
+    };
+    int ga, gb;
+    bool dense = next_group(0, ga, gb);
     if (pe - pa <= BS) {
-      // Window pipeline: while window w is written out, the layout of window
-      // w+1 is already done and its first batch of B loads is in flight.
+      // Group pipeline: while group g is written out, the layout of group
+      // g+1 is already done and its first batch of B loads is in flight.
+      // Skipped windows hold no products of the row, so every A entry's
+      // table offset at the start of a group equals the one at the end of
+      // the group before.  A ranked group's products fit the first batch.
       const int cnt = (int)(pe - pa);
       int32_t k = 0, o_cur = 0, o_nxt = 0;
       int64_t rb = 0;
@@ -703,8 +889,10 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
         if (VALS) av = vA[pa + t];
         if (nwin > 1) {
           wk = woff + (int64_t)k * (nwin + 1);
-          o_cur = wk[0];
-          o_nxt = wk[1];
+          if (ga < nwin) {
+            o_cur = wk[ga];
+            o_nxt = wk[gb];
+          }
         } else {
           o_nxt = (int32_t)(rpB[k + 1] - rb);
         }
@@ -712,26 +900,50 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
       int32_t total = layout_chunk<BS, VALS, V>(o_nxt - o_cur, rb + o_cur, av, L);
       Batch<WALK_U, V> g;
       gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, t, g);
-      for (int w = 0; w < nwin; w++) {
-        const int32_t o_after = (wk && w + 2 <= nwin) ? wk[w + 2] : 0;
-        const int64_t w0 = (int64_t)w * W;
-        consume_batch<BS, WALK_U, V>(g, t, total, adder(w0));
-        if (total > BS * WALK_U) walk_chunk<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, adder(w0), t + BS * WALK_U);
-        __syncthreads();  // window w accumulated; L free
+      while (ga < nwin) {
+        int na = nwin, nb = nwin;
+        bool ndense = true;
+        if (gb < nwin) ndense = next_group(gb, na, nb);
+        const int32_t o_after = (wk && na < nwin) ? wk[nb] : 0;
+        ready(dense);
+        const int64_t c0 = (int64_t)ga * W;
+        int32_t nrank = 0;
+        if (dense || !R::OK) {
+          consume_batch<BS, WALK_U, V>(g, t, total, dense_add(c0));
+          if (total > BS * WALK_U)
+            walk_chunk<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, dense_add(c0), t + BS * WALK_U);
+        } else {
+          const int64_t span = (int64_t)(gb - ga) * W;
+          consume_batch<BS, WALK_U, V>(g, t, total, rank_mark(c0, span));
+          __syncthreads();
+          nrank = rank_run<SR, BS>(rbits, rpre, rcol, racc, (gb - ga) * R::WPW, id, red);
+          __syncthreads();
+          consume_batch<BS, WALK_U, V>(g, t, total, rank_add(c0, span));
+        }
+        __syncthreads();  // group accumulated; L free
         int32_t total_n = 0;
-        if (w + 1 < nwin) {
+        if (na < nwin) {
           total_n = layout_chunk<BS, VALS, V>(o_after - o_nxt, rb + o_nxt, av, L);
           gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total_n, L, t, g);
         }
-        finish(w0);
+        if (dense || !R::OK)
+          written += extract_window<SR, BS, W>(vals, bits, id, c0, base + written, cC, vC, red);
+        else
+          written += extract_ranked<SR, BS>(racc, rcol, rbits, (gb - ga) * R::WPW, nrank, id, c0, base + written,
+                                            cC, vC, red);
         total = total_n;
         o_nxt = o_after;
+        ga = na;
+        gb = nb;
+        dense = ndense;
       }
     } else {
+      ready(true);
       for (int w = 0; w < nwin; w++) {
         const int64_t w0 = (int64_t)w * W;
-        for_products<BS, VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin, w, L, adder(w0));
-        finish(w0);
+        for_products<BS, VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin, w, w + 1, L,
+                                  dense_add(w0));
+        written += extract_window<SR, BS, W>(vals, bits, id, w0, base + written, cC, vC, red);
       }
     }
     if (t == 0) {
@@ -817,7 +1029,7 @@ __global__ void __launch_bounds__(BS) masked_rows(const int64_t *__restrict__ rp
         }
         __syncthreads();
         const int32_t c_lo = keys[0], c_hi = keys[n - 1];
-        for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nullptr, 0, 0, L, [&](int32_t j, V a, V b) {
+        for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nullptr, 0, 0, 1, L, [&](int32_t j, V a, V b) {
           if (SR::HAS_VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
           if (j < c_lo || j > c_hi) return;
           int lo = 0, hi = n - 1;
@@ -1034,7 +1246,7 @@ template <class SR> struct NumLaunch {
                     int32_t *cC, V *vC, A id, int64_t *kept, int32_t *any_short, int64_t *ctr) {
     if (rows == 0) return;
     constexpr int NV = SR::HAS_VALS ? W : 1;
-    const int stat = NV * (int)sizeof(A) + W / 8 + (int)sizeof(Chunk<BS, V>) + 64;
+    const int stat = NV * (int)sizeof(A) + W / 8 + (int)sizeof(Chunk<BS, V>) + (RankWin<SR, BS, W>::OK ? NWPW * 8 : 8) + 64;
     num_dense<SR, BS, W><<<L.grid(rows, stat, BS), BS, 0, L.s>>>(
         list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, woff,
         nwin, rpC, cC, vC, id, kept, any_short, ctr);
