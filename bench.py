@@ -200,8 +200,9 @@ def run_rmat18(args):
     if os.path.exists(tf):
         try:
             rec = json.load(open(tf))
-            if rec.get("kernel") == nm and rec.get("source_hash") == kernel_source_hash():
-                traffic = rec.get("hbm_bytes_per_launch")
+            k = rec.get("kernels", {}).get(nm)
+            if k and rec.get("source_hash") == kernel_source_hash():
+                traffic = k.get("hbm_bytes_per_launch")
         except Exception:
             traffic = None
     roof = {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

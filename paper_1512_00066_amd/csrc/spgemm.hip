@@ -803,8 +803,8 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
       __syncthreads();
     }
     // The group from window wa on: [ga, gb), dense or ranked (the same on
-    // every thread).  Windows without products are skipped; a run with one
-    // non-empty window stays dense.  ga == nwin: no group left.
+    // every thread).  Windows without products are skipped; a window with
+    // more than CAP products is dense.  ga == nwin: no group left.
     auto next_group = [&](int wa, int &ga, int &gb) -> bool {
       if (!use_rank) {
         ga = wa;
@@ -816,15 +816,8 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
       gb = wa + 1;
       if (wa >= nwin || pw[wa] > (unsigned long long)R::CAP) return true;
       unsigned long long sum = pw[wa];
-      int nonempty = 1;
-      while (gb < nwin && gb - wa < R::SPANW) {
-        const unsigned long long x = pw[gb];
-        if (sum + x > (unsigned long long)R::CAP) break;
-        sum += x;
-        nonempty += x > 0;
-        gb++;
-      }
-      return nonempty < 2;
+      while (gb < nwin && gb - wa < R::SPANW && sum + pw[gb] <= (unsigned long long)R::CAP) sum += pw[gb++];
+      return false;
     };
     // the accumulator space in the form the next group needs
     auto ready = [&](bool dense) {
@@ -1111,7 +1104,7 @@ const Schedule kSchedules[SRTC_NUM_SCHEDULES] = {
     {2048, 32, 256, 256, 256, 1, 256, 0},     // 2 dense windows from 257 outputs
     {8192, 32, 256, 2048, 4096, 0, 512, 1},   // 3 hash-heavy, wide dense windows
     {0, 0, 0, 0, 0, 0, 256, 0},               // 4 dense windows for every row
-    {2048, 32, 256, 2048, 2048, 0, 512, 0},   // 5 as 0, 512-thread dense windows from 2049 outputs
+    {2048, 32, 256, 256, 256, 0, 512, 0},     // 5 as 0, 512-thread dense windows from 257 outputs
     {2048, 32, 256, 2048, 4096, 0, 512, 2},   // 6 as 5 with narrow dense windows (more blocks per CU)
     {256, 32, 256, 1024, 1024, 1, 256, 0},    // 7 bitmap symbolic above 256 products
 };
