@@ -167,11 +167,14 @@ template <int BS, class V> struct Chunk {
 
 // Walking the products laid out by a chunk: L.off holds the exclusive scan of
 // the cnt segment lengths (total products), L.start each segment's first
-// position in B, L.a the A value.  Thread t takes products t, t+BS, ...; a
-// batch is U of them handled together (an interleaved binary search for the
-// owning segments, then all B loads), so a lane keeps U independent memory
-// requests in flight instead of one.  Gathering a batch and consuming it are
-// separate steps, so a caller can issue the loads early and use them later.
+// position in B, L.a the A value.  The products are taken in tiles of BS*U;
+// in a tile, thread t takes U consecutive ones, t*U .. t*U+U-1.  A binary
+// search finds the segment owning the first; the next ones advance from it
+// (one comparison with the next segment's offset, the B position otherwise
+// just increments), so the search is paid once per batch of U products, not
+// per product, and a lane keeps U independent loads in flight.  Gathering a
+// batch and consuming it are separate steps, so a caller can issue the loads
+// early and use them later.
 template <int U, class V> struct Batch {
   int32_t j[U];
   V a[U], b[U];
@@ -179,30 +182,40 @@ template <int U, class V> struct Batch {
 
 template <int BS, int U, bool VALS, class V>
 __device__ __forceinline__ void gather_batch(const int32_t *__restrict__ cB, const V *__restrict__ vB, int cnt,
-                                             int32_t total, const Chunk<BS, V> &L, int32_t q0, Batch<U, V> &g) {
-  const int top = cnt > 1 ? 1 << (31 - __clz(cnt - 1)) : 0;  // largest power of two <= cnt-1
-  int lo[U];
-#pragma unroll
-  for (int u = 0; u < U; u++) lo[u] = 0;
-  // largest lo with off[lo] <= q (off is non-decreasing, off[0] = 0)
-  for (int step = top; step > 0; step >>= 1) {
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const int c = lo[u] + step;
-      if (c < cnt && L.off[c] <= q0 + u * BS) lo[u] = c;
-    }
+                                             int32_t total, const Chunk<BS, V> &L, int32_t base, Batch<U, V> &g) {
+  const int32_t q0 = base + (int32_t)threadIdx.x * U;
+  // largest lo with off[lo] <= q0 (off is non-decreasing, off[0] = 0)
+  int lo = 0;
+  for (int step = cnt > 1 ? 1 << (31 - __clz(cnt - 1)) : 0; step > 0; step >>= 1) {
+    const int c = lo + step;
+    if (c < cnt && L.off[c] <= q0) lo = c;
   }
+  int32_t nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
+  int64_t pos = L.start[lo] + (q0 - L.off[lo]);
+  V av = VALS ? L.a[lo] : V{};
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    const int32_t q = q0 + u * BS;
+    const int32_t q = q0 + u;
     g.j[u] = 0;
     g.a[u] = V{};
     g.b[u] = V{};
     if (q < total) {
-      const int64_t pos = L.start[lo[u]] + (q - L.off[lo[u]]);
+      if (u > 0) {
+        if (q >= nxt) {
+          // the next non-empty segment (empty ones share its offset)
+          do {
+            lo++;
+            nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
+          } while (q >= nxt);
+          pos = L.start[lo] + (q - L.off[lo]);
+          if (VALS) av = L.a[lo];
+        } else {
+          pos++;
+        }
+      }
       g.j[u] = cB[pos];
       if (VALS) {
-        g.a[u] = L.a[lo[u]];
+        g.a[u] = av;
         g.b[u] = vB[pos];
       }
     }
@@ -210,25 +223,28 @@ __device__ __forceinline__ void gather_batch(const int32_t *__restrict__ cB, con
 }
 
 template <int BS, int U, class V, class F>
-__device__ __forceinline__ void consume_batch(const Batch<U, V> &g, int32_t q0, int32_t total, F &&f) {
+__device__ __forceinline__ void consume_batch(const Batch<U, V> &g, int32_t base, int32_t total, F &&f) {
+  const int32_t q0 = base + (int32_t)threadIdx.x * U;
 #pragma unroll
   for (int u = 0; u < U; u++)
-    if (q0 + u * BS < total) f(g.j[u], g.a[u], g.b[u]);
+    if (q0 + u < total) f(g.j[u], g.a[u], g.b[u]);
 }
 
-// All products of a laid-out chunk from product index q_start on (the
-// thread's own first product by default).
+// All products of a laid-out chunk from the tile starting at product `base`
+// (a multiple of BS*U) on.
 template <int BS, int U, bool VALS, class V, class F>
 __device__ __forceinline__ void walk_chunk(const int32_t *__restrict__ cB, const V *__restrict__ vB, int cnt,
-                                           int32_t total, const Chunk<BS, V> &L, F &&f, int32_t q_start = -1) {
-  for (int32_t q0 = q_start < 0 ? (int32_t)threadIdx.x : q_start; q0 < total; q0 += BS * U) {
+                                           int32_t total, const Chunk<BS, V> &L, F &&f, int32_t base = 0) {
+  for (int32_t b0 = base; b0 < total; b0 += BS * U) {
     Batch<U, V> g;
-    gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, q0, g);
-    consume_batch<BS, U, V>(g, q0, total, f);
+    gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, b0, g);
+    consume_batch<BS, U, V>(g, b0, total, f);
   }
 }
 
 constexpr int WALK_U = 4;
+// products in flight per lane in the symbolic bitmap walk (column indices only)
+constexpr int SYM_U = 4;
 
 // Lay out one chunk's segments: thread t < cnt owns a segment of `len`
 // products starting at B position `st` with A value `a`.  Returns the total;
@@ -251,7 +267,7 @@ __device__ __forceinline__ int32_t layout_chunk(int32_t len, int64_t st, V a, Ch
 // their B segments are laid end to end by a block scan and the threads walk
 // that flattened range, so the work per thread is balanced whatever the
 // segment lengths.
-template <int BS, bool VALS, class V, class F>
+template <int BS, bool VALS, class V, int U = WALK_U, class F>
 __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, const int32_t *__restrict__ cA,
                                              const V *__restrict__ vA, const int64_t *__restrict__ rpB,
                                              const int32_t *__restrict__ cB, const V *__restrict__ vB,
@@ -278,7 +294,7 @@ __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, co
       if (VALS) a = vA[p0 + t];
     }
     const int32_t total = layout_chunk<BS, VALS, V>(len, st, a, L);
-    walk_chunk<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, f);
+    walk_chunk<BS, U, VALS, V>(cB, vB, cnt, total, L, f);
     __syncthreads();
   }
 }
@@ -369,8 +385,9 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
       __syncthreads();
       // with several windows, the window table limits each pass to its own
       // products (each product is walked once over all passes)
-      for_products<BS, false, uint8_t>(rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr, i,
-                                       nwin > 1 ? woff : nullptr, nwin, (int)wi, (int)wi + 1, L, [&](int32_t j, uint8_t, uint8_t) {
+      for_products<BS, false, uint8_t, SYM_U>(rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr,
+                                              i, nwin > 1 ? woff : nullptr, nwin, (int)wi, (int)wi + 1, L,
+                                              [&](int32_t j, uint8_t, uint8_t) {
         const int64_t jj = (int64_t)j - w0;
         if (jj >= 0 && jj < wcols) atomicOr(&bits[jj >> 5], 1u << (jj & 31));
       });
@@ -892,7 +909,7 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
       }
       int32_t total = layout_chunk<BS, VALS, V>(o_nxt - o_cur, rb + o_cur, av, L);
       Batch<WALK_U, V> g;
-      gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, t, g);
+      gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, 0, g);
       while (ga < nwin) {
         int na = nwin, nb = nwin;
         bool ndense = true;
@@ -902,22 +919,22 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
         const int64_t c0 = (int64_t)ga * W;
         int32_t nrank = 0;
         if (dense || !R::OK) {
-          consume_batch<BS, WALK_U, V>(g, t, total, dense_add(c0));
+          consume_batch<BS, WALK_U, V>(g, 0, total, dense_add(c0));
           if (total > BS * WALK_U)
-            walk_chunk<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, dense_add(c0), t + BS * WALK_U);
+            walk_chunk<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, dense_add(c0), BS * WALK_U);
         } else {
           const int64_t span = (int64_t)(gb - ga) * W;
-          consume_batch<BS, WALK_U, V>(g, t, total, rank_mark(c0, span));
+          consume_batch<BS, WALK_U, V>(g, 0, total, rank_mark(c0, span));
           __syncthreads();
           nrank = rank_run<SR, BS>(rbits, rpre, rcol, racc, (gb - ga) * R::WPW, id, red);
           __syncthreads();
-          consume_batch<BS, WALK_U, V>(g, t, total, rank_add(c0, span));
+          consume_batch<BS, WALK_U, V>(g, 0, total, rank_add(c0, span));
         }
         __syncthreads();  // group accumulated; L free
         int32_t total_n = 0;
         if (na < nwin) {
           total_n = layout_chunk<BS, VALS, V>(o_after - o_nxt, rb + o_nxt, av, L);
-          gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total_n, L, t, g);
+          gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total_n, L, 0, g);
         }
         if (dense || !R::OK)
           written += extract_window<SR, BS, W>(vals, bits, id, c0, base + written, cC, vC, red);
