@@ -231,14 +231,27 @@ __device__ __forceinline__ void consume_batch(const Batch<U, V> &g, int32_t base
 }
 
 // All products of a laid-out chunk from the tile starting at product `base`
-// (a multiple of BS*U) on.
-template <int BS, int U, bool VALS, class V, class F>
+// (a multiple of BS*U) on.  PIPE: the next tile's search and loads are
+// issued before the current tile is consumed (twice the batch registers).
+template <int BS, int U, bool VALS, class V, bool PIPE = false, class F>
 __device__ __forceinline__ void walk_chunk(const int32_t *__restrict__ cB, const V *__restrict__ vB, int cnt,
                                            int32_t total, const Chunk<BS, V> &L, F &&f, int32_t base = 0) {
-  for (int32_t b0 = base; b0 < total; b0 += BS * U) {
+  if constexpr (PIPE) {
+    if (base >= total) return;
     Batch<U, V> g;
-    gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, b0, g);
-    consume_batch<BS, U, V>(g, b0, total, f);
+    gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, base, g);
+    for (int32_t b0 = base; b0 < total; b0 += BS * U) {
+      Batch<U, V> h = g;
+      if (b0 + BS * U < total) gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, b0 + BS * U, h);
+      consume_batch<BS, U, V>(g, b0, total, f);
+      g = h;
+    }
+  } else {
+    for (int32_t b0 = base; b0 < total; b0 += BS * U) {
+      Batch<U, V> g;
+      gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, b0, g);
+      consume_batch<BS, U, V>(g, b0, total, f);
+    }
   }
 }
 
@@ -267,7 +280,7 @@ __device__ __forceinline__ int32_t layout_chunk(int32_t len, int64_t st, V a, Ch
 // their B segments are laid end to end by a block scan and the threads walk
 // that flattened range, so the work per thread is balanced whatever the
 // segment lengths.
-template <int BS, bool VALS, class V, int U = WALK_U, class F>
+template <int BS, bool VALS, class V, int U = WALK_U, bool PIPE = false, class F>
 __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, const int32_t *__restrict__ cA,
                                              const V *__restrict__ vA, const int64_t *__restrict__ rpB,
                                              const int32_t *__restrict__ cB, const V *__restrict__ vB,
@@ -294,7 +307,7 @@ __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, co
       if (VALS) a = vA[p0 + t];
     }
     const int32_t total = layout_chunk<BS, VALS, V>(len, st, a, L);
-    walk_chunk<BS, U, VALS, V>(cB, vB, cnt, total, L, f);
+    walk_chunk<BS, U, VALS, V, PIPE>(cB, vB, cnt, total, L, f);
     __syncthreads();
   }
 }
@@ -385,9 +398,10 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
       __syncthreads();
       // with several windows, the window table limits each pass to its own
       // products (each product is walked once over all passes)
-      for_products<BS, false, uint8_t, SYM_U>(rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr,
-                                              i, nwin > 1 ? woff : nullptr, nwin, (int)wi, (int)wi + 1, L,
-                                              [&](int32_t j, uint8_t, uint8_t) {
+      // (two tiles in flight: the walk only gathers column indices)
+      for_products<BS, false, uint8_t, SYM_U, true>(
+          rpA, cA, (const uint8_t *)nullptr, rpB, cB, (const uint8_t *)nullptr, i, nwin > 1 ? woff : nullptr, nwin,
+          (int)wi, (int)wi + 1, L, [&](int32_t j, uint8_t, uint8_t) {
         const int64_t jj = (int64_t)j - w0;
         if (jj >= 0 && jj < wcols) atomicOr(&bits[jj >> 5], 1u << (jj & 31));
       });
