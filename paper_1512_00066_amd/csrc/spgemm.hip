@@ -933,9 +933,15 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
         const int64_t c0 = (int64_t)ga * W;
         int32_t nrank = 0;
         if (dense || !R::OK) {
-          consume_batch<BS, WALK_U, V>(g, 0, total, dense_add(c0));
-          if (total > BS * WALK_U)
-            walk_chunk<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, dense_add(c0), BS * WALK_U);
+          // g holds the first tile; each further tile is gathered before
+          // the one before it is consumed
+          for (int32_t b0 = 0; b0 < total; b0 += BS * WALK_U) {
+            Batch<WALK_U, V> h = g;
+            if (b0 + BS * WALK_U < total)
+              gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, b0 + BS * WALK_U, h);
+            consume_batch<BS, WALK_U, V>(g, b0, total, dense_add(c0));
+            g = h;
+          }
         } else {
           const int64_t span = (int64_t)(gb - ga) * W;
           consume_batch<BS, WALK_U, V>(g, 0, total, rank_mark(c0, span));
@@ -965,8 +971,8 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
       ready(true);
       for (int w = 0; w < nwin; w++) {
         const int64_t w0 = (int64_t)w * W;
-        for_products<BS, VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin, w, w + 1, L,
-                                  dense_add(w0));
+        for_products<BS, VALS, V, WALK_U, true>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin, w,
+                                                w + 1, L, dense_add(w0));
         written += extract_window<SR, BS, W>(vals, bits, id, w0, base + written, cC, vC, red);
       }
     }
