@@ -591,34 +591,41 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
 // boolean semiring they are the values), `vals` holds the accumulators of a
 // value semiring.  Every touched slot that does not hold the identity is
 // written out in column order; touched slots and their bits are reset.  Wave
-// wv owns words [wv*WPW, (wv+1)*WPW), a lane one word at a time, and walks
-// its set bits; ranks come from wave scans of the per-word counts and one
-// block-level prefix over the waves.  Returns the number of entries written
-// (the same on every thread).
+// wv owns words [wv*WPW, (wv+1)*WPW); a lane takes one word, or a part of
+// one (LPW lanes per word when a wave has more lanes than words, so no lane
+// idles), and walks its set bits; ranks come from wave scans of the
+// per-lane counts (adjacent lanes hold adjacent parts, so lane order is
+// column order) and one block-level prefix over the waves.  Returns the
+// number of entries written (the same on every thread).
 template <class SR, int BS, int W>
 __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint32_t *bits, typename SR::acc_t id,
                                                   int64_t w0, int64_t pos0, int32_t *__restrict__ cC,
                                                   typename SR::val_t *__restrict__ vC, int64_t *red) {
   using A = typename SR::acc_t;
   constexpr bool VALS = SR::HAS_VALS;
-  constexpr int NW = BS / WAVE, NWORD = W / 32, WPW = NWORD / NW, NG = (WPW + WAVE - 1) / WAVE;
-  static_assert(NWORD % NW == 0, "window split");
+  constexpr int NW = BS / WAVE, NWORD = W / 32, WPW = NWORD / NW;
+  constexpr int LPW = WPW >= WAVE ? 1 : WAVE / WPW;  // lanes per word
+  constexpr int BPL = 32 / LPW;                      // bits per lane
+  constexpr uint32_t MASK = BPL == 32 ? 0xffffffffu : (1u << BPL) - 1u;
+  constexpr int NG = (WPW * LPW + WAVE - 1) / WAVE;
+  static_assert(NWORD % NW == 0 && 32 % LPW == 0, "window split");
   const int wv = threadIdx.x / WAVE, l = lane_id();
-  // kept entries per word (value semirings re-read the accumulators; for
-  // the boolean one the count is the word's popcount, recomputed below)
+  // kept entries per lane part (value semirings re-read the accumulators;
+  // for the boolean one the count is the part's popcount, recomputed below)
   int32_t cnt[VALS ? NG : 1];
   int64_t wtot = 0;
 #pragma unroll 2
   for (int g = 0; g < NG; g++) {
-    const int uw = g * WAVE + l;
+    const int slot = g * WAVE + l;
+    const int uw = slot / LPW, sh = (slot % LPW) * BPL;
     const int u = wv * WPW + uw;
-    uint32_t wd = uw < WPW ? bits[u] : 0u;
+    uint32_t wd = uw < WPW ? (bits[u] >> sh) & MASK : 0u;
     if (VALS) {
       uint32_t t2 = wd;
       while (t2) {
         const int b = __ffs(t2) - 1;
         t2 &= t2 - 1;
-        if (SR::acc_absent(vals[u * 32 + b], id)) wd &= ~(1u << b);
+        if (SR::acc_absent(vals[u * 32 + sh + b], id)) wd &= ~(1u << b);
       }
       cnt[g] = __popc(wd);
     }
@@ -636,30 +643,31 @@ __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint
   int64_t pos = pos0 + before;
 #pragma unroll 2
   for (int g = 0; g < NG; g++) {
-    const int uw = g * WAVE + l;
+    const int slot = g * WAVE + l;
+    const int uw = slot / LPW, sh = (slot % LPW) * BPL;
     const int u = wv * WPW + uw;
     int32_t c;
     if constexpr (VALS) c = cnt[g];
-    else c = uw < WPW ? __popc(bits[u]) : 0;
+    else c = uw < WPW ? __popc((bits[u] >> sh) & MASK) : 0;
     const int32_t inc = wave_incl_scan(c);
     int64_t p = pos + (inc - c);
-    if (uw < WPW) {
-      uint32_t wd = bits[u];
-      bits[u] = 0;
-      while (wd) {
-        const int b = __ffs(wd) - 1;
-        wd &= wd - 1;
-        const int s = u * 32 + b;
-        A v = (A)1;
-        if (VALS) {
-          v = vals[s];
-          vals[s] = id;
-          if (SR::acc_absent(v, id)) continue;
-        }
-        cC[p] = (int32_t)(w0 + s);
-        vC[p] = SR::out(v);
-        p++;
+    uint32_t wd = uw < WPW ? (bits[u] >> sh) & MASK : 0u;
+    // every part of word u is read before part 0 clears it
+    if constexpr (LPW > 1) __builtin_amdgcn_wave_barrier();
+    if (uw < WPW && sh == 0) bits[u] = 0;
+    while (wd) {
+      const int b = __ffs(wd) - 1;
+      wd &= wd - 1;
+      const int s = u * 32 + sh + b;
+      A v = (A)1;
+      if (VALS) {
+        v = vals[s];
+        vals[s] = id;
+        if (SR::acc_absent(v, id)) continue;
       }
+      cC[p] = (int32_t)(w0 + s);
+      vC[p] = SR::out(v);
+      p++;
     }
     pos += lane63(inc);
   }
