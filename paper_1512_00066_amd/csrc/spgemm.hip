@@ -192,6 +192,8 @@ __device__ __forceinline__ void gather_batch(const int32_t *__restrict__ cB, con
   }
   int32_t nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
   int64_t pos = L.start[lo] + (q0 - L.off[lo]);
+  const int32_t *pc = cB + pos;
+  const V *pv = VALS ? vB + pos : nullptr;
   V av = VALS ? L.a[lo] : V{};
 #pragma unroll
   for (int u = 0; u < U; u++) {
@@ -208,15 +210,18 @@ __device__ __forceinline__ void gather_batch(const int32_t *__restrict__ cB, con
             nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
           } while (q >= nxt);
           pos = L.start[lo] + (q - L.off[lo]);
+          pc = cB + pos;
+          if (VALS) pv = vB + pos;
           if (VALS) av = L.a[lo];
         } else {
-          pos++;
+          pc++;
+          if (VALS) pv++;
         }
       }
-      g.j[u] = cB[pos];
+      g.j[u] = *pc;
       if (VALS) {
         g.a[u] = av;
-        g.b[u] = vB[pos];
+        g.b[u] = *pv;
       }
     }
   }
@@ -872,9 +877,8 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
     auto dense_add = [&](int64_t w0) {
       return [&, w0](int32_t j, V a, V b) {
         if (VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
-        const int64_t jl = (int64_t)j - w0;
-        if (jl < 0 || jl >= W) return;  // B rows must list columns in ascending order
-        const int jj = (int)jl;
+        const uint32_t jj = (uint32_t)j - (uint32_t)w0;
+        if (jj >= (uint32_t)W) return;  // B rows must list columns in ascending order
         if constexpr (VALS) SR::lds_add(&vals[jj], SR::mul(a, b));
         atomicOr(&bits[jj >> 5], 1u << (jj & 31));
       };
@@ -884,8 +888,8 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
       return [&, c0, span](int32_t j, V a, V b) {
         if constexpr (R::OK) {
           if (SR::absent(a, id) || SR::absent(b, id)) return;
-          const int64_t jl = (int64_t)j - c0;
-          if (jl < 0 || jl >= span) return;
+          const uint32_t jl = (uint32_t)j - (uint32_t)c0;
+          if (jl >= (uint32_t)span) return;
           atomicOr(&rbits[jl >> 5], 1u << (jl & 31));
         }
       };
@@ -894,9 +898,8 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
       return [&, c0, span](int32_t j, V a, V b) {
         if constexpr (R::OK) {
           if (SR::absent(a, id) || SR::absent(b, id)) return;
-          const int64_t jl = (int64_t)j - c0;
-          if (jl < 0 || jl >= span) return;
-          const int c = (int)jl;
+          const uint32_t c = (uint32_t)j - (uint32_t)c0;
+          if (c >= (uint32_t)span) return;
           const int q = rpre[c >> 5] + __popc(rbits[c >> 5] & ((1u << (c & 31)) - 1u));
           SR::lds_add(&racc[q], SR::mul(a, b));
         }
