@@ -996,12 +996,15 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
 
 // --------------------------------------------------------------- masked --
 // C = M (.) (A (x) B): only positions in M's pattern are formed (an output
-// with predefined sparsity, Sections 1 and 7).  A block takes a row; the
-// mask row's sorted columns are staged in LDS LM at a time with their
-// accumulators beside them, every product of the row finds its column by
-// binary search among them (products outside the mask are dropped), and the
-// kept entries are written in mask order into the row's mask-aligned
-// segment; kept[i] counts them for the final compaction.
+// with predefined sparsity, Sections 1 and 7).  The work items are (row,
+// chunk of LM consecutive mask entries of the row), handed out heaviest
+// first from one counter, so the chunks of a long mask row run on several
+// blocks at once instead of one after another on one.  A block stages its
+// chunk's sorted columns in LDS with their accumulators beside them, every
+// product of the row finds its column by binary search among them (products
+// outside the chunk are dropped), and the kept entries are written in mask
+// order into the chunk's own mask-aligned segment; kept[x] counts them for
+// the final compaction.
 template <class SR, int BS>
 __device__ __forceinline__ int64_t write_kept(const typename SR::acc_t *vals, const int32_t *keys, int n,
                                               typename SR::acc_t id, int64_t pos0, int32_t *__restrict__ cC,
@@ -1048,9 +1051,11 @@ __global__ void __launch_bounds__(BS) masked_rows(const int64_t *__restrict__ rp
                                                   const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB,
                                                   const typename SR::val_t *__restrict__ vB,
                                                   const int64_t *__restrict__ rpM, const int32_t *__restrict__ cM,
-                                                  int64_t m, int32_t *__restrict__ cC,
-                                                  typename SR::val_t *__restrict__ vC, typename SR::acc_t id,
-                                                  int64_t *__restrict__ kept) {
+                                                  const int32_t *__restrict__ irow,
+                                                  const int32_t *__restrict__ ichunk,
+                                                  const int32_t *__restrict__ order, int64_t items,
+                                                  int32_t *__restrict__ cC, typename SR::val_t *__restrict__ vC,
+                                                  typename SR::acc_t id, int64_t *__restrict__ kept, int64_t *ctr) {
   using V = typename SR::val_t;
   using A = typename SR::acc_t;
   __shared__ int32_t keys[LM];
@@ -1058,34 +1063,68 @@ __global__ void __launch_bounds__(BS) masked_rows(const int64_t *__restrict__ rp
   __shared__ Chunk<BS, V> L;
   __shared__ int64_t red[BS / WAVE + 1];
   const int t = threadIdx.x;
-  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
-    const int64_t m0 = rpM[i], m1 = rpM[i + 1];
-    int64_t written = 0;
-    if (m1 > m0 && rpA[i + 1] > rpA[i]) {
-      for (int64_t s0 = m0; s0 < m1; s0 += LM) {
-        const int n = (int)min((int64_t)LM, m1 - s0);
-        for (int q = t; q < n; q += BS) {
-          keys[q] = cM[s0 + q];
-          vals[q] = id;
-        }
-        __syncthreads();
-        const int32_t c_lo = keys[0], c_hi = keys[n - 1];
-        for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nullptr, 0, 0, 1, L, [&](int32_t j, V a, V b) {
-          if (SR::HAS_VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
-          if (j < c_lo || j > c_hi) return;
-          int lo = 0, hi = n - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (keys[mid] < j) lo = mid + 1; else hi = mid;
-          }
-          if (keys[lo] != j) return;
-          SR::lds_add(&vals[lo], SR::HAS_VALS ? SR::mul(a, b) : (A)1);
-        });
-        written += write_kept<SR, BS>(vals, keys, n, id, m0 + written, cC, vC, red);
-      }
+  for (int64_t r = next_row(ctr); r < items; r = next_row(ctr)) {
+    const int32_t x = order[r];
+    const int64_t i = irow[x];
+    const int64_t s0 = rpM[i] + (int64_t)ichunk[x] * LM;
+    const int n = (int)min((int64_t)LM, rpM[i + 1] - s0);
+    for (int q = t; q < n; q += BS) {
+      keys[q] = cM[s0 + q];
+      vals[q] = id;
     }
-    if (t == 0) kept[i] = written;
+    __syncthreads();
+    const int32_t c_lo = keys[0], c_hi = keys[n - 1];
+    for_products<BS, SR::HAS_VALS, V>(rpA, cA, vA, rpB, cB, vB, i, nullptr, 0, 0, 1, L, [&](int32_t j, V a, V b) {
+      if (SR::HAS_VALS && (SR::absent(a, id) || SR::absent(b, id))) return;
+      if (j < c_lo || j > c_hi) return;
+      int lo = 0, hi = n - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[mid] < j) lo = mid + 1; else hi = mid;
+      }
+      if (keys[lo] != j) return;
+      SR::lds_add(&vals[lo], SR::HAS_VALS ? SR::mul(a, b) : (A)1);
+    });
+    const int64_t written = write_kept<SR, BS>(vals, keys, n, id, s0, cC, vC, red);
+    if (t == 0) kept[x] = written;
   }
+}
+
+// Masked work items per row: chunks of LM mask entries (none when the mask
+// row or the A row is empty).
+__global__ void masked_count_items(const int64_t *__restrict__ rpA, const int64_t *__restrict__ rpM, int64_t m,
+                                   int lm, int64_t *__restrict__ cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t nm = rpM[i + 1] - rpM[i];
+    cnt[i] = (nm > 0 && rpA[i + 1] > rpA[i]) ? (nm + lm - 1) / lm : 0;
+  }
+}
+
+// Item x of row i (items of a row are consecutive, from ioff[i]): its row,
+// chunk, first mask position, weight (the row's products) and its slot in
+// the launch order (identity; sorted heaviest first afterwards).
+__global__ void masked_fill_items(const int64_t *__restrict__ ioff, const int64_t *__restrict__ rpM,
+                                  const int64_t *__restrict__ w, int64_t m, int lm, int32_t *__restrict__ irow,
+                                  int32_t *__restrict__ ichunk, int32_t *__restrict__ order,
+                                  int64_t *__restrict__ witem, int64_t *__restrict__ src) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t x = ioff[i]; x < ioff[i + 1]; x++) {
+      const int32_t c = (int32_t)(x - ioff[i]);
+      irow[x] = (int32_t)i;
+      ichunk[x] = c;
+      order[x] = (int32_t)x;
+      witem[x] = w[i];
+      src[x] = rpM[i] + (int64_t)c * lm;
+    }
+  }
+}
+
+// C's row pointers from the items' output offsets: row i starts at its first
+// item's offset (ioff[m] = number of items, koff[items] = nnz).
+__global__ void masked_rowptr(const int64_t *__restrict__ ioff, const int64_t *__restrict__ koff, int64_t m,
+                              int64_t *__restrict__ rp) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= m; i += (int64_t)gridDim.x * blockDim.x)
+    rp[i] = koff[ioff[i]];
 }
 
 // Window table: woff[k*(nwin+1) + w] = first position in B_k with column
@@ -1522,29 +1561,58 @@ void masked_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, const
     return;
   }
   constexpr int BS = 256, LM = 4096;
+  Launch L{c, s};
+  // work items: (row, chunk of LM mask entries)
+  Buf cnt(c, sizeof(int64_t) * (size_t)m), ioff(c, sizeof(int64_t) * (size_t)(m + 1));
+  masked_count_items<<<gridn(m), 256, 0, s>>>(Am.rowptr, Mm.rowptr, m, LM, cnt.as<int64_t>());
+  SRTC_LAUNCH_CHECK("masked_count_items");
+  excl_scan_i64(c, cnt.as<int64_t>(), ioff.as<int64_t>(), m, s);
+  const int64_t items = read_i64(c, ioff.as<int64_t>() + m, s);
+  out->rowptr = Buf(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
+  if (items == 0) {
+    fill_i64(out->rowptr.as<int64_t>(), m + 1, 0, s);
+    out->nnz = 0;
+    out->col = Buf(c, 4, out->kind);
+    out->val = Buf(c, es, out->kind);
+    return;
+  }
+  if (items >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "masked spgemm: more than 2^31-2 work items");
+  Buf irow(c, 4 * (size_t)items), ichunk(c, 4 * (size_t)items), order(c, 4 * (size_t)items);
+  Buf witem(c, 8 * (size_t)items), src(c, 8 * (size_t)items), kept(c, 8 * (size_t)items);
+  Buf koff(c, 8 * (size_t)(items + 1)), ctr(c, 64);
+  {
+    Buf w(c, sizeof(int64_t) * (size_t)m);
+    row_products(Am, Bm, w.as<int64_t>(), s);
+    masked_fill_items<<<gridn(m), 256, 0, s>>>(ioff.as<int64_t>(), Mm.rowptr, w.as<int64_t>(), m, LM,
+                                                irow.as<int32_t>(), ichunk.as<int32_t>(), order.as<int32_t>(),
+                                                witem.as<int64_t>(), src.as<int64_t>());
+    SRTC_LAUNCH_CHECK("masked_fill_items");
+    heavy_first(c, order.as<int32_t>(), items, witem.as<int64_t>(), s);
+  }
+  fill_i64(ctr.as<int64_t>(), 1, 0, s);
   Buf colM(c, sizeof(int32_t) * (size_t)Mm.nnz), valM(c, es * (size_t)Mm.nnz);
-  Buf kept(c, sizeof(int64_t) * (size_t)m);
   {
     ProfScope ps(c, "spgemm.masked", 16.0 * (m + 1) + 12.0 * Am.nnz + (4.0 + es) * Bm.nnz + 4.0 * Mm.nnz +
                  (4.0 + es) * Mm.nnz, s);
     const int stat = LM * (4 + (int)sizeof(A)) + (int)sizeof(Chunk<BS, V>) + 64;
-    Launch L{c, s};
-    masked_rows<SR, BS, LM><<<L.grid(m, stat, BS), BS, 0, s>>>(Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr,
-                                                                Bm.col, (const V *)Bm.val, Mm.rowptr, Mm.col, m,
-                                                                colM.as<int32_t>(), valM.as<V>(), id,
-                                                                kept.as<int64_t>());
+    masked_rows<SR, BS, LM><<<L.grid(items, stat, BS), BS, 0, s>>>(
+        Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Mm.rowptr, Mm.col,
+        irow.as<int32_t>(), ichunk.as<int32_t>(), order.as<int32_t>(), items, colM.as<int32_t>(), valM.as<V>(), id,
+        kept.as<int64_t>(), ctr.as<int64_t>());
     SRTC_LAUNCH_CHECK("masked_rows");
   }
-  out->rowptr = Buf(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
-  excl_scan_i64(c, kept.as<int64_t>(), out->rowptr.as<int64_t>(), m, s);
-  const int64_t total = read_i64(c, out->rowptr.as<int64_t>() + m, s);
+  excl_scan_i64(c, kept.as<int64_t>(), koff.as<int64_t>(), items, s);
+  const int64_t total = read_i64(c, koff.as<int64_t>() + items, s);
+  masked_rowptr<<<gridn(m + 1), 256, 0, s>>>(ioff.as<int64_t>(), koff.as<int64_t>(), m, out->rowptr.as<int64_t>());
+  SRTC_LAUNCH_CHECK("masked_rowptr");
   out->col = Buf(c, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), out->kind);
   out->val = Buf(c, es * (size_t)std::max<int64_t>(total, 1), out->kind);
   out->nnz = total;
   if (total > 0) {
-    compact_rows<V><<<gridn(m * WAVE, 256, 16384), 256, 0, s>>>(Mm.rowptr, out->rowptr.as<int64_t>(), m,
-                                                                colM.as<int32_t>(), valM.as<V>(),
-                                                                out->col.as<int32_t>(), out->val.as<V>());
+    // item x's kept entries: from its chunk's first mask position to koff[x]
+    compact_rows<V><<<gridn(items * WAVE, 256, 16384), 256, 0, s>>>(src.as<int64_t>(), koff.as<int64_t>(), items,
+                                                                    colM.as<int32_t>(), valM.as<V>(),
+                                                                    out->col.as<int32_t>(), out->val.as<V>());
     SRTC_LAUNCH_CHECK("compact_rows");
   }
 }
