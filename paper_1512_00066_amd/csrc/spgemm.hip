@@ -1560,7 +1560,7 @@ void masked_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, const
     out->val = Buf(c, es, out->kind);
     return;
   }
-  constexpr int BS = 256, LM = 4096;
+  constexpr int BS = 256, LM = 1024;  // short chunks: more items to balance, more blocks per CU
   Launch L{c, s};
   // work items: (row, chunk of LM mask entries)
   Buf cnt(c, sizeof(int64_t) * (size_t)m), ioff(c, sizeof(int64_t) * (size_t)(m + 1));
