@@ -769,13 +769,14 @@ __device__ __forceinline__ int64_t extract_ranked(const typename SR::acc_t *racc
 // exactly once over all windows.  A rows of at most BS entries keep their
 // entries in registers across the windows and fetch the next group's table
 // entries one group ahead; the next group's layout and first B loads are
-// issued before the current one is written out.  For value semirings and
-// rows of moderate output counts, the row first counts its products per
-// window (one pass over the A row's window-table entries): windows without
-// products are skipped, and runs of sparse windows become ranked groups
-// (above), so a row with few outputs spread over many windows pays for a few
-// passes instead of one per window.  Longer A rows are re-read in chunks for
-// every window.
+// issued before the current one is written out, and inside a group each
+// tile's loads are issued before the tile before it is consumed.  For value
+// semirings, rows of at most BS A entries and moderate output counts first
+// count their products per window (one pass over the A row's window-table
+// entries): windows without products are skipped, and runs of sparse
+// windows become ranked groups (above), so a row with few outputs spread
+// over many windows pays for a few passes instead of one per window.
+// Longer A rows are re-read in chunks for every window.
 template <class SR, int BS, int W>
 __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
                                                 int bin, const int64_t *__restrict__ rpA,
