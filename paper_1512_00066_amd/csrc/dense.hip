@@ -129,9 +129,9 @@ __global__ void __launch_bounds__(256) gemm_mfma(const T *__restrict__ A0, const
 
 // Large tiles: 128x128 outputs per 256-thread block, each wave a 64x64
 // quadrant of 4x4 MFMA 16x16 tiles (16 MFMAs per 4-deep k step against 8
-// fragment reads), the next 16-deep k-tile prefetched into registers while
+// fragment reads), the next 32-deep k-tile prefetched into registers while
 // the current one is multiplied.  Used when both output sides reach 128.
-constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int BM = 128, BN = 128, BK = 32;
 
 template <class T>
 __global__ void __launch_bounds__(256) gemm_mfma_128(const T *__restrict__ A0, const T *__restrict__ B0,
