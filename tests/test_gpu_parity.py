@@ -106,6 +106,66 @@ def test_spgemm_heavy_rows_all_schedules(ctx):
             check_csr(ctx.contract(semiring, "ik", G, "kj", G, "ij", schedule=sch), exp, semiring, dtype)
 
 
+def window_structured_pair(semiring, dtype, seed, cancel=False):
+    """A (15 x 2048) times B (2048 x 65,659): B's rows are dense in some
+    8192-column windows, sparse in others and empty in windows 4-5 (the last
+    window ragged); A's rows range from 1 to 500 entries, one avoids B's 16
+    dense rows and one hits them (its product is dense in most windows), one
+    is empty.  Rows of the product therefore mix dense windows, runs of
+    sparse windows, skipped empty windows, A rows longer than a block and
+    rows with several tiles per window."""
+    rng = np.random.default_rng(seed)
+    k, n, W = 2048, 65536 + 123, 8192
+    b_rows, b_cols = [], []
+    for r in range(k):
+        parts = []
+        for w, c in ((0, 40), (1, 6000 if r < 16 else 5), (2, 6000 if r < 16 else 5), (3, 6000 if r < 16 else 5),
+                     (6, 200 if r % 7 == 0 else 3), (7, 2), (8, 2)):
+            lo, hi = w * W, min(n, w * W + W)
+            parts.append(lo + rng.choice(hi - lo, size=min(c, hi - lo), replace=False))
+        cols = np.unique(np.concatenate(parts))
+        b_rows.append(np.full(cols.size, r)), b_cols.append(cols)
+    a_rows, a_cols = [], []
+    sizes = [1, 3, 10, 60, 100, 300, 40, 7, 2, 20, 500, 5, 260]
+    for i, c in enumerate(sizes):
+        cols = np.sort(16 + rng.choice(k - 16, size=c, replace=False))
+        a_rows.append(np.full(c, i)), a_cols.append(cols)
+    heavy = np.unique(np.concatenate([np.arange(16), rng.choice(k, size=300, replace=False)]))
+    a_rows.append(np.full(heavy.size, len(sizes))), a_cols.append(heavy)
+    m = len(sizes) + 2                                   # the last row stays empty
+    ar, ac = np.concatenate(a_rows), np.concatenate(a_cols)
+    br, bc = np.concatenate(b_rows), np.concatenate(b_cols)
+    if cancel:
+        av = rng.choice([-1.0, 1.0], ar.size).astype(oracle.NP_DTYPES[dtype])
+        bv = rng.choice([-1.0, 1.0], br.size).astype(oracle.NP_DTYPES[dtype])
+    else:
+        av, bv = values(semiring, dtype, ar.size, seed, 1), values(semiring, dtype, br.size, seed, 2)
+    return (ar, ac, av, m, k), (br, bc, bv, k, n)
+
+
+@pytest.mark.parametrize("semiring,dtype,cancel", [("plus_times", "f64", False), ("plus_times", "f64", True),
+                                                   ("plus_times", "f32", False), ("min_plus", "i32", False),
+                                                   ("max_times", "f64", False), ("or_and", "bool", False)])
+def test_spgemm_window_groups_all_schedules(ctx, semiring, dtype, cancel):
+    """Dense rows over many column windows: dense windows, ranked groups of
+    sparse windows, skipped empty windows, chunked long A rows, identity
+    results (exact cancellations) dropped; every schedule."""
+    say("window groups", semiring, dtype, cancel)
+    (ar, ac, av, m, k), (br, bc, bv, _, n) = window_structured_pair(semiring, dtype, 61, cancel)
+    GA = gpu_fold(ctx, semiring, dtype, ar, ac, av, m, k)
+    GB = gpu_fold(ctx, semiring, dtype, br, bc, bv, k, n)
+    exp = oracle.spgemm(semiring, dtype, oracle.fold(semiring, dtype, ar, ac, av, m, k),
+                        oracle.fold(semiring, dtype, br, bc, bv, k, n))
+    if cancel:
+        # some sums cancel to exactly zero (absent): fewer entries than the pattern
+        ones_a, ones_b = np.ones(ar.size, np.uint8), np.ones(br.size, np.uint8)
+        pat = oracle.spgemm("or_and", "bool", oracle.fold("or_and", "bool", ar, ac, ones_a, m, k),
+                            oracle.fold("or_and", "bool", br, bc, ones_b, k, n))
+        assert exp.rowptr[-1] < pat.rowptr[-1]
+    for sch in range(srtc.NUM_SCHEDULES):
+        check_csr(ctx.contract(semiring, "ik", GA, "kj", GB, "ij", schedule=sch), exp, semiring, dtype)
+
+
 def test_spgemm_star_and_identity(ctx):
     say("star / identity")
     L = 3000
