@@ -696,7 +696,7 @@ template <class SR, int BS, int W> struct RankWin {
   static constexpr int CAP = BS * WALK_U;
   static constexpr int WPW = W / 32;
   static constexpr int FIT = (RB - CAP * (4 + (int)sizeof(A))) / 8 / WPW;
-  static constexpr int SPANW = FIT < 16 ? FIT : 16;
+  static constexpr int SPANW = FIT < 32 ? FIT : 32;
   static constexpr int NBW = SPANW * WPW;
   static constexpr bool OK = SR::HAS_VALS && SPANW >= 2;
   // byte offsets: accumulators, columns, bitmap, prefixes
