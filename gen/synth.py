@@ -50,6 +50,22 @@ def mix64(z: np.ndarray) -> np.ndarray:
     return z ^ (z >> np.uint64(31))
 
 
+def _chunked(fn, n: int, chunk: int = 1 << 20) -> None:
+    """fn(e0, e1) over consecutive chunks of 0..n-1 on a few threads (numpy
+    releases the interpreter lock in its array loops); the draws are
+    counter-based, so the result does not depend on the split."""
+    bounds = [(e, min(n, e + chunk)) for e in range(0, n, chunk)]
+    if len(bounds) <= 1:
+        for e0, e1 in bounds:
+            fn(e0, e1)
+        return
+    import concurrent.futures
+    import os
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), len(bounds)))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda b: fn(*b), bounds))
+
+
 def stream_key(seed: int, tag: int) -> int:
     """Key of the stream ``tag`` under ``seed`` (a 64-bit integer)."""
     s = np.array([(seed * 0x100000001B3 + tag) & 0xFFFFFFFFFFFFFFFF],
@@ -67,6 +83,14 @@ def rand_u64(key: int, n: int, offset: int = 0) -> np.ndarray:
 
 def uniform_f64(key: int, n: int, offset: int = 0) -> np.ndarray:
     """Uniform doubles in [0, 1): top 53 bits times 2^-53."""
+    if n > (1 << 22):
+        out = np.empty(n, dtype=np.float64)
+
+        def part(e0, e1):
+            out[e0:e1] = uniform_f64(key, e1 - e0, offset + e0)
+
+        _chunked(part, n)
+        return out
     x = rand_u64(key, n, offset)
     return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
@@ -168,13 +192,18 @@ def rmat_edges(scale: int, edge_factor: int, a: float, b: float, c: float,
     src = np.zeros(m, dtype=np.int64)
     dst = np.zeros(m, dtype=np.int64)
     ab, abc = a + b, a + b + c
-    for lvl in range(scale):
-        u = uniform_f64(key, m, lvl * m)
-        sbit = (u >= ab).astype(np.int64)
-        dbit = (((u >= a) & (u < ab)) | (u >= abc)).astype(np.int64)
-        sh = scale - 1 - lvl
-        src |= sbit << sh
-        dst |= dbit << sh
+
+    def edges(e0, e1):
+        # edges e0 .. e1-1: draw lvl * m + e of the stream decides level lvl
+        for lvl in range(scale):
+            u = uniform_f64(key, e1 - e0, lvl * m + e0)
+            sbit = (u >= ab).astype(np.int64)
+            dbit = (((u >= a) & (u < ab)) | (u >= abc)).astype(np.int64)
+            sh = scale - 1 - lvl
+            src[e0:e1] |= sbit << sh
+            dst[e0:e1] |= dbit << sh
+
+    _chunked(edges, m)
     if relabel:
         perm = permutation(stream_key(seed, 300 + tag), 1 << scale)
         src = perm[src]

@@ -30,7 +30,19 @@
  *     (a caching allocator bound to `stream`, as torch's is) or synchronous.
  *     Without a callback, outputs come from hipMalloc and scratch from a
  *     per-context cache of hipMalloc blocks kept until srtc_ctx_destroy.
- *   - Environment: SRTC_TRACE=1 prints each phase of every call to stderr.
+ *   - Environment (read by srtc_ctx_create):
+ *       SRTC_TRACE=1          prints each phase of every call to stderr;
+ *       SRTC_VALIDATE=1       checks every sparse operand's structure as
+ *                             opts.validate does (SRTC_ERR_FORMAT);
+ *       SRTC_FORCE_SCHEDULE=k SpGEMM schedule k (0..SRTC_NUM_SCHEDULES-1)
+ *                             wherever the caller leaves the choice open
+ *                             (opts.schedule = -1);
+ *       SRTC_LDS_BUDGET=bytes LDS per workgroup the SpGEMM kernels may use:
+ *                             rows whose kernel would need more go to
+ *                             narrower dense windows (more passes, the same
+ *                             results); SRTC_ERR_UNSUPPORTED if even the
+ *                             narrowest window does not fit.
+ *     srtc_ctx_create returns SRTC_ERR_ARG for a malformed value.
  *   - No call aborts and no C++ exception crosses the ABI: failures return a
  *     negative srtc_status and srtc_last_error() describes the last one.
  *   - An operand entry equal to the additive identity is absent; output
@@ -70,13 +82,24 @@ typedef enum srtc_status {
  * caller (add_id, a host pointer to one value of the operand dtype; NULL
  * selects the default listed here). */
 typedef enum srtc_semiring {
-  SRTC_PLUS_TIMES = 0, /* (+, 0, x, 1) on F64/F32.  F32 products are formed
-                          exactly and summed in fp64, rounded once.  add_id
-                          must be 0. */
+  SRTC_PLUS_TIMES = 0, /* (+, 0, x, 1) on F64/F32.  add_id must be 0.  F32
+                          with a sparse operand: products are formed exactly
+                          in fp64 and summed in fp64, rounded once (relative
+                          error <= 2^-24 + t 2^-53 for t non-negative terms).
+                          F32 dense x dense on the matrix cores: fp32
+                          multiply-adds sum at most 128 consecutive k-terms
+                          in fp32, each partial sum then added into an fp64
+                          total, so |error| <= 128 * 2^-24 * sum_k |a_ik
+                          b_kj| (relative <= 7.7e-6 for non-negative data;
+                          signed data can cancel, and the bound is then on
+                          the sum of magnitudes, not on |c|). */
   SRTC_MIN_PLUS = 1,   /* tropical (min, id, +, 0) on I32 (default id
-                          INT32_MAX/2, Section 3.1) or F32 (default +inf).
-                          I32 results at or above id are clamped to id, hence
-                          absent; operands must lie in [-id, id]. */
+                          INT32_MAX/2, Section 3.1; id must lie in
+                          1..INT32_MAX/2, SRTC_ERR_ARG otherwise) or F32
+                          (default +inf).  I32 operands must lie in [-id, id]
+                          (checked with validate), so no sum overflows; a
+                          result at or above id is absent: dropped from a
+                          sparse output, stored as id in a dense one. */
   SRTC_OR_AND = 2,     /* boolean (or, false, and, true) on BOOL8 (any nonzero
                           byte is true) and BITS64 frontiers */
   SRTC_MAX_TIMES = 3   /* (max, id, x, 1) on F32/F64; default id 0 (for
@@ -190,7 +213,11 @@ srtc_status srtc_fold(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const
  * C = A (x) B).  Forms:
  *   sparse A x sparse B -> sparse C (CSR, allocated here; with accumulate the
  *       previous C joins the sum and is replaced by new arrays -- the old
- *       arrays stay the caller's).  Synchronizes once (output size).
+ *       arrays stay the caller's: each row's accumulator starts from the old
+ *       row's entries, as one more term of the sum, unless C interleaves its
+ *       letters or has a letter in all three tensors, where the product is
+ *       merged into the old C afterwards).  Synchronizes a few times (bin
+ *       and output sizes).
  *   sparse A x dense B  -> dense C (caller-allocated, fully asynchronous).
  *   dense A x dense B   -> dense C, (+,x) only, on the matrix cores (a
  *       letter in all three tensors makes it a strided batch of GEMMs);
@@ -227,6 +254,36 @@ srtc_status srtc_contract_masked(srtc_ctx *ctx, srtc_semiring sr, const void *ad
                                  const srtc_tensor *A, const char *ib, const srtc_tensor *B, const char *ic,
                                  const srtc_tensor *M, srtc_tensor *C, const srtc_opts *opts, void *stream);
 
+/* Consumer of one row panel of a streamed product (srtc_contract_panels).
+ * C_panel is a CSR matrix (order 2, split 1) holding rows [row0, row0 +
+ * nrows) of C folded to a matrix (rows: C's row letters linearized, columns:
+ * its column letters), with row pointers relative to the panel
+ * (rowptr[0] = 0).  Its three arrays come from the context's allocator and
+ * are the consumer's to keep or release; the work that forms them is on
+ * `stream`, so device work the consumer enqueues there sees them.  Return 0
+ * to continue; nonzero stops the product. */
+typedef int32_t (*srtc_panel_fn)(void *user, int64_t row0, int64_t nrows, srtc_tensor *C_panel,
+                                 void *stream);
+
+/* C[ic] = A[ia] (x) B[ib] for sparse A and B, formed and handed over one
+ * row panel at a time, for outputs larger than the device memory (the
+ * paper maps contractions under a memory constraint, Section 5.1; one GPU
+ * streams the output instead of replicating it).  Panels are consecutive
+ * runs of C's rows cut so that each holds at most `panel_products` products
+ * (<= 0: 2^31), a row with more forming a panel alone; a panel has at most
+ * as many entries as products.  Operands are folded once and the schedule is
+ * chosen once for the whole product (opts->schedule, or as srtc_contract
+ * chooses from the features of all rows); every panel is one SpGEMM of its
+ * rows of A with all of B, then `consume` receives it.  Rules as
+ * srtc_contract, except: no letter in all three tensors, and C lists its
+ * row letters first.  SRTC_ERR_ARG if the consumer stops the product (the
+ * panels handed over so far stay the consumer's).  Synchronizes a few times
+ * per panel. */
+srtc_status srtc_contract_panels(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const char *ia,
+                                 const srtc_tensor *A, const char *ib, const srtc_tensor *B, const char *ic,
+                                 const srtc_opts *opts, int64_t panel_products, srtc_panel_fn consume,
+                                 void *user, void *stream);
+
 /* ----------------------------------------------------------- fixpoint -- */
 
 /* Bellman-Ford as repeated semiring products (Section 4.2):
@@ -258,8 +315,11 @@ srtc_status srtc_fixpoint_ex(srtc_ctx *ctx, srtc_semiring sr, const void *add_id
                              srtc_tensor *X, int64_t max_iters, int32_t steps_per_check, int32_t flags,
                              int64_t *iters_out, void *stream);
 
-/* Multi-source breadth-first levels over the (or,and) semiring with a
- * bit-packed frontier (one uint64 per vertex, bit t = source t, nsrc <= 64).
+/* Multi-source breadth-first levels: Section 4.2's Bellman-Ford iteration
+ * X <- X (+) A (x) X taken over the boolean semiring (or, and) instead of the
+ * tropical one, so level l is the step at which a vertex is first reached,
+ * with a bit-packed frontier (one uint64 per vertex, bit t = source t, nsrc
+ * <= 64).
  * A's pattern gives the edges (entry (i, j) = edge j -> i; values ignored).
  * sources: host array of nsrc vertex ids.  levels: device n x nsrc int32,
  * level 0 at the source, -1 if unreachable.  *depth_out (host) = largest
@@ -346,14 +406,33 @@ srtc_status srtc_apsp_tiskin(srtc_ctx *ctx, const void *add_id, const srtc_tenso
 /* -------------------------------------------------------------- batch -- */
 
 /* Independent problems (an index shared by all three tensors, Sections
- * 3.3.1 and 5.1): C_b = A_b (x) B_b for b < ninst, all sparse CSR matrices,
- * in one set of launches over every instance's rows (persistent work-queue
- * kernels) instead of one set per instance.  Cs[b] receives CSR arrays that
- * point into shared allocations: Cs[0].rowptr/colidx/vals own the memory
- * (free those three to release every instance).  Synchronizes once. */
+ * 3.3.1 and 5.1): C_b[ic] = A_b[ia] (x) B_b[ib] for b < ninst, in one set of
+ * launches over every instance's rows (persistent work-queue kernels)
+ * instead of one set per instance.
+ *   ia, ib, ic  two letters per matrix, shared by all instances: A and B
+ *               share one contracted letter, C = (A's other letter, B's
+ *               other letter), e.g. "ik","kj","ij" or "ki","kj","ij" (A
+ *               transposed).  The instance number is the implicit letter in
+ *               all three tensors.
+ *   As, Bs      sparse matrices (order 2, COO or CSR) of one value type;
+ *               operands not already CSR in (row letter, column letter)
+ *               order are folded per instance first.
+ *   scheds      host int32[ninst] or NULL: instance b's SpGEMM schedule
+ *               (0..SRTC_NUM_SCHEDULES-1, or -1: chosen for that instance as
+ *               srtc_contract chooses).  Instances with the same schedule
+ *               share each launch; the result does not depend on the
+ *               schedules.  NULL: opts->schedule for all (-1: one choice for
+ *               the whole batch).
+ *   opts        sorted / validate / schedule as for srtc_contract (NULL:
+ *               defaults).
+ * Cs[b] receives CSR arrays that point into shared allocations:
+ * Cs[0].rowptr/colidx/vals own the memory (free those three to release
+ * every instance).  Synchronizes a few times (sizes; one features pass per
+ * instance left to choose). */
 srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
                                 int32_t ninst, const srtc_tensor *As, const srtc_tensor *Bs,
-                                srtc_tensor *Cs, const srtc_opts *opts, void *stream);
+                                srtc_tensor *Cs, const char *ia, const char *ib, const char *ic,
+                                const int32_t *scheds, const srtc_opts *opts, void *stream);
 
 /* Batched Bellman-Ford: X_b <- X_b (+) A_b (x) X_b for every instance until
  * each is unchanged; converged instances drop out.  All X_b have the same
@@ -366,23 +445,42 @@ srtc_status srtc_batch_fixpoint(srtc_ctx *ctx, srtc_semiring sr, const void *add
 /* --------------------------------------------------------- scheduling -- */
 
 /* The 32 scale-free features of an SpGEMM problem A (x) B (both CSR
- * matrices): histograms of row lengths and row product counts, sizes, a
- * sampled compression-ratio estimate, skew measures and the semiring/dtype.
- * out: host float[SRTC_NUM_FEATURES].  Synchronizes once. */
+ * matrices), the inputs of the schedule choice (Section 5.1 selects among
+ * decompositions with performance models driven by sizes and nonzero
+ * fractions; Section 7 proposes adjusting such models automatically).  With
+ * m rows, w_i = sum over A's row i of the lengths of the B rows it meets
+ * (products), out[] (host float[SRTC_NUM_FEATURES]) holds:
+ *   0..9    fraction of rows of A whose length has bit length b (b >= 9 in 9)
+ *   10..19  fraction of rows whose w_i has (bit length + 1) / 2 = b (bin 0:
+ *           rows without products; b >= 9 in 19)
+ *   20..23  log2 of m + 1, columns of B + 1, nnz(A) + 1, sum_i w_i + 1
+ *   24      log2 of the compression ratio sum w / outputs over the rows
+ *           floor(t m / s), t < s = min(512, m), outputs counted
+ *           structurally (1 when nothing is sampled)
+ *   25, 26  log2 of max_i w_i + 1 and of the longest row of A + 1
+ *   27      coefficient of variation of w (population; 0 for a zero mean)
+ *   28..31  one-hot of the semiring.
+ * Synchronizes a few times. */
 srtc_status srtc_features(srtc_ctx *ctx, srtc_semiring sr, const srtc_tensor *A,
                           const srtc_tensor *B, float *out, void *stream);
 
-/* Exhaustive autotuner: time every schedule on A (x) B (median of `reps`
- * runs after one warm-up, the paper's Section 6 protocol), cache the winner
- * under the feature vector, return it in *best and the median times in
- * times_ms (host float[SRTC_NUM_SCHEDULES], may be NULL). */
+/* Exhaustive autotuner (Section 5.1's search over candidate mappings, with
+ * measured instead of modelled costs): time every schedule on A (x) B
+ * (median of `reps` runs after one warm-up, the paper's Section 6
+ * protocol), cache the winner under the feature vector, return it in *best
+ * and the median times in times_ms (host float[SRTC_NUM_SCHEDULES], may be
+ * NULL). */
 srtc_status srtc_autotune(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
                           const srtc_tensor *A, const srtc_tensor *B, int32_t reps,
                           int32_t *best, float *times_ms, void *stream);
 
-/* Learned selector: schedule predicted for a feature vector (host float[32])
- * by the context's MLP (32 -> 64 -> 64 -> SRTC_NUM_SCHEDULES, ReLU),
- * evaluated on the GPU.  SRTC_ERR_UNSUPPORTED if no network is loaded. */
+/* Learned selector, the automatically adjusted performance model Section 7
+ * proposes (fitted to measured times instead of Section 5.1's analytic
+ * models): the schedule predicted for a feature vector (host float[32]) by
+ * the context's MLP (32 -> 64 -> 64 -> SRTC_NUM_SCHEDULES, ReLU), evaluated
+ * on the GPU (the network stays on the device; one 128-byte upload, one
+ * kernel, one 4-byte read on the context's current stream).
+ * SRTC_ERR_UNSUPPORTED if no network is loaded. */
 srtc_status srtc_select(srtc_ctx *ctx, const float *features, int32_t *schedule);
 
 typedef struct srtc_train_cfg {
@@ -393,11 +491,16 @@ typedef struct srtc_train_cfg {
   uint64_t seed;       /* weight initialization and shuffling */
 } srtc_train_cfg;
 
-/* Train the selector on nsamples rows of features X (host, nsamples x 32)
- * and per-schedule targets T (host, nsamples x SRTC_NUM_SCHEDULES: log2
- * time, centered per sample) with the MSE loss and Adam; forward, backward
- * and update run as HIP kernels.  Features are standardized with statistics
- * kept in the network.  *final_loss (host) = mean loss of the last epoch. */
+/* Train the selector (the performance model of srtc_select, Sections 5.1
+ * and 7) on nsamples rows of features X (host, nsamples x 32) and
+ * per-schedule targets T (host, nsamples x SRTC_NUM_SCHEDULES: log2 time,
+ * centered per sample) with the MSE loss and Adam; forward, backward and
+ * update run as HIP kernels.  Features are standardized with statistics
+ * kept in the network.  A context that already holds a network continues
+ * training it (weights, moments and step count).  *final_loss (host) = mean
+ * loss of the last epoch.  save/load write and read the network, its
+ * feature statistics and Adam state (SRTC_ERR_FORMAT: not a selector file;
+ * SRTC_ERR_ARG: the file cannot be opened or written). */
 srtc_status srtc_selector_train(srtc_ctx *ctx, const float *X, const float *T, int32_t nsamples,
                                 const srtc_train_cfg *cfg, float *final_loss, void *stream);
 srtc_status srtc_selector_save(srtc_ctx *ctx, const char *path);
@@ -414,6 +517,14 @@ srtc_status srtc_mlp_forward(srtc_ctx *ctx, const float *params, const float *X,
 srtc_status srtc_mlp_loss_grad(srtc_ctx *ctx, const float *params, const float *X,
                                const float *T, int32_t n, float *loss, float *grads,
                                void *stream);
+/* One Adam update (Kingma and Ba) of all srtc_mlp_num_params() parameters,
+ * in place, as the training loop makes it:
+ *   m1 = beta1 m1 + (1 - beta1) g;  m2 = beta2 m2 + (1 - beta2) g^2
+ *   params -= lr (m1 / (1 - beta1^step)) / (sqrt(m2 / (1 - beta2^step)) + eps)
+ * params, grads (g), m1, m2: device fp32, same layout; step >= 1 (the
+ * count of updates including this one).  Fully asynchronous. */
+srtc_status srtc_mlp_adam_step(srtc_ctx *ctx, float *params, const float *grads, float *m1, float *m2,
+                               int64_t step, float lr, float beta1, float beta2, float eps, void *stream);
 int64_t srtc_mlp_num_params(void);
 
 #ifdef __cplusplus

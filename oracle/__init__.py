@@ -458,3 +458,71 @@ def transform(op, alpha, ia, A, ib, B, ic, C):
     if op == "fma":
         return (C + C.dtype.type(alpha) * a * b).astype(C.dtype)
     return (C / (a + b)).astype(C.dtype)
+
+
+def _bit_length(x):
+    """Bit length of non-negative integers (0 for 0): floor(log2 x) + 1."""
+    x = np.asarray(x, dtype=np.int64)
+    _, e = np.frexp(x.astype(np.float64))  # x = f 2^e with 0.5 <= f < 1, exact below 2^53
+    return np.where(x > 0, e, 0).astype(np.int64)
+
+
+def features(semiring, A: CSR, B: CSR):
+    """The 32 schedule features of the product A (x) B, from their
+    definitions (the inputs of the schedule choice; Section 5.1 picks among
+    mappings with performance models driven by sizes and nonzero counts).
+    With m rows and w_i = sum over the entries (i, k) of A of the length of
+    B's row k (the products of row i):
+      0..9    fraction of rows of A whose length has bit length b (b >= 9: 9)
+      10..19  fraction of rows with (bit length of w_i + 1) // 2 = b (w_i = 0:
+              bin 0; b >= 9: 19)
+      20..23  log2(m + 1), log2(columns of B + 1), log2(nnz(A) + 1),
+              log2(sum w + 1)
+      24      log2 of sum w / sum outputs over the rows floor(t m / s),
+              t < s = min(512, m); an output is a distinct column reached
+              from the row (by structure); 1 if no output was sampled
+      25, 26  log2(max w + 1), log2(longest row of A + 1)
+      27      population standard deviation of w over its mean (0 if the
+              mean is 0)
+      28..31  one-hot of the semiring.
+    Returns float32[32]."""
+    out = np.zeros(32, dtype=np.float32)
+    m = A.nrows
+    mm = float(max(m, 1))
+    nz = np.diff(A.rowptr).astype(np.int64)
+    blen = np.diff(B.rowptr).astype(np.int64)
+    w = np.zeros(m, dtype=np.int64)
+    if A.nnz:
+        np.add.at(w, np.repeat(np.arange(m, dtype=np.int64), nz), blen[A.col[:A.nnz]])
+    bn = np.minimum(9, _bit_length(nz))
+    bw = np.where(w == 0, 0, np.minimum(9, (_bit_length(w) + 1) // 2))
+    for b in range(10):
+        out[b] = np.float32(int(np.count_nonzero(bn == b)) / mm)
+        out[10 + b] = np.float32(int(np.count_nonzero(bw == b)) / mm)
+    ns = min(512, m)
+    cr = 1.0
+    if ns > 0 and A.nnz > 0 and B.nnz > 0:
+        sw_s, sn_s = 0, 0
+        for t in range(ns):
+            i = (t * m) // ns
+            ks = A.col[A.rowptr[i]:A.rowptr[i + 1]]
+            cols = [B.col[B.rowptr[k]:B.rowptr[k + 1]] for k in ks]
+            sw_s += int(w[i])
+            if cols:
+                sn_s += int(np.unique(np.concatenate(cols)).size)
+        if sn_s > 0:
+            cr = sw_s / sn_s
+    sw = int(w.sum())
+    sq = int(np.sum(w.astype(object) * w.astype(object))) if m else 0
+    mean = sw / mm
+    var = max(0.0, float(sq) / mm - mean * mean)
+    out[20] = np.float32(np.log2(m + 1.0))
+    out[21] = np.float32(np.log2(B.ncols + 1.0))
+    out[22] = np.float32(np.log2(A.nnz + 1.0))
+    out[23] = np.float32(np.log2(sw + 1.0))
+    out[24] = np.float32(np.log2(cr))
+    out[25] = np.float32(np.log2(float(w.max() if m else 0) + 1.0))
+    out[26] = np.float32(np.log2(float(nz.max() if m else 0) + 1.0))
+    out[27] = np.float32(np.sqrt(var) / mean if mean > 0 else 0.0)
+    out[28 + SEMIRINGS[semiring]] = 1.0
+    return out

@@ -77,6 +77,8 @@ class _TrainCfg(ctypes.Structure):
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
 _FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_PANEL = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(_Tensor),
+                          ctypes.c_void_p)
 
 _lib = None
 
@@ -107,7 +109,10 @@ def lib():
             "srtc_transform": ([P, ctypes.c_int, ctypes.c_double, S, T, S, T, S, T, P], ctypes.c_int),
             "srtc_jacobi": ([P, T, T, T, ctypes.c_double, I64_, I32_, ctypes.POINTER(I64_),
                              ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
-            "srtc_batch_contract": ([P, ctypes.c_int, P, I32_, T, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
+            "srtc_batch_contract": ([P, ctypes.c_int, P, I32_, T, T, T, S, S, S, ctypes.POINTER(I32_),
+                                     ctypes.POINTER(_Opts), P], ctypes.c_int),
+            "srtc_contract_panels": ([P, ctypes.c_int, P, S, T, S, T, S, ctypes.POINTER(_Opts), I64_, _PANEL, P, P],
+                                     ctypes.c_int),
             "srtc_batch_fixpoint": ([P, ctypes.c_int, P, I32_, T, T, I64_, I32_, ctypes.POINTER(I64_), P],
                                     ctypes.c_int),
             "srtc_features": ([P, ctypes.c_int, T, T, ctypes.POINTER(ctypes.c_float), P], ctypes.c_int),
@@ -120,6 +125,11 @@ def lib():
             "srtc_selector_load": ([P, S], ctypes.c_int),
             "srtc_mlp_forward": ([P, P, P, I32_, P, P], ctypes.c_int),
             "srtc_mlp_loss_grad": ([P, P, P, P, I32_, P, P, P], ctypes.c_int),
+            "srtc_mlp_adam_step": ([P, P, P, P, P, I64_, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, P], ctypes.c_int),
+            "srtc_profile_enable": ([P, I32_], ctypes.c_int),
+            "srtc_profile_query": ([P, I32_, ctypes.c_char_p, I32_, ctypes.POINTER(I64_),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "srtc_mlp_num_params": ([], I64_),
         }
         for name, (args, res) in sig.items():
@@ -351,6 +361,36 @@ class Context:
             return self._csr_out(cd)
         return C
 
+    def contract_panels(self, semiring, ia: str, A, ib: str, B, ic: str, consume, panel_products: int = 0,
+                        add_id=None, schedule: int = -1, sorted: bool = True, validate: bool = False) -> int:
+        """C[ic] = A[ia] (x) B[ib] streamed by row panels: ``consume(row0, P)``
+        receives each panel P (a CSR of C's rows row0 .. row0 + P.shape[0] - 1,
+        folded to a matrix) and may keep it; returning False stops the
+        product (SrtcError).  Panels hold at most ``panel_products`` products
+        each (0: 2^31).  Returns the number of panels."""
+        ad, bd = _desc(A), _desc(B)
+        opts = _Opts(schedule, 1 if sorted else 0, 1 if validate else 0, 0)
+        errors = []
+        count = [0]
+
+        def _cb(user, row0, nrows, desc, stream):
+            try:
+                P = self._csr_out(desc.contents)
+                count[0] += 1
+                return 1 if consume(int(row0), P) is False else 0
+            except BaseException as e:  # noqa: BLE001 -- re-raised after the call
+                errors.append(e)
+                return 1
+
+        cb = _PANEL(_cb)
+        st = lib().srtc_contract_panels(self._h, _sr(semiring), _add_id(add_id, ad.dtype), ia.encode(),
+                                        ctypes.byref(ad), ib.encode(), ctypes.byref(bd), ic.encode(),
+                                        ctypes.byref(opts), int(panel_products), cb, None, self._stream())
+        if errors:
+            raise errors[0]
+        self._check(st)
+        return count[0]
+
     def contract_masked(self, semiring, ia: str, A, ib: str, B, ic: str, M, add_id=None,
                         validate: bool = False) -> "CSR":
         """C[ic] = M (.) (A[ia] (x) B[ib]): only positions in M's pattern
@@ -445,15 +485,24 @@ class Context:
         return D, H, r.value
 
     def batch_contract(self, semiring, As: List[CSR], Bs: List[CSR], add_id=None, schedule: int = -1,
-                       sorted: bool = True) -> List[CSR]:
-        """C_b = A_b (x) B_b for every instance in one set of launches."""
+                       sorted: bool = True, ia: str = "ik", ib: str = "kj", ic: str = "ij",
+                       schedules: Optional[Sequence[int]] = None, validate: bool = False) -> List[CSR]:
+        """C_b[ic] = A_b[ia] (x) B_b[ib] for every instance in one set of
+        launches; ``schedules`` (one id per instance, -1 = choose) or one
+        ``schedule`` for all."""
         n = len(As)
         arrA = (_Tensor * n)(*[_desc(a) for a in As])
         arrB = (_Tensor * n)(*[_desc(b) for b in Bs])
         arrC = (_Tensor * n)()
-        opts = _Opts(schedule, 1 if sorted else 0, 0, 0)
+        opts = _Opts(schedule, 1 if sorted else 0, 1 if validate else 0, 0)
+        sch = None
+        if schedules is not None:
+            if len(schedules) != n:
+                raise SrtcError(-1, "one schedule per instance")
+            sch = (ctypes.c_int32 * n)(*[int(x) for x in schedules])
         st = lib().srtc_batch_contract(self._h, _sr(semiring), _add_id(add_id, arrA[0].dtype), n, arrA, arrB, arrC,
-                                       ctypes.byref(opts), self._stream())
+                                       ia.encode(), ib.encode(), ic.encode(), sch, ctypes.byref(opts),
+                                       self._stream())
         self._check(st)
         c0 = arrC[0]
         base_rp = self._live.pop(c0.rowptr)
@@ -529,6 +578,12 @@ class Context:
         self._check(lib().srtc_mlp_forward(self._h, _ptr(params), _ptr(X), int(X.shape[0]), _ptr(Y),
                                            self._stream()))
         return Y
+
+    def mlp_adam_step(self, params: torch.Tensor, grads: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor,
+                      step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        """One Adam update of params, m1 and m2 in place (step >= 1)."""
+        self._check(lib().srtc_mlp_adam_step(self._h, _ptr(params), _ptr(grads), _ptr(m1), _ptr(m2), int(step),
+                                             float(lr), float(beta1), float(beta2), float(eps), self._stream()))
 
     def mlp_loss_grad(self, params: torch.Tensor, X: torch.Tensor, T: torch.Tensor):
         loss = torch.zeros(1, dtype=torch.float32, device=self.device)

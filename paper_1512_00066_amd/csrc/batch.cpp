@@ -135,13 +135,18 @@ void check_matrix(const srtc_tensor &t, const char *name) {
   if (t.nnz < 0 || !t.rowptr || (t.nnz > 0 && (!t.colidx || !t.vals))) fail(SRTC_ERR_ARG, std::string(name) + ": bad CSR");
 }
 
+CsrView view_of(const srtc_tensor &t) {
+  return CsrView{t.dims[0], t.dims[1], t.nnz, t.rowptr, t.colidx, t.vals};
+}
+
 // Lay instances end to end; columns shift by col_shift[b].
-void build_block_diag(Ctx *c, const srtc_tensor *T, int ninst, const std::vector<int64_t> &col_shift, int64_t cols,
-                      BlockDiag *bd, hipStream_t s) {
+void build_block_diag(Ctx *c, const std::vector<CsrView> &T, int dt, const std::vector<int64_t> &col_shift,
+                      int64_t cols, BlockDiag *bd, hipStream_t s) {
+  const int ninst = (int)T.size();
   bd->rowoff.assign(ninst + 1, 0);
   bd->nnzoff.assign(ninst + 1, 0);
   for (int b = 0; b < ninst; b++) {
-    bd->rowoff[b + 1] = bd->rowoff[b] + T[b].dims[0];
+    bd->rowoff[b + 1] = bd->rowoff[b] + T[b].m;
     bd->nnzoff[b + 1] = bd->nnzoff[b] + T[b].nnz;
   }
   bd->coloff = col_shift;
@@ -151,8 +156,8 @@ void build_block_diag(Ctx *c, const srtc_tensor *T, int ninst, const std::vector
   std::vector<uint64_t> ptrs(3 * (size_t)ninst);
   for (int b = 0; b < ninst; b++) {
     ptrs[b] = (uint64_t)T[b].rowptr;
-    ptrs[ninst + b] = (uint64_t)T[b].colidx;
-    ptrs[2 * ninst + b] = (uint64_t)T[b].vals;
+    ptrs[ninst + b] = (uint64_t)T[b].col;
+    ptrs[2 * ninst + b] = (uint64_t)T[b].val;
   }
   bd->ptrs = upload(c, ptrs, s);
   bd->rowoff_d = upload(c, bd->rowoff, s);
@@ -166,7 +171,7 @@ void build_block_diag(Ctx *c, const srtc_tensor *T, int ninst, const std::vector
   t.nnzoff = bd->nnzoff_d.as<int64_t>();
   t.coloff = bd->coloff_d.as<int64_t>();
   t.ninst = ninst;
-  const size_t es = dtype_size(T[0].dtype);
+  const size_t es = dtype_size(dt);
   bd->rp = Buf(c, sizeof(int64_t) * (size_t)(bd->rows + 1));
   bd->col = Buf(c, sizeof(int32_t) * (size_t)std::max<int64_t>(bd->nnz, 1));
   bd->val = Buf(c, es * (size_t)std::max<int64_t>(bd->nnz, 1));
@@ -187,45 +192,153 @@ void build_block_diag(Ctx *c, const srtc_tensor *T, int ninst, const std::vector
   }
 }
 
+void build_block_diag(Ctx *c, const srtc_tensor *T, int ninst, const std::vector<int64_t> &col_shift, int64_t cols,
+                      BlockDiag *bd, hipStream_t s) {
+  std::vector<CsrView> v(ninst);
+  for (int b = 0; b < ninst; b++) v[b] = view_of(T[b]);
+  build_block_diag(c, v, T[0].dtype, col_shift, cols, bd, s);
+}
+
+// Row ids b0 .. b0 + n - 1 of every listed instance, laid end to end.
+__global__ void fill_rows(const int64_t *__restrict__ starts, const int64_t *__restrict__ offs, int nr, int64_t total,
+                          int32_t *__restrict__ rows) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = find_inst(offs, nr, e);
+    rows[e] = (int32_t)(starts[r] + (e - offs[r]));
+  }
+}
+
 }  // namespace
 
 extern "C" {
 
 srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int32_t ninst,
-                                const srtc_tensor *As, const srtc_tensor *Bs, srtc_tensor *Cs, const srtc_opts *opts,
+                                const srtc_tensor *As, const srtc_tensor *Bs, srtc_tensor *Cs, const char *ia,
+                                const char *ib, const char *ic, const int32_t *scheds, const srtc_opts *opts,
                                 void *stream) {
   return guard(ctx, [&] {
     if (ninst <= 0 || !As || !Bs || !Cs) fail(SRTC_ERR_ARG, "batch: bad arguments");
+    if (!ia || !ib || !ic) fail(SRTC_ERR_INDEX, "batch: null index string");
+    const std::string a(ia), b(ib), cs(ic);
+    // each instance is C[ic] = A[ia] (x) B[ib] over matrices: one row, one
+    // contracted and one column letter (the instance number is the letter
+    // shared by all three tensors, Section 3.3.1)
+    if (a.size() != 2 || b.size() != 2 || cs.size() != 2 || a[0] == a[1] || b[0] == b[1] || cs[0] == cs[1])
+      fail(SRTC_ERR_INDEX, "batch: two distinct letters per matrix");
+    char kk = 0;
+    for (char ch : a)
+      if (b.find(ch) != std::string::npos) kk = ch;
+    if (!kk || cs.find(kk) != std::string::npos) fail(SRTC_ERR_INDEX, "batch: A and B must share one contracted letter");
+    const char ri = a[0] == kk ? a[1] : a[0], cj = b[0] == kk ? b[1] : b[0];
+    if (ri == cj || cs != std::string{ri, cj})
+      fail(SRTC_ERR_INDEX, "batch: C's letters must be A's free letter, then B's");
     const int dt = As[0].dtype;
-    for (int b = 0; b < ninst; b++) {
-      check_matrix(As[b], "A");
-      check_matrix(Bs[b], "B");
-      if (As[b].dtype != dt || Bs[b].dtype != dt) fail(SRTC_ERR_DTYPE, "batch: mixed value types");
-      if (As[b].dims[1] != Bs[b].dims[0]) fail(SRTC_ERR_DIM, "batch: inner dimensions differ");
-    }
+    srtc_opts o{-1, 1, 0, 0};
+    if (opts) o = *opts;
     const IdVal id = make_id_public(sr, dt, add_id);
     Ctx *c = &ctx->c;
     hipStream_t s = (hipStream_t)stream;
     ctx->c.stream = s;
+    for (int q = 0; q < ninst; q++) {
+      for (const srtc_tensor *t : {&As[q], &Bs[q]}) {
+        if (t->order != 2 || t->format == SRTC_DENSE) fail(SRTC_ERR_FORMAT, "batch: sparse matrices (COO or CSR) required");
+        if (t->nnz < 0 || (t->format == SRTC_CSR && (!t->rowptr || t->split != 1)) ||
+            (t->nnz > 0 && (!t->vals || (t->format == SRTC_CSR ? !t->colidx : !t->coo_keys))))
+          fail(SRTC_ERR_ARG, "batch: bad sparse operand");
+        if (t->dtype != dt) fail(SRTC_ERR_DTYPE, "batch: mixed value types");
+        if (t->dims[0] <= 0 || t->dims[1] <= 0) fail(SRTC_ERR_DIM, "batch: nonpositive dimension");
+      }
+      if (As[q].dims[a[0] == kk ? 0 : 1] != Bs[q].dims[b[0] == kk ? 0 : 1])
+        fail(SRTC_ERR_DIM, "batch: inner dimensions differ");
+      if (scheds && (scheds[q] < -1 || scheds[q] >= SRTC_NUM_SCHEDULES)) fail(SRTC_ERR_ARG, "batch: schedule id out of range");
+    }
+    if (o.validate || c->validate_all)
+      for (int q = 0; q < ninst; q++) {
+        validate_operand(c, sr, &As[q], "A", s, &id);
+        validate_operand(c, sr, &Bs[q], "B", s, &id);
+      }
+    // every operand as a (row letter, column letter) CSR: borrowed when it
+    // already is one, else folded (transposed) per instance
+    const std::string arow{ri}, acol{kk}, brow{kk}, bcol{cj};
+    std::vector<CsrOut> owned;
+    owned.reserve(2 * (size_t)ninst);
+    std::vector<CsrView> av(ninst), bv(ninst);
+    auto as_csr = [&](const srtc_tensor &t, const std::string &idx, const std::string &rows, const std::string &cols) {
+      if (t.format == SRTC_CSR && idx == rows + cols) return view_of(t);
+      std::vector<int> rm{(int)idx.find(rows[0])}, cm{(int)idx.find(cols[0])};
+      const int64_t nr = t.dims[rm[0]], nc = t.dims[cm[0]];
+      Buf keys(c, sizeof(int64_t) * (size_t)std::max<int64_t>(t.nnz, 1));
+      const int64_t *src = t.coo_keys;
+      Buf tmp;
+      if (t.format == SRTC_CSR) {
+        tmp = Buf(c, sizeof(int64_t) * (size_t)std::max<int64_t>(t.nnz, 1));
+        csr_to_keys(view_of(t), tmp.as<int64_t>(), s);
+        src = tmp.as<int64_t>();
+      }
+      remap_keys(c, src, t.nnz, 2, t.dims, 1, rm.data(), 1, cm.data(), keys.as<int64_t>(), s);
+      owned.emplace_back();
+      owned.back().kind = SCRATCH;
+      fold_keys_to_csr(c, sr, dt, id, keys.as<int64_t>(), t.vals, t.nnz, nr, nc, &owned.back(), s);
+      const CsrOut &f = owned.back();
+      return CsrView{f.m, f.n, f.nnz, f.rowptr.as<int64_t>(), f.col.as<int32_t>(), f.val.p};
+    };
+    for (int q = 0; q < ninst; q++) {
+      av[q] = as_csr(As[q], a, arow, acol);
+      bv[q] = as_csr(Bs[q], b, brow, bcol);
+    }
     // A's columns follow B's row blocks; B keeps each instance's own columns
     // (a row of A only reaches B rows of its instance), so C comes out with
     // instance-local columns and every column-width cost of the SpGEMM
     // (bitmaps, dense windows) is that of the widest instance, not of the sum
     std::vector<int64_t> a_shift(ninst), b_shift(ninst, 0);
-    int64_t kk = 0, nn = 0;
-    for (int b = 0; b < ninst; b++) {
-      a_shift[b] = kk;
-      kk += As[b].dims[1];
-      nn = std::max<int64_t>(nn, Bs[b].dims[1]);
+    int64_t kt = 0, nn = 0;
+    for (int q = 0; q < ninst; q++) {
+      a_shift[q] = kt;
+      kt += av[q].n;
+      nn = std::max<int64_t>(nn, bv[q].n);
     }
-    if (kk >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "batch: more than 2^31-2 inner rows in total");
+    if (kt >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "batch: more than 2^31-2 inner rows in total");
     BlockDiag A, B;
-    build_block_diag(c, As, ninst, a_shift, kk, &A, s);
-    build_block_diag(c, Bs, ninst, b_shift, nn, &B, s);
-    const int sched = (opts && opts->schedule >= 0) ? opts->schedule : 0;
-    const int sorted = opts ? opts->sorted : 1;
+    build_block_diag(c, av, dt, a_shift, kt, &A, s);
+    build_block_diag(c, bv, dt, b_shift, nn, &B, s);
+    if (A.rows >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "batch: more than 2^31-2 rows in total");
+    // schedules: per instance (-1 chooses for that instance), else one for
+    // the whole batch; instances sharing a schedule form one row group
+    std::vector<int> isched(ninst);
+    if (scheds) {
+      for (int q = 0; q < ninst; q++)
+        isched[q] = scheds[q] >= 0 ? scheds[q] : choose_schedule(ctx, sr, dt, av[q], bv[q], -1, s);
+    } else {
+      const int one = choose_schedule(ctx, sr, dt, A.view(), B.view(), o.schedule, s);
+      for (int q = 0; q < ninst; q++) isched[q] = one;
+    }
     CsrOut C;
-    spgemm(c, sr, dt, id, A.view(), B.view(), sched, sorted, &C, nullptr, s);
+    std::vector<RowGroup> groups;
+    std::vector<Buf> maps;
+    bool uniform = true;
+    for (int q = 1; q < ninst; q++) uniform = uniform && isched[q] == isched[0];
+    if (uniform) {
+      spgemm(c, sr, dt, id, A.view(), B.view(), isched[0], o.sorted, &C, nullptr, s);
+    } else {
+      for (int k = 0; k < SRTC_NUM_SCHEDULES; k++) {
+        std::vector<int64_t> starts, offs{0};
+        for (int q = 0; q < ninst; q++)
+          if (isched[q] == k && A.rowoff[q + 1] > A.rowoff[q]) {
+            starts.push_back(A.rowoff[q]);
+            offs.push_back(offs.back() + A.rowoff[q + 1] - A.rowoff[q]);
+          }
+        if (starts.empty()) continue;
+        const int64_t nrow = offs.back();
+        Buf sd = upload(c, starts, s), od = upload(c, offs, s);
+        Buf rows(c, sizeof(int32_t) * (size_t)nrow);
+        fill_rows<<<gridn(nrow), 256, 0, s>>>(sd.as<int64_t>(), od.as<int64_t>(), (int)starts.size(), nrow,
+                                             rows.as<int32_t>());
+        SRTC_LAUNCH_CHECK("fill_rows");
+        groups.push_back(RowGroup{rows.as<int32_t>(), nrow, k});
+        maps.push_back(std::move(rows));
+      }
+      spgemm_grouped(c, sr, dt, id, A.view(), B.view(), groups, o.sorted, &C, nullptr, s);
+    }
     // per-instance views
     Buf rp_all(c, sizeof(int64_t) * (size_t)(A.rows + ninst), OUTPUT);
     split_rowptr<<<gridn(A.rows + ninst), 256, 0, s>>>(C.rowptr.as<int64_t>(), A.rowoff_d.as<int64_t>(), ninst, A.rows,
@@ -240,20 +353,20 @@ srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add
     int64_t *rpa = (int64_t *)rp_all.release();
     int32_t *col = (int32_t *)C.col.release();
     char *val = (char *)C.val.release();
-    for (int b = 0; b < ninst; b++) {
-      srtc_tensor &o = Cs[b];
-      o.order = 2;
-      o.format = SRTC_CSR;
-      o.dtype = dt;
-      o.split = 1;
-      for (int q = 0; q < SRTC_MAX_ORDER; q++) o.dims[q] = 0;
-      o.dims[0] = As[b].dims[0];
-      o.dims[1] = Bs[b].dims[1];
-      o.nnz = hst[b + 1] - hst[b];
-      o.coo_keys = nullptr;
-      o.rowptr = rpa + A.rowoff[b] + b;
-      o.colidx = col + hst[b];
-      o.vals = val + es * (size_t)hst[b];
+    for (int q = 0; q < ninst; q++) {
+      srtc_tensor &out = Cs[q];
+      out.order = 2;
+      out.format = SRTC_CSR;
+      out.dtype = dt;
+      out.split = 1;
+      for (int r = 0; r < SRTC_MAX_ORDER; r++) out.dims[r] = 0;
+      out.dims[0] = av[q].m;
+      out.dims[1] = bv[q].n;
+      out.nnz = hst[q + 1] - hst[q];
+      out.coo_keys = nullptr;
+      out.rowptr = rpa + A.rowoff[q] + q;
+      out.colidx = col + hst[q];
+      out.vals = val + es * (size_t)hst[q];
     }
   });
 }

@@ -202,7 +202,9 @@ IdVal make_id(int sr, int dt, const void *add_id) {
     case SRTC_MIN_PLUS:
       if (dt == SRTC_I32) {
         v.i = add_id ? *(const int32_t *)add_id : (int32_t)(INT32_MAX / 2);
-        if (v.i <= 0) fail(SRTC_ERR_ARG, "(min,+) int identity must be positive");
+        // a product of two operands in [-id, id] then stays inside int32
+        if (v.i <= 0 || v.i > INT32_MAX / 2)
+          fail(SRTC_ERR_ARG, "(min,+) int identity must lie in 1..INT32_MAX/2");
       } else if (dt == SRTC_PATH64) {
         // a packed path: the identity's weight (its hop count must be 0)
         const uint64_t pv = add_id ? *(const uint64_t *)add_id : (uint64_t)(INT32_MAX / 2) << 32;
@@ -407,9 +409,134 @@ __global__ void bfs_init(const int64_t *src, int nsrc, uint64_t *front, uint64_t
   }
 }
 
+// ---------------------------------------------------- accumulate (+=) --
+// C_new = C_old (+) A (x) B as one product: A' = [A | I] and B' = [B ; C_old]
+// give A' (x) B' = A (x) B (+) I (x) C_old, and I (x) C_old = C_old because
+// the identity's entries are the multiplicative identity.  Each row's
+// accumulator thus starts from (holds) the old row's values, the symbolic
+// pass counts the union of patterns, and no sort is needed.
+__global__ void aug_a_rowptr(const int64_t *__restrict__ rpA, int64_t m, int64_t *__restrict__ rp) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= m; i += (int64_t)gridDim.x * blockDim.x)
+    rp[i] = rpA[i] - rpA[0] + i;
+}
+
+template <class V>
+__global__ void aug_a_entries(const int64_t *__restrict__ rpA, const int32_t *__restrict__ cA, const V *__restrict__ vA,
+                              int64_t m, int64_t k, V one, const int64_t *__restrict__ rp, int32_t *__restrict__ col,
+                              V *__restrict__ val) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  for (int64_t i = wid; i < m; i += nw) {
+    const int64_t a = rpA[i], n = rpA[i + 1] - a, o = rp[i];
+    for (int64_t q = lane_id(); q < n; q += WAVE) {
+      col[o + q] = cA[a + q];
+      val[o + q] = vA[a + q];
+    }
+    if (lane_id() == 0) {
+      col[o + n] = (int32_t)(k + i);  // after every column of A: the row stays ascending
+      val[o + n] = one;
+    }
+  }
+}
+
+__global__ void aug_b_rowptr(const int64_t *__restrict__ rpB, int64_t k, const int64_t *__restrict__ rpC, int64_t m,
+                             int64_t *__restrict__ rp) {
+  const int64_t b0 = rpB[0], nb = rpB[k] - b0, c0 = rpC[0];
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= k + m; r += (int64_t)gridDim.x * blockDim.x)
+    rp[r] = r <= k ? rpB[r] - b0 : nb + (rpC[r - k] - c0);
+}
+
+template <class V>
+__global__ void aug_b_entries(const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB,
+                              const V *__restrict__ vB, int64_t nb, const int64_t *__restrict__ rpC,
+                              const int32_t *__restrict__ cC, const V *__restrict__ vC, int64_t nc,
+                              int32_t *__restrict__ col, V *__restrict__ val) {
+  const int64_t b0 = rpB[0], c0 = rpC[0];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nb + nc; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nb) {
+      col[e] = cB[b0 + e];
+      val[e] = vB[b0 + e];
+    } else {
+      col[e] = cC[c0 + e - nb];
+      val[e] = vC[c0 + e - nb];
+    }
+  }
+}
+
+unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)); }
+
+// The augmented operands of C_old (+) A (x) B; views into `keep`.
+struct Augmented {
+  Buf arp, acol, aval, brp, bcol, bval;
+  CsrView a, b;
+};
+
+template <class V>
+void augment_typed(Ctx *c, const CsrView &A, const CsrView &B, const CsrView &Cold, V one, Augmented *g,
+                   hipStream_t s) {
+  const int64_t m = A.m, k = A.n;
+  const int64_t nA = A.nnz + m, nB = B.nnz + Cold.nnz;
+  g->arp = Buf(c, sizeof(int64_t) * (size_t)(m + 1));
+  g->acol = Buf(c, sizeof(int32_t) * (size_t)std::max<int64_t>(nA, 1));
+  g->aval = Buf(c, sizeof(V) * (size_t)std::max<int64_t>(nA, 1));
+  g->brp = Buf(c, sizeof(int64_t) * (size_t)(k + m + 1));
+  g->bcol = Buf(c, sizeof(int32_t) * (size_t)std::max<int64_t>(nB, 1));
+  g->bval = Buf(c, sizeof(V) * (size_t)std::max<int64_t>(nB, 1));
+  aug_a_rowptr<<<grid_for(m + 1), 256, 0, s>>>(A.rowptr, m, g->arp.as<int64_t>());
+  SRTC_LAUNCH_CHECK("aug_a_rowptr");
+  aug_a_entries<V><<<grid_for(m * WAVE), 256, 0, s>>>(A.rowptr, A.col, (const V *)A.val, m, k, one,
+                                                       g->arp.as<int64_t>(), g->acol.as<int32_t>(), g->aval.as<V>());
+  SRTC_LAUNCH_CHECK("aug_a_entries");
+  aug_b_rowptr<<<grid_for(k + m + 1), 256, 0, s>>>(B.rowptr, k, Cold.rowptr, m, g->brp.as<int64_t>());
+  SRTC_LAUNCH_CHECK("aug_b_rowptr");
+  if (nB > 0) {
+    aug_b_entries<V><<<grid_for(nB), 256, 0, s>>>(B.rowptr, B.col, (const V *)B.val, B.nnz, Cold.rowptr, Cold.col,
+                                                   (const V *)Cold.val, Cold.nnz, g->bcol.as<int32_t>(),
+                                                   g->bval.as<V>());
+    SRTC_LAUNCH_CHECK("aug_b_entries");
+  }
+  g->a = CsrView{m, k + m, nA, g->arp.as<int64_t>(), g->acol.as<int32_t>(), g->aval.p};
+  g->b = CsrView{k + m, B.n, nB, g->brp.as<int64_t>(), g->bcol.as<int32_t>(), g->bval.p};
+}
+
+void augment(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B, const CsrView &Cold, Augmented *g,
+             hipStream_t s) {
+  // the multiplicative identity of each semiring (Section 3.1)
+  switch (dt) {
+    case SRTC_F64: augment_typed<double>(c, A, B, Cold, 1.0, g, s); break;
+    case SRTC_F32: augment_typed<float>(c, A, B, Cold, sr == SRTC_MIN_PLUS ? 0.f : 1.f, g, s); break;
+    case SRTC_I32: augment_typed<int32_t>(c, A, B, Cold, 0, g, s); break;
+    case SRTC_BOOL8: augment_typed<uint8_t>(c, A, B, Cold, (uint8_t)1, g, s); break;
+    case SRTC_PATH64: augment_typed<uint64_t>(c, A, B, Cold, (uint64_t)0, g, s); break;
+    default: fail(SRTC_ERR_DTYPE, "accumulate: value type");
+  }
+}
+
 }  // namespace
 
 IdVal make_id_public(int sr, int dt, const void *add_id) { return make_id(sr, dt, add_id); }
+
+// The schedule of an SpGEMM: a forced one (the argument, else the
+// environment's SRTC_FORCE_SCHEDULE), else the autotune cache's entry for
+// the problem's features, else the learned selector's pick, else schedule 0.
+int choose_schedule(srtc_ctx *ctx, int sr, int dt, const CsrView &A, const CsrView &B, int requested,
+                    hipStream_t s) {
+  Ctx *c = &ctx->c;
+  if (requested >= SRTC_NUM_SCHEDULES) fail(SRTC_ERR_ARG, "schedule id out of range");
+  if (requested >= 0) return requested;
+  if (c->force_schedule >= 0) return c->force_schedule;
+  int sched = 0;
+  if (c->mlp || !c->tune_cache.empty()) {
+    float feat[SRTC_NUM_FEATURES];
+    spgemm_features(c, sr, dt, A, B, feat, s);
+    auto hit = c->tune_cache.find(tune_key(sr, dt, feat));
+    int32_t pick = 0;
+    if (hit != c->tune_cache.end()) sched = hit->second;
+    else if (c->mlp && srtc_select(ctx, feat, &pick) == SRTC_OK) sched = pick;
+    c->tracef("schedule: %d (%s)", sched, hit != c->tune_cache.end() ? "autotune cache" : "selector");
+  }
+  return sched;
+}
 
 std::string tune_key(int sr, int dt, const float *f) {
   std::string k = std::to_string(sr) + ":" + std::to_string(dt);
@@ -463,6 +590,28 @@ srtc_status srtc_ctx_create(int device, srtc_alloc_fn alloc, srtc_free_fn free_f
   }
   const char *tr = getenv("SRTC_TRACE");
   c->c.trace = tr && *tr && *tr != '0';
+  const char *va = getenv("SRTC_VALIDATE");
+  c->c.validate_all = va && *va && *va != '0';
+  const char *fs = getenv("SRTC_FORCE_SCHEDULE");
+  if (fs && *fs) {
+    char *end = nullptr;
+    const long v = strtol(fs, &end, 10);
+    if (end == fs || *end != 0 || v < 0 || v >= SRTC_NUM_SCHEDULES) {
+      delete c;
+      return SRTC_ERR_ARG;
+    }
+    c->c.force_schedule = (int)v;
+  }
+  const char *lb = getenv("SRTC_LDS_BUDGET");
+  if (lb && *lb) {
+    char *end = nullptr;
+    const long long v = strtoll(lb, &end, 10);
+    if (end == lb || *end != 0 || v < 16384) {
+      delete c;
+      return SRTC_ERR_ARG;
+    }
+    c->c.lds_budget = (int64_t)v;
+  }
   *out = c;
   return SRTC_OK;
 }
@@ -555,32 +704,37 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
     brow += p.K;
     bcol += p.N;
     const bool a_sparse = A->format != SRTC_DENSE, b_sparse = B->format != SRTC_DENSE;
-    if (o.validate) {
-      validate_operand(c, sr, A, "A", s);
-      validate_operand(c, sr, B, "B", s);
-      if (accumulate && C->format == SRTC_CSR) validate_operand(c, sr, C, "C", s);
+    if (o.validate || c->validate_all) {
+      validate_operand(c, sr, A, "A", s, &id);
+      validate_operand(c, sr, B, "B", s, &id);
+      if (accumulate && C->format == SRTC_CSR) validate_operand(c, sr, C, "C", s, &id);
     }
     if (a_sparse && b_sparse) {
       if (C->format == SRTC_DENSE) fail(SRTC_ERR_UNSUPPORTED, "sparse x sparse gives a sparse (CSR) C");
       Folded fa, fb;
       fold_sparse(c, sr, id, A, a, crow, acol, &fa, s);
       fold_sparse(c, sr, id, B, b, brow, bcol, &fb, s);
-      int sched = o.schedule;
-      if (sched >= SRTC_NUM_SCHEDULES) fail(SRTC_ERR_ARG, "schedule id out of range");
-      if (sched < 0) {
-        // autotune cache first, then the learned selector, else the default
-        sched = 0;
-        if (c->mlp || !c->tune_cache.empty()) {
-          float feat[SRTC_NUM_FEATURES];
-          spgemm_features(c, sr, dt, fa.view, fb.view, feat, s);
-          auto hit = c->tune_cache.find(tune_key(sr, dt, feat));
-          int32_t pick = 0;
-          if (hit != c->tune_cache.end()) sched = hit->second;
-          else if (c->mlp && srtc_select(ctx, feat, &pick) == SRTC_OK) sched = pick;
-        }
-      }
+      const int sched = choose_schedule(ctx, sr, dt, fa.view, fb.view, o.schedule, s);
       CsrOut t;
       SpgemmStats st;
+      // += without batch letters or a fold-back: the old C joins the
+      // product's accumulators directly (one product, no merge pass)
+      const bool seeded = accumulate && C->format == SRTC_CSR && C->nnz > 0 && p.batch.empty() &&
+                          crow + p.N == cidx && fa.view.n + fa.view.m < 0x7fffffff;
+      if (seeded) {
+        if (C->split != (int)crow.size()) fail(SRTC_ERR_FORMAT, "C: split differs from the row indices");
+        if (C->dtype != dt) fail(SRTC_ERR_DTYPE, "C value type differs");
+        CsrView cv = csr_view(C);
+        if (cv.m != fa.view.m || cv.n != fb.view.n) fail(SRTC_ERR_DIM, "C: shape differs from the product's");
+        if (fa.view.n != fb.view.m) fail(SRTC_ERR_DIM, "inner dimensions differ");
+        Augmented g;
+        augment(c, sr, dt, fa.view, fb.view, cv, &g, s);
+        spgemm(c, sr, dt, id, g.a, g.b, sched, o.sorted, &t, &st, s);
+        int64_t dims[SRTC_MAX_ORDER];
+        for (size_t q = 0; q < cidx.size(); q++) dims[q] = p.dim.at(cidx[q]);
+        set_csr_out(C, t, (int)cidx.size(), dims, (int)crow.size(), dt);
+        return;
+      }
       spgemm(c, sr, dt, id, fa.view, fb.view, sched, o.sorted, &t, &st, s);
       if (!p.batch.empty() && t.nnz > 0) {
         col_mod_kernel<<<4096, 256, 0, s>>>(t.col.as<int32_t>(), t.nnz, extent(p, p.N));
@@ -698,6 +852,81 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
   });
 }
 
+srtc_status srtc_contract_panels(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const char *ia,
+                                 const srtc_tensor *A, const char *ib, const srtc_tensor *B, const char *ic,
+                                 const srtc_opts *opts, int64_t panel_products, srtc_panel_fn consume, void *user,
+                                 void *stream) {
+  return guard(ctx, [&] {
+    check_tensor(A, "A");
+    check_tensor(B, "B");
+    if (!consume) fail(SRTC_ERR_ARG, "panels: null consumer");
+    if (A->format == SRTC_DENSE || B->format == SRTC_DENSE)
+      fail(SRTC_ERR_UNSUPPORTED, "panels: A and B must be sparse (COO or CSR)");
+    const std::string a = letters(ia, A, "A"), b = letters(ib, B, "B");
+    if (!ic) fail(SRTC_ERR_INDEX, "C: null index string");
+    // C's extents come from the letters it shares with A and B
+    srtc_tensor Ct{};
+    Ct.order = (int32_t)strlen(ic);
+    if (Ct.order > SRTC_MAX_ORDER) fail(SRTC_ERR_INDEX, "C: too many indices");
+    for (int q = 0; q < Ct.order; q++) {
+      const size_t pa = a.find(ic[q]), pb = b.find(ic[q]);
+      Ct.dims[q] = pa != std::string::npos ? A->dims[pa] : pb != std::string::npos ? B->dims[pb] : 1;
+    }
+    const std::string cidx = letters(ic, &Ct, "C");
+    if (A->dtype != B->dtype) fail(SRTC_ERR_DTYPE, "A and B value types differ");
+    const int dt = A->dtype;
+    const IdVal id = make_id(sr, dt, add_id);
+    const Plan p = plan_contraction(a, A, b, B, cidx, &Ct);
+    if (!p.batch.empty()) fail(SRTC_ERR_UNSUPPORTED, "panels: no index may appear in A, B and C");
+    const std::string crow = rows_of_c(cidx, p);
+    if (crow + p.N != cidx) fail(SRTC_ERR_UNSUPPORTED, "panels: C's row indices must precede its column indices");
+    srtc_opts o{-1, 1, 0, 0};
+    if (opts) o = *opts;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    Ctx *c = &ctx->c;
+    if (o.validate || c->validate_all) {
+      validate_operand(c, sr, A, "A", s, &id);
+      validate_operand(c, sr, B, "B", s, &id);
+    }
+    Folded fa, fb;
+    fold_sparse(c, sr, id, A, a, crow, p.K, &fa, s);
+    fold_sparse(c, sr, id, B, b, p.K, p.N, &fb, s);
+    const CsrView &av = fa.view;
+    // one schedule for the whole product, from the features of all rows
+    const int sched = choose_schedule(ctx, sr, dt, av, fb.view, o.schedule, s);
+    const int64_t m = av.m;
+    if (panel_products <= 0) panel_products = (int64_t)1 << 31;
+    // panel cuts at running product counts
+    std::vector<int64_t> pre((size_t)m + 1, 0), hrp((size_t)m + 1, 0);
+    if (m > 0) {
+      Buf w(c, sizeof(int64_t) * (size_t)m), wp(c, sizeof(int64_t) * (size_t)(m + 1));
+      row_products(av, fb.view, w.as<int64_t>(), s);
+      excl_scan_i64(c, w.as<int64_t>(), wp.as<int64_t>(), m, s);
+      read_to_host(c, pre.data(), wp.p, sizeof(int64_t) * (size_t)(m + 1), s);
+      read_to_host(c, hrp.data(), av.rowptr, sizeof(int64_t) * (size_t)(m + 1), s);
+    }
+    int64_t dims[2] = {m, fb.view.n};
+    c->tracef("srtc_contract_panels: %lld rows, %lld products, schedule %d, at most %lld products per panel",
+              (long long)m, (long long)pre[m], sched, (long long)panel_products);
+    int64_t r0 = 0;
+    while (r0 < m) {
+      // the longest run of rows from r0 within the budget (at least one row)
+      int64_t r1 = (int64_t)(std::upper_bound(pre.begin() + r0 + 1, pre.end(), pre[r0] + panel_products) - pre.begin()) - 1;
+      if (r1 <= r0) r1 = r0 + 1;
+      CsrView pv{r1 - r0, av.n, hrp[r1] - hrp[r0], av.rowptr + r0, av.col, av.val};
+      CsrOut t;
+      spgemm(c, sr, dt, id, pv, fb.view, sched, o.sorted, &t, nullptr, s);
+      srtc_tensor Cp{};
+      dims[0] = r1 - r0;
+      set_csr_out(&Cp, t, 2, dims, 1, dt);
+      const int32_t rc = consume(user, r0, r1 - r0, &Cp, stream);
+      if (rc != 0) fail(SRTC_ERR_ARG, "panels: stopped by the consumer");
+      r0 = r1;
+    }
+  });
+}
+
 srtc_status srtc_contract_masked(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const char *ia,
                                  const srtc_tensor *A, const char *ib, const srtc_tensor *B, const char *ic,
                                  const srtc_tensor *M, srtc_tensor *C, const srtc_opts *opts, void *stream) {
@@ -725,9 +954,9 @@ srtc_status srtc_contract_masked(srtc_ctx *ctx, srtc_semiring sr, const void *ad
     hipStream_t s = (hipStream_t)stream;
     ctx->c.stream = s;
     Ctx *c = &ctx->c;
-    if (o.validate) {
-      validate_operand(c, sr, A, "A", s);
-      validate_operand(c, sr, B, "B", s);
+    if (o.validate || c->validate_all) {
+      validate_operand(c, sr, A, "A", s, &id);
+      validate_operand(c, sr, B, "B", s, &id);
       validate_operand(c, SRTC_OR_AND, M, "M", s);
     }
     const std::string crow = rows_of_c(cidx, p);

@@ -229,6 +229,15 @@ template <class T> struct MaxTimes {
   __device__ static val_t out(acc_t v) { return v; }
 };
 
+// The stored form of an accumulator in a dense output: a result that counts
+// as absent (for (min,+) int32 a sum at or above the identity, Section 3.1's
+// reading that such sums are no path) is written as the identity itself, so
+// a dense result never holds a value beyond it.
+template <class SR>
+__device__ __forceinline__ typename SR::val_t out_clamped(typename SR::acc_t v, typename SR::acc_t id) {
+  return SR::acc_absent(v, id) ? SR::out(id) : SR::out(v);
+}
+
 // Identity holder passed to kernels: the caller's add_id converted once.
 struct IdVal {
   double f;

@@ -286,7 +286,7 @@ __global__ void permute_combine_kernel(const typename SR::val_t *__restrict__ sr
     const auto x = src[si], y = dst[o];
     if (!SR::absent(x, id)) acc = SR::add(acc, (A)x);
     if (!SR::absent(y, id)) acc = SR::add(acc, (A)y);
-    dst[o] = SR::out(acc);
+    dst[o] = out_clamped<SR>(acc, id);
   }
 }
 
@@ -338,7 +338,7 @@ __global__ void hadamard_kernel(const typename SR::val_t *__restrict__ A, const 
       const auto y = C[e];
       if (!SR::absent(y, id)) acc = SR::add(acc, (Acc)y);
     }
-    C[e] = SR::out(acc);
+    C[e] = out_clamped<SR>(acc, id);
   }
 }
 

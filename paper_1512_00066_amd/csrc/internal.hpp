@@ -35,6 +35,13 @@ struct Ctx {
   std::vector<std::vector<void *>> free_blocks = std::vector<std::vector<void *>>(64);
   hipStream_t cache_stream = nullptr;
   bool trace = false;
+  // environment switches read at context creation: SRTC_VALIDATE (check
+  // every sparse operand's structure), SRTC_FORCE_SCHEDULE (the SpGEMM
+  // schedule of every product whose caller leaves the choice open) and
+  // SRTC_LDS_BUDGET (bytes of LDS a SpGEMM kernel may use per block)
+  bool validate_all = false;
+  int force_schedule = -1;
+  int64_t lds_budget = 160 * 1024;
   void release_cache();
   void tracef(const char *fmt, ...);
   // per-kernel profile: HIP events around each launch on its stream, with
@@ -139,9 +146,20 @@ struct SpgemmStats {
 };
 
 // C = A (x) B, output CSR with ascending columns (sorted=1) allocated from
-// the context.  Synchronizes once.
+// the context.  Synchronizes a few times (bin sizes, output size, flags).
 void spgemm(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B, int sched,
             int sorted, CsrOut *out, SpgemmStats *st, hipStream_t s);
+// Rows of A multiplied under their own schedules: group g covers the rows
+// listed in row_map (device, nsel ids; every row of A belongs to at most one
+// group, rows in none get no entries).  One output, as spgemm().
+struct RowGroup {
+  const int32_t *row_map;
+  int64_t nsel;
+  int sched;
+};
+void spgemm_grouped(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B,
+                    const std::vector<RowGroup> &groups, int sorted, CsrOut *out, SpgemmStats *st,
+                    hipStream_t s);
 // C = M (.) (A (x) B) over M's pattern (sorted rows; identity results dropped).
 void spgemm_masked(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B, const CsrView &M,
                    CsrOut *out, hipStream_t s);
@@ -226,6 +244,11 @@ void jacobi_step_call(const JacobiPlan &pl, const void *b, const void *x_in, voi
 void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B, float *out,
                      hipStream_t s);
 
+// The schedule of an SpGEMM A (x) B: `requested` if >= 0, else the
+// environment's forced one, else the autotune cache, the learned selector
+// or schedule 0 (features are computed only when a cache or network exists).
+int choose_schedule(srtc_ctx *ctx, int sr, int dt, const CsrView &A, const CsrView &B, int requested, hipStream_t s);
+
 // The caller's additive identity checked against the semiring, or the
 // default identity (Section 3.1).
 IdVal make_id_public(int sr, int dt, const void *add_id);
@@ -233,7 +256,8 @@ IdVal make_id_public(int sr, int dt, const void *add_id);
 std::string tune_key(int sr, int dt, const float *features);
 // Structure checks of a sparse operand (SRTC_ERR_FORMAT on failure); one
 // host sync.
-void validate_operand(Ctx *c, int sr, const srtc_tensor *t, const char *name, hipStream_t s);
+void validate_operand(Ctx *c, int sr, const srtc_tensor *t, const char *name, hipStream_t s,
+                      const IdVal *id = nullptr);
 
 }  // namespace srtc
 

@@ -25,9 +25,18 @@ struct Mlp {
   std::vector<float> params, m1, m2;  // host copies (weights, Adam moments)
   float mean[IN], stdv[IN];
   int64_t step = 0;
+  // device copy for selection: params, then mean and stdv (uploaded once per
+  // training or load; the network is small, so it lives outside the
+  // allocator callback and is freed with the network)
+  float *dev = nullptr;
+  int dev_id = -1;
 };
 
-void mlp_destroy(Mlp *m) { delete m; }
+void mlp_destroy(Mlp *m) {
+  if (!m) return;
+  if (m->dev) (void)hipFree(m->dev);
+  delete m;
+}
 
 namespace {
 
@@ -126,6 +135,8 @@ __global__ void gather_rows(const float *__restrict__ src, const int32_t *__rest
   dst[t] = src[(int64_t)idx[r] * width + q];
 }
 
+// Adam (Kingma and Ba): first and second moment estimates, bias corrections
+// c1 = 1 - b1^t and c2 = 1 - b2^t for step t, then the scaled step.
 __global__ void adam_update(float *__restrict__ P, const float *__restrict__ G, float *__restrict__ M1,
                             float *__restrict__ M2, float lr, float b1, float b2, float eps, float c1, float c2) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -136,6 +147,57 @@ __global__ void adam_update(float *__restrict__ P, const float *__restrict__ G, 
   M1[p] = m;
   M2[p] = v;
   P[p] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// Selection: one 64-thread block standardizes the features with the
+// network's statistics, evaluates the network and writes the arg-min of the
+// predicted (centred log2) times.
+__global__ void __launch_bounds__(64) mlp_select_kernel(const float *__restrict__ P, const float *__restrict__ mean,
+                                                        const float *__restrict__ stdv, const float *__restrict__ feat,
+                                                        int32_t *__restrict__ pick) {
+  __shared__ float x[IN], h1[H], h2[H], y[K];
+  const int t = threadIdx.x;
+  if (t < IN) x[t] = (feat[t] - mean[t]) / stdv[t];
+  __syncthreads();
+  float z1 = P[OFF_B1 + t];
+  for (int i = 0; i < IN; i++) z1 += P[OFF_W1 + t * IN + i] * x[i];
+  h1[t] = z1 > 0.f ? z1 : 0.f;
+  __syncthreads();
+  float z2 = P[OFF_B2 + t];
+  for (int i = 0; i < H; i++) z2 += P[OFF_W2 + t * H + i] * h1[i];
+  h2[t] = z2 > 0.f ? z2 : 0.f;
+  __syncthreads();
+  if (t < K) {
+    float v = P[OFF_B3 + t];
+    for (int i = 0; i < H; i++) v += P[OFF_W3 + t * H + i] * h2[i];
+    y[t] = v;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int best = 0;
+    for (int k = 1; k < K; k++)
+      if (y[k] < y[best]) best = k;
+    *pick = best;
+  }
+}
+
+// Upload the network (parameters and feature statistics) for selection.
+void mlp_to_device(Ctx *c, Mlp *m) {
+  const size_t bytes = 4ull * (NPARAM + 2 * IN);
+  if (!m->dev || m->dev_id != c->device) {
+    if (m->dev) (void)hipFree(m->dev);
+    m->dev = nullptr;
+    if (hipMalloc(&m->dev, bytes) != hipSuccess) {
+      m->dev = nullptr;
+      fail(SRTC_ERR_OOM, "selector network: device allocation failed");
+    }
+    m->dev_id = c->device;
+  }
+  std::vector<float> h(NPARAM + 2 * IN);
+  std::copy(m->params.begin(), m->params.end(), h.begin());
+  std::copy(m->mean, m->mean + IN, h.begin() + NPARAM);
+  std::copy(m->stdv, m->stdv + IN, h.begin() + NPARAM + IN);
+  SRTC_HIP(hipMemcpy(m->dev, h.data(), bytes, hipMemcpyHostToDevice));
 }
 
 struct Scratch {
@@ -292,6 +354,7 @@ srtc_status srtc_selector_train(srtc_ctx *ctx, const float *X, const float *T, i
     read_to_host(c, m->params.data(), P.p, 4ull * NPARAM, s);
     read_to_host(c, m->m1.data(), M1.p, 4ull * NPARAM, s);
     read_to_host(c, m->m2.data(), M2.p, 4ull * NPARAM, s);
+    mlp_to_device(c, m);
     if (final_loss) *final_loss = last;
   });
 }
@@ -300,20 +363,35 @@ srtc_status srtc_select(srtc_ctx *ctx, const float *features, int32_t *schedule_
   return guard(ctx, [&] {
     if (!features || !schedule_out) fail(SRTC_ERR_ARG, "select: null");
     Ctx *c = &ctx->c;
-    if (!c->mlp) fail(SRTC_ERR_UNSUPPORTED, "no selector network loaded");
-    float xn[IN];
-    normalize(c->mlp, features, xn, 1);
+    Mlp *m = c->mlp;
+    if (!m) fail(SRTC_ERR_UNSUPPORTED, "no selector network loaded");
+    if (!m->dev || m->dev_id != c->device) mlp_to_device(c, m);
     hipStream_t s = c->stream;  // the caller's stream when nested in a contraction
-    Buf P(c, 4ull * NPARAM), Xd(c, 4ull * IN), Yd(c, 4ull * K);
-    SRTC_HIP(hipMemcpyAsync(P.p, c->mlp->params.data(), 4ull * NPARAM, hipMemcpyHostToDevice, s));
-    SRTC_HIP(hipMemcpyAsync(Xd.p, xn, 4ull * IN, hipMemcpyHostToDevice, s));
-    forward_dev(P.as<float>(), Xd.as<float>(), 1, Yd.as<float>(), s);
-    float y[K];
-    read_to_host(c, y, Yd.p, sizeof(y), s);
-    int best = 0;
-    for (int k = 1; k < K; k++)
-      if (y[k] < y[best]) best = k;
+    // features in, pick out: one 32-float upload, one kernel, one int read
+    Buf io(c, 4ull * IN + 64);
+    float *pin = (float *)c->host_scratch(4ull * IN);
+    memcpy(pin, features, 4ull * IN);
+    SRTC_HIP(hipMemcpyAsync(io.p, pin, 4ull * IN, hipMemcpyHostToDevice, s));
+    int32_t *pick = reinterpret_cast<int32_t *>(io.as<char>() + 4ull * IN);
+    mlp_select_kernel<<<1, 64, 0, s>>>(m->dev, m->dev + NPARAM, m->dev + NPARAM + IN, io.as<float>(), pick);
+    SRTC_LAUNCH_CHECK("mlp_select_kernel");
+    int32_t best = 0;
+    read_to_host(c, &best, pick, sizeof(best), s);
     *schedule_out = best;
+  });
+}
+
+srtc_status srtc_mlp_adam_step(srtc_ctx *ctx, float *params, const float *grads, float *m1, float *m2, int64_t step,
+                               float lr, float beta1, float beta2, float eps, void *stream) {
+  return guard(ctx, [&] {
+    if (!params || !grads || !m1 || !m2 || step < 1) fail(SRTC_ERR_ARG, "mlp_adam_step: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    // the same bias corrections as the training loop
+    const float c1 = 1.f - (float)std::pow((double)beta1, (double)step);
+    const float c2 = 1.f - (float)std::pow((double)beta2, (double)step);
+    adam_update<<<(NPARAM + 255) / 256, 256, 0, s>>>(params, grads, m1, m2, lr, beta1, beta2, eps, c1, c2);
+    SRTC_LAUNCH_CHECK("adam_update");
   });
 }
 
@@ -361,6 +439,7 @@ srtc_status srtc_selector_load(srtc_ctx *ctx, const char *path) {
     }
     mlp_destroy(c->mlp);
     c->mlp = m;
+    mlp_to_device(c, m);
   });
 }
 

@@ -1231,15 +1231,24 @@ int32_t bitmap_words(int64_t ncols, int bs, int64_t budget_bytes) {
   return (int32_t)wv;
 }
 
-// Symbolic pass over `nsel` rows whose product counts are wsel (row ids in
-// row_map, or 0..nsel-1): nnz_row[row] for each.  Returns the product total.
-// Synchronizes once (bin sizes).
-int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, const CsrView &Bm, const int64_t *wsel,
+// Symbolic pass over `nsel` rows (row ids in row_map, or 0..nsel-1) whose
+// product counts are w (indexed by row id): nnz_row[row] for each.  Returns
+// the product total.  Synchronizes once (bin sizes).
+int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, const CsrView &Bm, const int64_t *w,
                      const int32_t *row_map, int64_t nsel, int64_t *info1, int32_t *list, int64_t *nnz_row,
                      int64_t *err) {
   hipStream_t s = L.s;
   Ctx *c = L.c;
   const int64_t n = Bm.n;
+  // product counts in selection order
+  Buf wbuf;
+  const int64_t *wsel = w;
+  if (row_map) {
+    wbuf = Buf(c, sizeof(int64_t) * (size_t)std::max<int64_t>(nsel, 1));
+    gather_i64<<<gridn(nsel), 256, 0, s>>>(w, row_map, nsel, wbuf.as<int64_t>());
+    SRTC_LAUNCH_CHECK("gather_i64");
+    wsel = wbuf.as<int64_t>();
+  }
   Thresholds th1{};
   {
     // bins: 1: <=32 (64-slot hash), 2: <=256 (512), 3: <=2048 (4096),
@@ -1259,7 +1268,7 @@ int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, cons
   SRTC_LAUNCH_CHECK("bin_scatter");
   int64_t hinfo[INFO];
   read_to_host(c, hinfo, info1, sizeof(hinfo), s);
-  if (!row_map) heavy_first(c, list + hinfo[NBIN + 5], hinfo[5], wsel, s);
+  heavy_first(c, list + hinfo[NBIN + 5], hinfo[5], w, s);
   int64_t *ctr1 = info1 + 3 * NBIN;
   // algorithmic bytes of a symbolic bin: its A rows (pointers + columns),
   // B's columns once, one count per row
@@ -1286,7 +1295,8 @@ int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, cons
     // at most 64 KB of bitmap (2^19 columns) per pass: two blocks per CU
     // instead of one; with the window table the extra passes only re-lay
     // the A row (R-MAT 21 panel squared, fp32: 213 -> 177 ms per product)
-    const int32_t ww = bitmap_words(n, BS, std::min<int64_t>(LDS_BYTES - stat - 1024, 64 * 1024));
+    const int32_t ww = bitmap_words(n, BS, std::min<int64_t>(std::min<int64_t>(LDS_BYTES, c->lds_budget) - stat - 1024,
+                                                             64 * 1024));
     const int64_t wcols = (int64_t)ww * 32;
     const int nwin = (int)((n + wcols - 1) / wcols);
     Buf woff;
@@ -1342,79 +1352,101 @@ template <class SR> constexpr int64_t dense_width(int code) {
   return (code == 1 ? 16384 : code == 2 ? 4096 : 8192) * (8 / (int64_t)sizeof(typename SR::acc_t));
 }
 
+// LDS a block of each kernel uses (the same expressions as the launchers).
+template <int BS> constexpr int sym_hash_lds(int tbl) { return tbl * 4 + (int)sizeof(Chunk<BS, uint8_t>) + 64; }
+template <class SR, int BS> constexpr int num_hash_lds(int tbl) {
+  return tbl * 4 + (SR::HAS_VALS ? tbl : 1) * (int)sizeof(typename SR::acc_t) +
+         (int)sizeof(Chunk<BS, typename SR::val_t>) + 64;
+}
+template <class SR, int BS, int W> constexpr int num_dense_lds() {
+  return (SR::HAS_VALS ? W : 1) * (int)sizeof(typename SR::acc_t) + W / 8 +
+         (int)sizeof(Chunk<BS, typename SR::val_t>) + (RankWin<SR, BS, W>::OK ? NWPW * 8 : 8) + 64;
+}
+
+// A schedule as run under the context's LDS budget (SRTC_LDS_BUDGET): a
+// hash bin whose kernel would need more LDS per block is merged into the
+// next larger one, up to the dense windows (a row's result does not depend
+// on the kernel that forms it); dense windows too wide for the budget give
+// way to the narrowest (more passes per row); symbolic hash tables too large
+// send their rows to the bitmap pass, whose bitmap also stays within it.
+template <class SR> Schedule budgeted(const Ctx *c, int id) {
+  Schedule S = schedule(id);
+  const int64_t B = c->lds_budget;
+  if (B >= LDS_BYTES) return S;
+  if (sym_hash_lds<512>(16384) > B) S.sym_hash_max = std::min<int64_t>(S.sym_hash_max, 2048);
+  if (sym_hash_lds<256>(4096) > B) S.sym_hash_max = std::min<int64_t>(S.sym_hash_max, 256);
+  if (sym_hash_lds<64>(512) > B) S.sym_hash_max = std::min<int64_t>(S.sym_hash_max, 32);
+  if (sym_hash_lds<64>(64) > B) S.sym_hash_max = 0;
+  // numeric bins, largest first: a dropped bin's rows fall through to the
+  // dense windows (thresholds are applied as running maxima)
+  if (num_hash_lds<SR, 512>(8192) > B) S.t_big = S.t_mid;
+  if (num_hash_lds<SR, 256>(4096) > B) S.t_mid = S.t_big = S.t_small;
+  if (num_hash_lds<SR, 128>(512) > B) S.t_small = S.t_mid = S.t_big = S.t_tiny;
+  if (num_hash_lds<SR, 64>(64) > B) S.t_tiny = S.t_small = S.t_mid = S.t_big = 0;
+  constexpr int W0 = (int)dense_width<SR>(0), W1 = (int)dense_width<SR>(1), W2 = (int)dense_width<SR>(2);
+  int need = 0;
+  if (S.dense_wide == 1) need = S.dense_bs == 512 ? num_dense_lds<SR, 512, W1>() : num_dense_lds<SR, 256, W1>();
+  else if (S.dense_wide == 2) need = num_dense_lds<SR, 512, W2>();
+  else need = S.dense_bs == 512 ? num_dense_lds<SR, 512, W0>() : num_dense_lds<SR, 256, W0>();
+  if (need > B) {
+    S.dense_wide = 2;
+    S.dense_bs = 512;
+    if (num_dense_lds<SR, 512, W2>() > B)
+      fail(SRTC_ERR_UNSUPPORTED, "SRTC_LDS_BUDGET is below the narrowest dense window (" +
+                                     std::to_string(num_dense_lds<SR, 512, W2>()) + " bytes)");
+  }
+  return S;
+}
+
+// Numeric binning of one group of rows (row ids in g.row_map, or every row
+// when it is null) under schedule g.sched: rows go to bins by their exact
+// output counts (info2: INFO entries, zeroed by the caller; list: the
+// group's rows by bin).  Nothing is read back here.
 template <class SR>
-void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int sched, int sorted, CsrOut *out,
-                  SpgemmStats *st, hipStream_t s) {
-  using V = typename SR::val_t;
-  using A = typename SR::acc_t;
-  const A id = id_as<SR>(idv);
-  const Schedule &S = schedule(sched);
-  const int64_t m = Am.m, n = Bm.n;
-  Launch L{c, s};
-  out->m = m;
-  out->n = n;
-  out->rowptr = Buf(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
-  const size_t es = sizeof(V);
-  if (m == 0 || Am.nnz == 0 || Bm.nnz == 0) {
-    fill_i64(out->rowptr.as<int64_t>(), m + 1, 0, s);
-    out->nnz = 0;
-    out->col = Buf(c, 4, out->kind);
-    out->val = Buf(c, es, out->kind);
-    if (st) *st = SpgemmStats{};
-    return;
+void numeric_bin(Ctx *c, const CsrView &Am, const int64_t *nnz_row, const RowGroup &g, int64_t *info2, int32_t *list,
+                 Buf *vbuf, hipStream_t s) {
+  const Schedule S = budgeted<SR>(c, g.sched);
+  const int64_t nsel = g.row_map ? g.nsel : Am.m;
+  if (nsel == 0) return;
+  // output counts in selection order
+  const int64_t *vsel = nnz_row;
+  if (g.row_map) {
+    *vbuf = Buf(c, sizeof(int64_t) * (size_t)nsel);
+    gather_i64<<<gridn(nsel), 256, 0, s>>>(nnz_row, g.row_map, nsel, vbuf->as<int64_t>());
+    SRTC_LAUNCH_CHECK("gather_i64");
+    vsel = vbuf->as<int64_t>();
   }
-  // 1-3. products per row, symbolic bins, symbolic pass
-  Buf w(c, sizeof(int64_t) * (size_t)m);
-  {
-    ProfScope ps(c, "spgemm.row_products", 16.0 * (m + 1) + 4.0 * Am.nnz + 8.0 * (Bm.m + 1), s);
-    row_products(Am, Bm, w.as<int64_t>(), s);
-  }
-  Buf info(c, sizeof(int64_t) * INFO * 2);
-  int64_t *info1 = info.as<int64_t>(), *info2 = info1 + INFO;
-  fill_i64(info1, INFO * 2, 0, s);
-  Buf list(c, sizeof(int32_t) * (size_t)m);
-  Buf nnz_row(c, sizeof(int64_t) * (size_t)m);
-  fill_i64(nnz_row.as<int64_t>(), m, 0, s);
-  c->tracef("spgemm: %lld x %lld (nnz %lld) times %lld x %lld (nnz %lld), schedule %d", (long long)m,
-            (long long)Am.n, (long long)Am.nnz, (long long)Bm.m, (long long)n, (long long)Bm.nnz, sched);
-  const int64_t products = run_symbolic(L, S, Am, Bm, w.as<int64_t>(), nullptr, m, info1, list.as<int32_t>(),
-                                        nnz_row.as<int64_t>(), info2 + INFO - 1);
-  c->tracef("spgemm: symbolic launched, %lld products", (long long)products);
-  if (st) st->products = products;
-  // 4. rowptr, numeric bins (by exact nnz)
-  excl_scan_i64(c, nnz_row.as<int64_t>(), out->rowptr.as<int64_t>(), m, s);
   Thresholds th2{};
   th2.t[0] = S.t_tiny;
   th2.t[1] = std::max(S.t_small, th2.t[0]);
   th2.t[2] = std::max(S.t_mid, th2.t[1]);
   th2.t[3] = std::max(S.t_big, th2.t[2]);
-  bin_count<<<gridn(m, 256, 2048), 256, 0, s>>>(nnz_row.as<int64_t>(), m, th2, info2, Am.rowptr, nullptr);
+  bin_count<<<gridn(nsel, 256, 2048), 256, 0, s>>>(vsel, nsel, th2, info2, Am.rowptr, g.row_map);
   SRTC_LAUNCH_CHECK("bin_count");
   bin_offsets<<<1, 64, 0, s>>>(info2);
-  bin_scatter<<<gridn(m, 256, 4096), 256, 0, s>>>(nnz_row.as<int64_t>(), m, th2, info2, list.as<int32_t>(), nullptr);
+  bin_scatter<<<gridn(nsel, 256, 4096), 256, 0, s>>>(vsel, nsel, th2, info2, list, g.row_map);
   SRTC_LAUNCH_CHECK("bin_scatter");
-  int64_t hinfo2[INFO];
-  read_to_host(c, hinfo2, info2, sizeof(hinfo2), s);
-  if (hinfo2[INFO - 1]) fail(SRTC_ERR_DEVICE, "spgemm: symbolic hash table overflow (internal invariant)");
-  heavy_first(c, list.as<int32_t>() + hinfo2[NBIN + 5], hinfo2[5], w.as<int64_t>(), s);
-  const int64_t total = hinfo2[4 * NBIN];
-  c->tracef("spgemm: nnz(C) = %lld; numeric bins %lld %lld %lld %lld %lld", (long long)total, (long long)hinfo2[1],
-            (long long)hinfo2[2], (long long)hinfo2[3], (long long)hinfo2[4], (long long)hinfo2[5]);
-  if (st) { st->nnz = total; st->dense_rows = hinfo2[5]; }
-  // 5. numeric
-  Buf col(c, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), out->kind);
-  Buf val(c, es * (size_t)std::max<int64_t>(total, 1), out->kind);
-  Buf kept(c, sizeof(int64_t) * (size_t)m);
-  fill_i64(kept.as<int64_t>(), m, 0, s);  // rows in no bin (no outputs) keep 0
-  Buf flag(c, 64);
-  fill_i32(flag.as<int32_t>(), 2, 0, s);
+}
+
+// Numeric kernels of one binned group (hinfo2: the host copy of its bin
+// table), writing at rpC.  kp[row] = entries written; fl[0] is raised when a
+// row came out short (identity results dropped), fl[1] on a broken hash
+// invariant.
+template <class SR>
+void numeric_launch(Ctx *c, typename SR::acc_t id, const CsrView &Am, const CsrView &Bm, const int64_t *w,
+                    const RowGroup &g, const int64_t *hinfo2, int64_t *info2, int32_t *lst, int sorted,
+                    const int64_t *rpC, int32_t *cC, typename SR::val_t *vC, int64_t *kp, int32_t *fl,
+                    SpgemmStats *st, hipStream_t s) {
+  using V = typename SR::val_t;
+  const Schedule S = budgeted<SR>(c, g.sched);
+  const int64_t n = Bm.n;
+  Launch L{c, s};
+  heavy_first(c, lst + hinfo2[NBIN + 5], hinfo2[5], w, s);
+  c->tracef("spgemm: schedule %d, nnz %lld; numeric bins %lld %lld %lld %lld %lld", g.sched,
+            (long long)hinfo2[4 * NBIN], (long long)hinfo2[1], (long long)hinfo2[2], (long long)hinfo2[3],
+            (long long)hinfo2[4], (long long)hinfo2[5]);
+  if (st) st->dense_rows += hinfo2[5];
   int64_t *ctr2 = info2 + 3 * NBIN;
-  const int64_t *rpC = out->rowptr.as<int64_t>();
-  int32_t *cC = col.as<int32_t>();
-  V *vC = val.as<V>();
-  int32_t *lst = list.as<int32_t>();
-  int64_t *kp = kept.as<int64_t>();
-  int32_t *fl = flag.as<int32_t>();
   using NL = NumLaunch<SR>;
   // algorithmic bytes of a numeric bin: its C entries written, its A rows
   // read, B read once
@@ -1428,7 +1460,7 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
                                        "spgemm.numeric.dense"};
   // profile names carry the value type, so each names one kernel instance
   const char *vt = std::is_same<V, double>::value ? ".f64" : std::is_same<V, float>::value ? ".f32"
-                   : std::is_same<V, int32_t>::value ? ".i32" : ".u8";
+                   : std::is_same<V, int32_t>::value ? ".i32" : std::is_same<V, uint64_t>::value ? ".path" : ".u8";
   auto pname = [&](int b) { return std::string(kNumName[b]) + vt; };
   for (int b = 1; b < NBIN - 1; b++) {
     if (hinfo2[b] == 0) continue;
@@ -1459,7 +1491,9 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
       SRTC_LAUNCH_CHECK("build_woff");
     }
     const int32_t *wo = woff.as<int32_t>();
-    ProfScope ps(c, pname(5).c_str(), num_bytes(5) + (nwin > 1 ? 8.0 * hinfo2[SUMA + 5] * nwin : 0.0), s);
+    // the window-table lookups (8 B per A entry and window) are overhead of
+    // the method, not bytes the product must move: they stay out of the count
+    ProfScope ps(c, pname(5).c_str(), num_bytes(5), s);
     constexpr int W0 = (int)dense_width<SR>(0), W1 = (int)dense_width<SR>(1), W2 = (int)dense_width<SR>(2);
     if (S.dense_wide == 1) {
       if (S.dense_bs == 512) NL::template dense<512, W1>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
@@ -1471,10 +1505,105 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
       else NL::template dense<256, W0>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
     }
   }
+}
+
+__global__ void copy_i64(const int64_t *src, int64_t *dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+// C = A (x) B with the rows split into groups, each multiplied under its own
+// schedule (one group of every row for a plain product).  The symbolic
+// counts do not depend on the schedule, so one row pointer array and one
+// output allocation serve every group.  Host reads: each group's symbolic
+// bin sizes, then the output size with every group's numeric bin sizes,
+// then the end-of-product flags.
+template <class SR>
+void spgemm_groups(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, const std::vector<RowGroup> &groups,
+                   int sorted, CsrOut *out, SpgemmStats *st, hipStream_t s) {
+  using V = typename SR::val_t;
+  using A = typename SR::acc_t;
+  const A id = id_as<SR>(idv);
+  const int64_t m = Am.m;
+  Launch L{c, s};
+  out->m = m;
+  out->n = Bm.n;
+  out->rowptr = Buf(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
+  const size_t es = sizeof(V);
+  if (st) *st = SpgemmStats{};
+  if (m == 0 || Am.nnz == 0 || Bm.nnz == 0) {
+    fill_i64(out->rowptr.as<int64_t>(), m + 1, 0, s);
+    out->nnz = 0;
+    out->col = Buf(c, 4, out->kind);
+    out->val = Buf(c, es, out->kind);
+    return;
+  }
+  const int G = (int)groups.size();
+  // flags: [0] a row came out short, [1] numeric hash invariant broken,
+  // int64 at byte 8: symbolic hash invariant broken
+  Buf flag(c, 64);
+  fill_i32(flag.as<int32_t>(), 4, 0, s);
+  int32_t *fl = flag.as<int32_t>();
+  int64_t *sym_err = reinterpret_cast<int64_t *>(flag.as<char>() + 8);
+  // 1-3. products per row, symbolic bins, symbolic pass (per group)
+  Buf w(c, sizeof(int64_t) * (size_t)m);
+  {
+    ProfScope ps(c, "spgemm.row_products", 16.0 * (m + 1) + 4.0 * Am.nnz + 8.0 * (Bm.m + 1), s);
+    row_products(Am, Bm, w.as<int64_t>(), s);
+  }
+  Buf nnz_row(c, sizeof(int64_t) * (size_t)m);
+  fill_i64(nnz_row.as<int64_t>(), m, 0, s);
+  c->tracef("spgemm: %lld x %lld (nnz %lld) times %lld x %lld (nnz %lld), %d group(s), schedule %d", (long long)m,
+            (long long)Am.n, (long long)Am.nnz, (long long)Bm.m, (long long)Bm.n, (long long)Bm.nnz, G,
+            G ? groups[0].sched : -1);
+  // per group: a bin table (symbolic, then reused for the numeric pass) and
+  // a row list; slot 0 of `tables` receives the output size
+  Buf tables(c, sizeof(int64_t) * (size_t)(1 + G * INFO));
+  int64_t *tab = tables.as<int64_t>();
+  fill_i64(tab, 1 + (int64_t)G * INFO, 0, s);
+  std::vector<Buf> lists(G);
+  int64_t products = 0;
+  for (int q = 0; q < G; q++) {
+    const RowGroup &g = groups[q];
+    const int64_t nsel = g.row_map ? g.nsel : m;
+    lists[q] = Buf(c, sizeof(int32_t) * (size_t)std::max<int64_t>(nsel, 1));
+    if (nsel == 0) continue;
+    int64_t *info1 = tab + 1 + (int64_t)q * INFO;
+    products += run_symbolic(L, budgeted<SR>(c, g.sched), Am, Bm, w.as<int64_t>(), g.row_map, nsel, info1,
+                             lists[q].as<int32_t>(), nnz_row.as<int64_t>(), sym_err);
+    fill_i64(info1, INFO, 0, s);  // the table serves the numeric binning next
+  }
+  c->tracef("spgemm: symbolic launched, %lld products", (long long)products);
+  if (st) st->products = products;
+  // 4. rowptr of C, numeric bins; one host read sizes C and every bin
+  excl_scan_i64(c, nnz_row.as<int64_t>(), out->rowptr.as<int64_t>(), m, s);
+  std::vector<Buf> vbufs(G);
+  for (int q = 0; q < G; q++)
+    numeric_bin<SR>(c, Am, nnz_row.as<int64_t>(), groups[q], tab + 1 + (int64_t)q * INFO, lists[q].as<int32_t>(),
+                    &vbufs[q], s);
+  copy_i64<<<1, 64, 0, s>>>(out->rowptr.as<int64_t>() + m, tab);
+  std::vector<int64_t> htab(1 + (size_t)G * INFO);
+  read_to_host(c, htab.data(), tab, sizeof(int64_t) * htab.size(), s);
+  const int64_t total = htab[0];
+  c->tracef("spgemm: nnz(C) = %lld", (long long)total);
+  if (st) st->nnz = total;
+  // 5. numeric, group by group into the one output
+  Buf col(c, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), out->kind);
+  Buf val(c, es * (size_t)std::max<int64_t>(total, 1), out->kind);
+  Buf kept(c, sizeof(int64_t) * (size_t)m);
+  fill_i64(kept.as<int64_t>(), m, 0, s);  // rows in no bin (no outputs) keep 0
+  const int64_t *rpC = out->rowptr.as<int64_t>();
+  int32_t *cC = col.as<int32_t>();
+  V *vC = val.as<V>();
+  int64_t *kp = kept.as<int64_t>();
+  if (total > 0)
+    for (int q = 0; q < G; q++)
+      numeric_launch<SR>(c, id, Am, Bm, w.as<int64_t>(), groups[q], htab.data() + 1 + (size_t)q * INFO,
+                         tab + 1 + (int64_t)q * INFO, lists[q].as<int32_t>(), sorted, rpC, cC, vC, kp, fl, st, s);
   // 6. compaction when identity results were dropped
-  int32_t flags_h[2] = {0, 0};
+  int32_t flags_h[4] = {0, 0, 0, 0};
   read_to_host(c, flags_h, fl, sizeof(flags_h), s);
   c->tracef("spgemm: numeric done (short %d, error %d)", flags_h[0], flags_h[1]);
+  if (flags_h[2] || flags_h[3]) fail(SRTC_ERR_DEVICE, "spgemm: symbolic hash table overflow (internal invariant)");
   if (flags_h[1]) fail(SRTC_ERR_DEVICE, "spgemm: numeric hash table overflow (internal invariant)");
   const int32_t short_flag = flags_h[0];
   if (short_flag) {
@@ -1496,6 +1625,17 @@ void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int s
   }
   out->col = std::move(col);
   out->val = std::move(val);
+}
+
+template <class SR>
+void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, const std::vector<RowGroup> *groups,
+                  int sched, int sorted, CsrOut *out, SpgemmStats *st, hipStream_t s) {
+  if (groups) {
+    spgemm_groups<SR>(c, idv, Am, Bm, *groups, sorted, out, st, s);
+  } else {
+    const std::vector<RowGroup> one{RowGroup{nullptr, Am.m, sched}};
+    spgemm_groups<SR>(c, idv, Am, Bm, one, sorted, out, st, s);
+  }
 }
 
 // Row statistics for the schedule features: log2 histograms of row lengths
@@ -1630,7 +1770,16 @@ void spgemm(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B
             CsrOut *out, SpgemmStats *st, hipStream_t s) {
   if (A.n != B.m) fail(SRTC_ERR_DIM, "spgemm: inner dimensions differ");
   if (B.n >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "spgemm: more than 2^31-2 columns");
-  SRTC_DISPATCH_SR(sr, dt, spgemm_typed, c, id, A, B, sched, sorted, out, st, s);
+  (void)schedule(sched);
+  SRTC_DISPATCH_SR(sr, dt, spgemm_typed, c, id, A, B, nullptr, sched, sorted, out, st, s);
+}
+
+void spgemm_grouped(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B,
+                    const std::vector<RowGroup> &groups, int sorted, CsrOut *out, SpgemmStats *st, hipStream_t s) {
+  if (A.n != B.m) fail(SRTC_ERR_DIM, "spgemm: inner dimensions differ");
+  if (B.n >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "spgemm: more than 2^31-2 columns");
+  for (const RowGroup &g : groups) (void)schedule(g.sched);
+  SRTC_DISPATCH_SR(sr, dt, spgemm_typed, c, id, A, B, &groups, 0, sorted, out, st, s);
 }
 
 }  // namespace srtc
@@ -1638,8 +1787,18 @@ void spgemm(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B
 namespace srtc {
 
 // Features of an SpGEMM problem (32 scale-free numbers; the selector's
-// input).  Compression ratio: products / outputs over a stratified sample of
-// up to 512 rows, counted exactly by the symbolic kernels.
+// input, Section 5.1's performance-model inputs):
+//   0..9    fraction of A's rows with row length of bit length b (b >= 9 in 9)
+//   10..19  fraction of rows whose product count w has (bit length + 1) / 2
+//           = b (base-4 bins; bin 0 = no products, b >= 9 in 19)
+//   20..23  log2 of (rows + 1), (columns of B + 1), (nnz(A) + 1), (sum w + 1)
+//   24      log2 of the compression ratio: sum w / outputs over the rows
+//           floor(t m / s), t < s = min(512, m) (structural outputs, counted
+//           by the symbolic kernels; 1 when nothing is sampled)
+//   25, 26  log2 of (max w + 1), (longest A row + 1)
+//   27      coefficient of variation of w (population standard deviation /
+//           mean; 0 for a zero mean)
+//   28..31  the semiring, one-hot
 void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B, float *out, hipStream_t s) {
   for (int q = 0; q < SRTC_NUM_FEATURES; q++) out[q] = 0.f;
   const int64_t m = A.m;
@@ -1672,7 +1831,7 @@ void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B,
     Buf list(c, sizeof(int32_t) * (size_t)ns);
     Buf nnz_row(c, sizeof(int64_t) * (size_t)m);
     fill_i64(nnz_row.as<int64_t>(), m, 0, s);
-    run_symbolic(L, schedule(0), A, B, wsel.as<int64_t>(), rows.as<int32_t>(), ns, info.as<int64_t>(),
+    run_symbolic(L, schedule(0), A, B, w.as<int64_t>(), rows.as<int32_t>(), ns, info.as<int64_t>(),
                  list.as<int32_t>(), nnz_row.as<int64_t>(), info.as<int64_t>() + INFO - 1);
     gather_i64<<<gridn(ns), 256, 0, s>>>(nnz_row.as<int64_t>(), rows.as<int32_t>(), ns, nsel.as<int64_t>());
     std::vector<int64_t> hw(ns), hn(ns);
@@ -1700,10 +1859,10 @@ void spgemm_features(Ctx *c, int sr, int dt, const CsrView &A, const CsrView &B,
   out[25] = (float)std::log2((double)hs[21] + 1);
   out[26] = (float)std::log2((double)hs[22] + 1);
   out[27] = (float)(mean > 0 ? std::sqrt(var) / mean : 0.0);
-  out[28] = (float)(hs[20] / mm);
-  out[29] = (float)sr / 3.0f;
-  out[30] = (float)dtype_size(dt) / 8.0f;
-  out[31] = (float)std::log2((double)B.nnz / (double)std::max<int64_t>(B.m, 1) + 1);
+  // the semiring, one-hot (the fraction of rows without products is
+  // feature 10, the first bin of the product histogram)
+  (void)dt;
+  for (int q = 0; q < 4; q++) out[28 + q] = sr == q ? 1.f : 0.f;
 }
 
 }  // namespace srtc

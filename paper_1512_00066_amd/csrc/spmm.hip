@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256) spmm_items(const int32_t *__restrict__ ir
             const V prev = Y[row * s + col];
             if (!SR::absent(prev, id)) acc = SR::add(acc, (A)prev);
           }
-          const V o = SR::out(acc);
+          const V o = out_clamped<SR>(acc, id);
           Y[row * s + col] = o;
           if (MODE == 1) diff = o != X[row * s + col];
         }
@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) spmm_combine(const int32_t *__restrict__ 
         const V prev = Y[row * s + col];
         if (!SR::absent(prev, id)) acc = SR::add(acc, (A)prev);
       }
-      const V o = SR::out(acc);
+      const V o = out_clamped<SR>(acc, id);
       Y[row * s + col] = o;
       if (MODE == 1 && o != X[row * s + col]) {
         *changed = 1;

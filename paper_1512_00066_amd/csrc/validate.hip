@@ -4,7 +4,8 @@
 // at nnz, columns in [0, ncols) and strictly ascending within each row (the
 // canonical form the fold produces; the dense accumulator windows rely on
 // the order).  COO keys must lie in [0, product of dims).  Float (min,+)
-// values may not be NaN or -inf (the identity +inf is allowed).  Every read
+// values may not be NaN or -inf (the identity +inf is allowed); int32
+// (min,+) values must lie in [-id, id].  Every read
 // stays inside the operand's declared extents, so a malformed operand is
 // reported, never dereferenced out of range.
 #include <cmath>
@@ -23,6 +24,7 @@ enum : int32_t {
   BAD_COL_ORDER = 16,
   BAD_KEY_RANGE = 32,
   BAD_VALUE = 64,
+  BAD_RANGE = 128,
 };
 
 __global__ void check_csr_kernel(const int64_t *__restrict__ rp, int64_t m, const int32_t *__restrict__ col,
@@ -65,11 +67,22 @@ __global__ void check_tropical_kernel(const T *__restrict__ v, int64_t n, int32_
   if (bad) atomicOr(err, bad);
 }
 
+// (min,+) int32 operands must lie in [-id, id] so that no sum of two
+// overflows int32 (the identity is at most INT32_MAX / 2).
+__global__ void check_tropical_i32_kernel(const int32_t *__restrict__ v, int64_t n, int32_t id, int32_t *err) {
+  int32_t bad = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = v[e];
+    if (x < -id || x > id) bad |= BAD_RANGE;
+  }
+  if (bad) atomicOr(err, bad);
+}
+
 unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); }
 
 }  // namespace
 
-void validate_operand(Ctx *c, int sr, const srtc_tensor *t, const char *name, hipStream_t s) {
+void validate_operand(Ctx *c, int sr, const srtc_tensor *t, const char *name, hipStream_t s, const IdVal *id) {
   if (t->format == SRTC_DENSE) return;
   Buf err(c, 64);
   fill_i32(err.as<int32_t>(), 1, 0, s);
@@ -91,6 +104,9 @@ void validate_operand(Ctx *c, int sr, const srtc_tensor *t, const char *name, hi
   if (sr == SRTC_MIN_PLUS && nvals > 0) {
     if (t->dtype == SRTC_F32)
       check_tropical_kernel<float><<<grid_of(nvals), 256, 0, s>>>((const float *)t->vals, nvals, err.as<int32_t>());
+    if (t->dtype == SRTC_I32 && id)
+      check_tropical_i32_kernel<<<grid_of(nvals), 256, 0, s>>>((const int32_t *)t->vals, nvals, (int32_t)id->i,
+                                                               err.as<int32_t>());
     SRTC_LAUNCH_CHECK("check_tropical_kernel");
   }
   int32_t bad = 0;
@@ -104,6 +120,7 @@ void validate_operand(Ctx *c, int sr, const srtc_tensor *t, const char *name, hi
   if (bad & BAD_COL_ORDER) msg += " columns not strictly ascending within a row;";
   if (bad & BAD_KEY_RANGE) msg += " COO key out of range;";
   if (bad & BAD_VALUE) msg += " NaN or -inf value for (min,+);";
+  if (bad & BAD_RANGE) msg += " (min,+) int32 value outside [-identity, identity];";
   fail(SRTC_ERR_FORMAT, msg);
 }
 

@@ -1,9 +1,12 @@
 """Full-size parity of the measured workloads (GPU only).
 
 * R-MAT scale 18, edge factor 16, A.A over (+,x) in fp64 and fp32, in every
-  SpGEMM schedule, compared on sampled rows (the heaviest rows and a seeded
-  random sample) with the oracle computing just those rows; the order-3
-  tensor contraction of the same workload in full.
+  SpGEMM schedule, compared on sampled rows (the 300 heaviest rows and a
+  seeded 1% of all rows) with the oracle computing just those rows; the
+  order-3 tensor contraction of the same workload in full.
+* R-MAT scale 21, edge factor 16, A.A in full, streamed in row panels as the
+  benchmark runs it, in (+,x) fp64 and fp32 and (min,+) int32, on sampled
+  rows (the heaviest and a seeded random sample).
 * R-MAT scale 20: 64-source Bellman-Ford fixpoint and BFS in full.
 * 512 uneven ER instances, batched against per-instance and the oracle.
 """
@@ -38,8 +41,10 @@ def test_rmat18_square_sampled_rows(rmat18, dtype):
     rn = np.diff(O.rowptr)
     w = np.zeros(n, dtype=np.int64)
     np.add.at(w, np.repeat(np.arange(n), rn), rn[O.col])
-    heavy = np.argsort(w)[-12:]
-    rnd = synth.permutation(synth.stream_key(synth.SEED_CFG1, 99), n)[:300]
+    # the 300 heaviest rows (the dense-window and ranked-group paths carry
+    # nearly all of C) and a seeded 1% of all rows
+    heavy = np.argsort(w)[-300:]
+    rnd = synth.permutation(synth.stream_key(synth.SEED_CFG1, 99), n)[:n // 100]
     rows = np.unique(np.concatenate([heavy, rnd]))
     exp = oracle.spgemm("plus_times", dtype, O, O, rows=rows)
     for sch in range(srtc.NUM_SCHEDULES):
@@ -201,3 +206,54 @@ def test_spgemm_wide_matrix_multiwindow_symbolic(semiring, dtype):
         say("  schedule", sched)
         C = ctx.contract(semiring, "ik", A, "kj", B, "ij", schedule=sched)
         check_csr(C, exp, semiring, dtype)
+
+
+@pytest.fixture(scope="module")
+def rmat21():
+    src, dst = synth.rmat_edges(21, 16, 0.57, 0.19, 0.19, synth.SEED_CFG4, tag=21)
+    return src, dst
+
+
+@pytest.mark.parametrize("semiring,dtype,heavy,frac", [("plus_times", "f64", 300, 1e-3),
+                                                         ("plus_times", "f32", 100, 5e-4),
+                                                         ("min_plus", "i32", 100, 5e-4)])
+def test_rmat21_square_in_panels_sampled_rows(rmat21, semiring, dtype, heavy, frac):
+    """R-MAT scale 21 (edge factor 16) A.A in full, streamed in row panels
+    of at most 8e9 products as the benchmark runs it (schedule chosen by the
+    library); the heaviest rows and a seeded random sample are checked
+    against the oracle computing just those rows."""
+    src, dst = rmat21
+    n = 1 << 21
+    v = synth.edge_values(dtype, src.size, synth.SEED_CFG4, tag=21, lo=1, hi=100)
+    ctx = srtc.Context(0)
+    keys = torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda")
+    A = ctx.fold(semiring, srtc.COO(keys, torch.as_tensor(v, device="cuda"), (n, n)), "ij", "i", "j")
+    del keys
+    O = oracle.fold(semiring, dtype, dst, src, v, n, n)
+    rn = np.diff(O.rowptr)
+    w = np.zeros(n, dtype=np.int64)
+    np.add.at(w, np.repeat(np.arange(n), rn), rn[O.col])
+    rows = np.unique(np.concatenate([np.argsort(w)[-heavy:],
+                                     synth.permutation(synth.stream_key(synth.SEED_CFG4, 98), n)[:int(n * frac)]]))
+    got = {}
+
+    def take(r0, P):
+        r1 = r0 + P.shape[0]
+        sel = rows[(rows >= r0) & (rows < r1)]
+        if sel.size == 0:
+            return
+        rp = P.rowptr.cpu().numpy()
+        for r in sel:
+            a, b = int(rp[r - r0]), int(rp[r - r0 + 1])
+            got[int(r)] = (P.col[a:b].cpu().numpy(), P.val[a:b].cpu().numpy())
+
+    say("rmat21", semiring, dtype, "streaming")
+    count = ctx.contract_panels(semiring, "ik", A, "kj", A, "ij", take, panel_products=8_000_000_000)
+    say("rmat21 panels", count, "oracle rows", rows.size)
+    assert count >= int(w.sum() // 8_000_000_000)
+    exp = oracle.spgemm(semiring, dtype, O, O, rows=rows)
+    rp = np.concatenate([[0], np.cumsum([got[int(r)][0].size if int(r) in got else 0 for r in rows])])
+    col = np.concatenate([got[int(r)][0] for r in rows if int(r) in got])
+    val = np.concatenate([got[int(r)][1] for r in rows if int(r) in got])
+    G = srtc.CSR(torch.as_tensor(rp), torch.as_tensor(col), torch.as_tensor(val), (rows.size, n))
+    check_csr(G, exp, semiring, dtype)

@@ -166,6 +166,50 @@ def test_spgemm_window_groups_all_schedules(ctx, semiring, dtype, cancel):
         check_csr(ctx.contract(semiring, "ik", GA, "kj", GB, "ij", schedule=sch), exp, semiring, dtype)
 
 
+def wide_window_pair(semiring, dtype, seed):
+    """A (8 x 1024) times B (1024 x 1,310,928): every B row holds one entry in
+    each 8192-column stretch (160 of them, the last ragged), so a row of the
+    product spreads its products thinly over 40 to 320 dense windows
+    depending on the window width -- more than a ranked group may span (at
+    most 32 windows).  A's rows of 1, 5, 40 and 200 entries make runs that end
+    at the span limit, at the product cap of a group, or hold one product per
+    window; a row of 600 entries (longer than a block) and an empty row take
+    the other paths."""
+    rng = np.random.default_rng(seed)
+    k, n, S = 1024, 160 * 8192 + 208, 8192
+    b_rows, b_cols = [], []
+    for r in range(k):
+        cols = np.arange(160) * S + (r * 37 + np.arange(160) * 11) % S
+        cols = np.unique(np.append(cols, n - 1 - (r % 200)))
+        b_rows.append(np.full(cols.size, r)), b_cols.append(cols)
+    a_rows, a_cols = [], []
+    sizes = [1, 5, 40, 200, 600, 0, 3, 120]
+    for i, c in enumerate(sizes):
+        cols = np.sort(rng.choice(k, size=c, replace=False))
+        a_rows.append(np.full(c, i)), a_cols.append(cols)
+    ar, ac = np.concatenate(a_rows), np.concatenate(a_cols)
+    br, bc = np.concatenate(b_rows), np.concatenate(b_cols)
+    av, bv = values(semiring, dtype, ar.size, seed, 1), values(semiring, dtype, br.size, seed, 2)
+    return (ar, ac, av, len(sizes), k), (br, bc, bv, k, n)
+
+
+@pytest.mark.parametrize("semiring,dtype", [("plus_times", "f64"), ("plus_times", "f32"), ("min_plus", "i32"),
+                                            ("max_times", "f64"), ("or_and", "bool")])
+def test_spgemm_groups_past_the_span_limit(ctx, semiring, dtype):
+    """Ranked groups cut at their window-span limit and at their product
+    cap, then continued, over more than 30 windows of the widest window;
+    every schedule."""
+    say("wide windows", semiring, dtype)
+    (ar, ac, av, m, k), (br, bc, bv, _, n) = wide_window_pair(semiring, dtype, 62)
+    GA = gpu_fold(ctx, semiring, dtype, ar, ac, av, m, k)
+    GB = gpu_fold(ctx, semiring, dtype, br, bc, bv, k, n)
+    exp = oracle.spgemm(semiring, dtype, oracle.fold(semiring, dtype, ar, ac, av, m, k),
+                        oracle.fold(semiring, dtype, br, bc, bv, k, n))
+    assert np.diff(exp.rowptr).max() > 30 * 1000
+    for sch in range(srtc.NUM_SCHEDULES):
+        check_csr(ctx.contract(semiring, "ik", GA, "kj", GB, "ij", schedule=sch), exp, semiring, dtype)
+
+
 def test_spgemm_star_and_identity(ctx):
     say("star / identity")
     L = 3000
@@ -452,6 +496,41 @@ def test_batch_contract_and_fixpoint(ctx):
 
 
 # -------------------------------------------------------------------- MLP --
+def test_batch_index_strings_and_per_instance_schedules(ctx):
+    """Batched C_b = A_b (x) B_b with one schedule per instance (every
+    schedule id, and -1 = choose) is bit-identical to per-instance calls
+    with those schedules and matches the oracle; A given transposed as COO
+    ("ki","kj","ij") folds per instance to the same result."""
+    ninst = 20
+    As, ATs, Os, want = [], [], [], []
+    scheds = [(b % (srtc.NUM_SCHEDULES + 1)) - 1 for b in range(ninst)]
+    for b in range(ninst):
+        n = 300 + 137 * b
+        src, dst = synth.er_edges(n, 3.0 + b, 0x5EEDBA7C, tag=b)
+        w = synth.edge_values("i32", src.size, 0x5EEDBA7C, tag=b, lo=1, hi=100)
+        G = gpu_fold(ctx, "min_plus", "i32", dst, src, w, n, n)
+        As.append(G)
+        # A^T stored as (k, i) index-value pairs
+        ATs.append(srtc.COO(torch.as_tensor(src.astype(np.int64) * n + dst, device="cuda"),
+                            torch.as_tensor(w, device="cuda"), (n, n)))
+        O = oracle.fold("min_plus", "i32", dst, src, w, n, n)
+        Os.append(oracle.spgemm("min_plus", "i32", O, O))
+        want.append(ctx.contract("min_plus", "ik", G, "kj", G, "ij", schedule=max(scheds[b], 0)))
+    Cs = ctx.batch_contract("min_plus", As, As, schedules=scheds)
+    Ct = ctx.batch_contract("min_plus", ATs, As, ia="ki", ib="kj", ic="ij", schedule=5)
+    for b in range(ninst):
+        for got in (Cs[b], Ct[b]):
+            g, e = got.to_host(), want[b].to_host()
+            assert all(np.array_equal(x, y) for x, y in zip(g, e)), b
+            check_csr(got, Os[b], "min_plus", "i32")
+    with pytest.raises(srtc.SrtcError):
+        ctx.batch_contract("min_plus", As[:2], As[:2], schedules=[0])
+    for ia, ib, ic in (("ik", "kj", "ik"), ("ik", "kj", "ji"), ("ik", "jl", "ij"), ("ii", "kj", "ij")):
+        with pytest.raises(srtc.SrtcError) as e:
+            ctx.batch_contract("min_plus", As[:2], As[:2], ia=ia, ib=ib, ic=ic)
+        assert e.value.status == -2
+
+
 def test_mlp_gradients_match_oracle(ctx):
     say("mlp gradients")
     from oracle import mlp

@@ -685,3 +685,104 @@ def test_transform_pins():
     assert np.array_equal(out, M / (va[:, None] + vb[None, :]))
     assert np.array_equal(oracle.transform("recip", 2.0, "", None, "", None, "ij", M), 2.0 / M)
     assert np.array_equal(oracle.transform("fma", 0.5, "ji", M.T, "ij", M, "ij", M), M + 0.5 * M * M)
+
+
+# ------------------------------------------------- schedule features pins --
+def _bin_of_len(x):
+    # row-length bin from its definition: the bit length, capped at 9
+    return min(9, int(x).bit_length())
+
+
+def test_features_path_graph_closed_form():
+    # path 0 -> 1 -> ... -> n-1: row 0 of A is empty, row i >= 1 holds (i, i-1);
+    # w_0 = w_1 = 0 and w_i = 1 (i >= 2); every product reaches its own column
+    n = 40
+    A = oracle.fold("min_plus", "i32", np.arange(1, n), np.arange(0, n - 1), np.ones(n - 1, np.int32), n, n)
+    f = oracle.features("min_plus", A, A)
+    exp = np.zeros(32)
+    exp[0], exp[1] = 1 / n, (n - 1) / n          # one empty row, n-1 rows of length 1
+    exp[10], exp[11] = 2 / n, (n - 2) / n        # two rows without products
+    exp[20], exp[21], exp[22] = np.log2(n + 1), np.log2(n + 1), np.log2(n)
+    exp[23] = np.log2(n - 1)                     # sum w = n - 2
+    exp[24] = 0.0                                # one output per product
+    exp[25], exp[26] = 1.0, 1.0                  # log2(1 + 1)
+    exp[27] = np.sqrt(2.0 / (n - 2))             # CV of n-2 ones and 2 zeros
+    exp[29] = 1.0                                # (min,+)
+    np.testing.assert_allclose(f, exp.astype(np.float32), rtol=1e-6, atol=1e-7)
+
+
+def test_features_star_closed_form():
+    # bidirectional star with L leaves: every row has L products; row 0 reaches
+    # only column 0, a leaf reaches all L leaves: CR = L(L+1) / (L^2 + 1)
+    L = 100
+    rows = np.concatenate([np.zeros(L, np.int64), np.arange(1, L + 1)])
+    cols = np.concatenate([np.arange(1, L + 1), np.zeros(L, np.int64)])
+    A = oracle.fold("plus_times", "f64", rows, cols, np.ones(2 * L), L + 1, L + 1)
+    f = oracle.features("plus_times", A, A)
+    m = L + 1
+    assert f[_bin_of_len(L)] == np.float32(1 / m) and f[1] == np.float32(L / m)   # 100 -> bit length 7
+    assert f[10 + (L.bit_length() + 1) // 2] == np.float32(1.0)                   # w = 100: bin 4
+    assert f[24] == np.float32(np.log2(L * (L + 1) / (L * L + 1)))
+    assert f[27] == 0.0                                                           # every w equal
+    assert f[25] == np.float32(np.log2(L + 1)) and f[26] == np.float32(np.log2(L + 1))
+    assert f[23] == np.float32(np.log2(L * (L + 1) + 1))
+    assert list(f[28:]) == [1, 0, 0, 0]
+
+
+def test_features_identity_and_empty():
+    n = 700
+    I = oracle.fold("or_and", "bool", np.arange(n), np.arange(n), np.ones(n, np.uint8), n, n)
+    f = oracle.features("or_and", I, I)
+    assert f[1] == 1.0 and f[11] == 1.0 and f[24] == 0.0 and f[27] == 0.0
+    assert list(f[28:]) == [0, 0, 1, 0]
+    E = oracle.fold("or_and", "bool", np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0, np.uint8), 5, 5)
+    g = oracle.features("or_and", E, E)
+    assert g[0] == 1.0 and g[10] == 1.0 and g[24] == 0.0 and g[27] == 0.0 and g[23] == 0.0
+
+
+def test_features_compression_ratio_samples_stride_rows():
+    # m = 1024 rows, s = 512 samples: rows floor(t * 1024 / 512) = 2t, the
+    # even rows.  Even rows reach 4 columns through 8 products (CR 2), odd rows
+    # 8 columns through 8 products (CR 1): the estimate must be exactly 2.
+    m = 1024
+    # B: 2 rows per "kind"; B row 0 = cols {0,1,2,3}, row 1 = cols {0,1,2,3},
+    # row 2 = {4..7}, row 3 = {8..11}
+    brows = np.repeat(np.arange(4), 4)
+    bcols = np.array([0, 1, 2, 3, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+    B = oracle.fold("plus_times", "f64", brows, bcols, np.ones(16), 4, 12)
+    even = np.arange(0, m, 2)
+    odd = np.arange(1, m, 2)
+    arows = np.concatenate([np.repeat(even, 2), np.repeat(odd, 2)])
+    acols = np.concatenate([np.tile([0, 1], even.size), np.tile([2, 3], odd.size)])
+    A = oracle.fold("plus_times", "f64", arows, acols, np.ones(arows.size), m, 4)
+    f = oracle.features("plus_times", A, B)
+    assert f[24] == np.float32(1.0)  # log2(2)
+    assert f[23] == np.float32(np.log2(8 * m + 1))
+
+
+# ----------------------------------------------------------- Adam pins --
+def test_adam_first_step_closed_form():
+    # with zero moments the bias corrections cancel exactly: the first step
+    # moves every parameter by -lr g / (|g| + eps)
+    from oracle import mlp
+    rng = np.random.default_rng(5)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50)
+    lr, eps = 0.01, 1e-8
+    p1, m, v = mlp.adam_step(p, g, np.zeros(50), np.zeros(50), 1, lr, 0.9, 0.999, eps)
+    np.testing.assert_allclose(p1, p - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-12)
+
+
+def test_adam_two_steps_by_hand():
+    # beta1 = 1/2, beta2 = 3/4, lr = 1/10, eps = 0, p0 = 1, g1 = 2, g2 = 1:
+    # step 1: p1 = 1 - 0.1 * 2 / 2 = 0.9; m = 1, v = 1
+    # step 2: m = 0.5 + 0.5 = 1, mh = 1 / (1 - 1/4) = 4/3;
+    #         v = 0.75 + 0.25 = 1, vh = 1 / (1 - 9/16) = 16/7;
+    #         p2 = 0.9 - 0.1 * (4/3) / (4 / sqrt 7) = 0.9 - sqrt(7) / 30
+    from oracle import mlp
+    p1, m, v = mlp.adam_step(np.array([1.0]), np.array([2.0]), np.zeros(1), np.zeros(1), 1, 0.1, 0.5, 0.75, 0.0)
+    assert abs(p1[0] - 0.9) < 1e-15 and abs(m[0] - 1.0) < 1e-15 and abs(v[0] - 1.0) < 1e-15
+    p2, m, v = mlp.adam_step(p1, np.array([1.0]), m, v, 2, 0.1, 0.5, 0.75, 0.0)
+    assert abs(p2[0] - (0.9 - np.sqrt(7.0) / 30.0)) < 1e-15
