@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the semiring contraction hot path on one MI355X.
 
-Default workload (one "step" = every hot-path stage this workload uses,
-over one batch of synthetic input already resident in HBM):
-  * R-MAT scale 18 (262,144 vertices), edge factor 16,
-    (a,b,c,d) = (0.57,0.19,0.19,0.05), relabelled; values U[0,1)
-    - fold of the COO edge list to CSR (fp64), schedule selection,
-      C = A.A over (+,x) fp64: symbolic, numeric, compaction
-    - the same in fp32 (exact products, fp64 accumulation)
-  * order-3 tensor T[512,512,512] (Bernoulli 1e-3, fp32) contracted with a
-    dense M[512,64]: C["ijl"] = T["ijk"] * M["kl"] (fold + SpMM)
+Default workload (--workload rmat21; one "step" = every hot-path stage over
+one batch of synthetic input already resident in HBM):
+  * R-MAT scale 21 (2,097,152 vertices), edge factor 16,
+    (a,b,c,d) = (0.57,0.19,0.19,0.05), relabelled
+  * C = A.A in full, in (+,x) fp64 and fp32 (values U[0,1)) and (min,+)
+    int32 (weights U[1,100]): per product the fold of the COO edge list to
+    CSR, the features and the learned selector's schedule choice, then the
+    symbolic, numeric and compaction passes of every row panel (C has
+    2.4e10 entries, more than one GPU holds in fp64, so it is streamed in
+    panels of at most --panel-products products and each panel is
+    released once handed over)
+  * the selector is trained in the same run, before the timed steps, on
+    timings of generated matrices and R-MAT 17-19 row panels
 Metric: semiring ops per second (one op = one (x) and one (+); SpGEMM ops =
-products A_ik*B_kj, SpMM ops = nnz(T) * 64), aggregated over the step.
+products A_ik*B_kj), aggregated over the step.  Other workloads:
+--workload rmat18 | rmat20_sssp | batch512 | selector | masked18 | apsp2048 |
+mp3 | jacobi | gemm.
 
 Prints one JSON line (see the module help for the fields).
 """
@@ -117,6 +123,226 @@ def cpu_baseline_rmat18(inp, products_by_row, seconds):
                       f"+ the full tensor contraction; {t:.1f} s"}
 
 
+def oracle_timing(fn, reps):
+    """Median seconds of `reps` runs of fn after one warm-up (the paper's
+    protocol, Section 6)."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def roofline_of(prof, dominant=None):
+    """Roofline record of the dominant kernel (the largest total time, or
+    the named one): algorithmic bytes per launch over the average launch
+    time (HIP events on the launch stream), HBM bytes from the committed
+    counter record when it was taken on the current kernel sources."""
+    if dominant is None:
+        nm, cnt, tms, by = max(prof, key=lambda r: r[2])
+    else:
+        nm, cnt, tms, by = next(r for r in prof if r[0] == dominant)
+    achieved = (by / cnt) / (tms / cnt / 1e3) / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf):
+        try:
+            rec = json.load(open(tf))
+            k = rec.get("kernels", {}).get(nm)
+            if (k and rec.get("source_hash") == kernel_source_hash()
+                    and rec.get("workload", "rmat18") == WORKLOAD_TAG[0]):
+                traffic = k.get("hbm_bytes_per_launch")
+        except Exception:
+            traffic = None
+    return {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_launch_ms": round(tms / cnt, 4),
+            "algorithmic_bytes_per_launch": round(by / cnt), "launches": cnt}
+
+
+WORKLOAD_TAG = [""]
+
+
+def train_selector(ctx, args):
+    """A selector trained on timings of the training recipe (generated
+    matrices as (+,x) fp32 and (min,+) int32 A.A, and row panels of R-MAT
+    17-19 graphs), or loaded from --selector-file."""
+    import torch
+    import paper_1512_00066_amd as srtc
+    from paper_1512_00066_amd import selector as S
+    from gen import synth
+    if args.selector_file:
+        ctx.selector_load(args.selector_file)
+        return {"loaded": args.selector_file}
+    pairs = (("plus_times", "f32"), ("min_plus", "i32"))
+    X, T = [], []
+    t0 = time.perf_counter()
+    for i in range(args.bench_selector_matrices):
+        fam, n, src, dst, _ = synth.selector_matrix(i, synth.SEED_CFG4)
+        keys = torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda")
+        for sr, dt in pairs:
+            v = synth.edge_values(dt, src.size, synth.SEED_CFG4, tag=i, lo=1, hi=100)
+            A = ctx.fold(sr, srtc.COO(keys, torch.as_tensor(v, device="cuda"), (n, n)), "ij", "i", "j")
+            f, t = S.collect(ctx, sr, A, A, reps=3)
+            X.append(f)
+            T.append(t)
+    for scale in (17, 18, 19):
+        n = 1 << scale
+        src, dst = synth.rmat_edges(scale, 16, 0.57, 0.19, 0.19, synth.SEED_CFG4, tag=300 + scale)
+        keys_b = torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda")
+        for sr, dt in pairs:
+            v = synth.edge_values(dt, src.size, synth.SEED_CFG4, tag=300 + scale, lo=1, hi=100)
+            B = ctx.fold(sr, srtc.COO(keys_b, torch.as_tensor(v, device="cuda"), (n, n)), "ij", "i", "j")
+            for j in range(args.bench_selector_panels):
+                rows = synth.selector_panel_rows(n, 1000 * scale + j, synth.SEED_CFG4)
+                pos = np.full(n, -1, dtype=np.int64)
+                pos[rows] = np.arange(rows.size)
+                sel = pos[dst] >= 0
+                Ap = ctx.fold(sr, srtc.COO(torch.as_tensor(pos[dst[sel]] * n + src[sel], device="cuda"),
+                                           torch.as_tensor(v[sel], device="cuda"), (rows.size, n)), "ij", "i", "j")
+                f, t = S.collect(ctx, sr, Ap, B, reps=3)
+                X.append(f)
+                T.append(t)
+    X, T = np.array(X, np.float32), np.array(T, np.float64)
+    t1 = time.perf_counter()
+    loss = S.train(ctx, X, T, epochs=400, batch=64, lr=1e-3, seed=0)
+    fixed = S.best_fixed(T)
+    ev = S.evaluate(ctx, X, T, fixed)
+    log(f"selector: {len(X)} samples collected in {t1 - t0:.1f} s, trained to loss {loss:.4f}; "
+        f"in-sample regret {ev['mean_regret']:.3f}, gain over fixed schedule {fixed} {ev['total_gain']:.3f}")
+    return {"samples": int(len(X)), "collect_s": round(t1 - t0, 1), "train_loss": loss, "fixed_schedule": fixed,
+            "in_sample_mean_regret": ev["mean_regret"], "in_sample_gain": ev["total_gain"]}
+
+
+def run_rmat21(args):
+    """R-MAT scale 21 (2,097,152 vertices), edge factor 16, (a,b,c,d) =
+    (0.57,0.19,0.19,0.05), relabelled: the full square C = A.A, whose
+    output (2.4e10 entries) exceeds what one GPU holds in fp64, streamed in
+    row panels through the library.  A step, for each of (+,x) fp64 (values
+    U[0,1)), (+,x) fp32 and (min,+) int32 (weights U[1,100]): fold of the
+    COO edge list to CSR, features and schedule selection by the learned
+    selector, then every row panel's symbolic, numeric and compaction
+    passes; each panel is handed to a consumer that releases it."""
+    import torch
+    import oracle
+    import paper_1512_00066_amd as srtc
+    from gen import synth
+
+    WORKLOAD_TAG[0] = "rmat21"
+    ctx = srtc.Context(0)
+    scale = 21
+    n = 1 << scale
+    log("generating R-MAT 21 ...")
+    src, dst = synth.rmat_edges(scale, 16, 0.57, 0.19, 0.19, synth.SEED_CFG4, tag=21)
+    kinds = (("plus_times", "f64"), ("plus_times", "f32"), ("min_plus", "i32"))
+    vals = {dt: synth.edge_values(dt, src.size, synth.SEED_CFG4, tag=21, lo=1, hi=100) for _, dt in kinds}
+    keys = torch.as_tensor(dst.astype(np.int64) * n + src, device="cuda")
+    coo = {dt: srtc.COO(keys, torch.as_tensor(vals[dt], device="cuda"), (n, n)) for _, dt in kinds}
+    A = ctx.fold("plus_times", coo["f64"], "ij", "i", "j")
+    rn = torch.diff(A.rowptr)
+    wrow = torch.zeros(n, dtype=torch.int64, device="cuda")
+    wrow.index_add_(0, torch.repeat_interleave(torch.arange(n, device="cuda"), rn), rn[A.col.long()])
+    products = int(wrow.sum().item())
+    wrow = wrow.cpu().numpy()
+    del A, rn
+    ops_step = len(kinds) * products
+    log(f"nnz(A) entries generated {src.size}, products per A.A {products}, ops/step {ops_step:.4e}")
+    sel_info = {"forced_schedule": args.schedule} if args.schedule >= 0 else train_selector(ctx, args)
+    if args.schedule < 0:
+        # the schedule the timed step will pick for each product (the same
+        # features and network; reported, not used)
+        picks = {}
+        for sr, dt in kinds:
+            Af = ctx.fold(sr, coo[dt], "ij", "i", "j")
+            picks[dt] = ctx.select(ctx.features(sr, Af, Af))
+            del Af
+        sel_info["picks"] = picks
+        log(f"selected schedules: {picks}")
+    if args.dtypes:
+        kinds = tuple(k for k in kinds if k[1] in args.dtypes.split(","))
+        ops_step = len(kinds) * products
+    budget = int(args.panel_products)
+    nnz_out = {}
+
+    def step():
+        for sr, dt in kinds:
+            Af = ctx.fold(sr, coo[dt], "ij", "i", "j")
+            tot = [0]
+
+            def consume(r0, P):
+                tot[0] += P.nnz
+
+            ctx.contract_panels(sr, "ik", Af, "kj", Af, "ij", consume, panel_products=budget, schedule=args.schedule)
+            nnz_out[dt] = tot[0]
+            del Af
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    srtc.lib().srtc_profile_enable(ctx._h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = profile_table(ctx)
+    srtc.lib().srtc_profile_enable(ctx._h, 0)
+    ms = (t1 - t0) * 1e3 / args.steps
+    log(f"nnz(C) {nnz_out}; {ms:.1f} ms/step")
+    log("kernel profile (name, launches, total ms, GB/s algorithmic):")
+    for nm, cnt, tms, by in sorted(prof, key=lambda r: -r[2]):
+        log(f"  {nm:34s} {cnt:5d} {tms:10.3f} {by / max(tms, 1e-9) / 1e6:10.1f}")
+    out = {"metric": METRIC, "value": ops_step * args.steps / (t1 - t0), "unit": "semiring-ops/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32+i32", "data": "synthetic",
+           "config": {"workload": "rmat21_AxA_full_panels_f64_f32_i32", "rmat_scale": scale, "edge_factor": 16,
+                      "abcd": [0.57, 0.19, 0.19, 0.05], "products_per_AxA": products, "nnz_C": nnz_out,
+                      "panel_products": budget, "selector": sel_info},
+           "roofline": roofline_of(prof)}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline_sampled(n, src, dst, vals, kinds, wrow, args.cpu_seconds, synth.SEED_CFG4)
+    return out
+
+
+def cpu_baseline_sampled(n, src, dst, vals, kinds, w, seconds, seed):
+    """The oracle on a bounded random sample of rows of the same products:
+    median of 3 timed runs after a warm-up on all host threads, and on one
+    thread for the first product, as semiring-ops/s."""
+    import oracle
+    from gen import synth
+    Os = {dt: oracle.fold(sr, dt, dst, src, vals[dt], n, n) for sr, dt in kinds}
+    perm = synth.permutation(synth.stream_key(seed, 77), n)
+    cum = np.cumsum(w[perm])
+    sr0, dt0 = kinds[0]
+    k0 = int(np.searchsorted(cum, 2e7)) + 1
+    t0 = time.perf_counter()
+    oracle.spgemm(sr0, dt0, Os[dt0], Os[dt0], rows=np.sort(perm[:k0]))
+    rate = max(cum[k0 - 1] / max(time.perf_counter() - t0, 1e-3), 1.0)
+    # 4 runs per product (warm-up + 3) plus the one-thread runs: ~seconds total
+    k = int(np.searchsorted(cum, rate * seconds / (5.0 * len(kinds)))) + 1
+    rows = np.sort(perm[:k])
+    ops = float(w[rows].sum())
+    t_all = 0.0
+    for sr, dt in kinds:
+        t_all += oracle_timing(lambda: oracle.spgemm(sr, dt, Os[dt], Os[dt], rows=rows), 3)
+    threads = oracle.num_threads()
+    k1 = max(1, k // max(threads, 1))
+    rows1 = np.sort(perm[:k1])
+    oracle.set_threads(1)
+    try:
+        t1 = oracle_timing(lambda: oracle.spgemm(sr0, dt0, Os[dt0], Os[dt0], rows=rows1), 3)
+    finally:
+        oracle.set_threads(threads)
+    return {"value": ops * len(kinds) / t_all, "unit": "semiring-ops/s", "cores": threads, "kind": "oracle",
+            "value_one_thread": float(w[rows1].sum()) / t1,
+            "sample": f"{k} random rows of each of the {len(kinds)} products ({int(ops)} products each), median "
+                      f"of 3 runs after a warm-up; one thread: {k1} rows of the {dt0} product; the fold is not "
+                      f"timed"}
+
+
 def run_rmat18(args):
     import torch
     import paper_1512_00066_amd as srtc
@@ -192,22 +418,8 @@ def run_rmat18(args):
     log("kernel profile (name, launches, total ms, GB/s algorithmic):")
     for nm, cnt, tms, by in sorted(prof, key=lambda r: -r[2]):
         log(f"  {nm:32s} {cnt:5d} {tms:10.3f} {by / max(tms, 1e-9) / 1e6:10.1f}")
-    dom = max(prof, key=lambda r: r[2])
-    nm, cnt, tms, by = dom
-    achieved = (by / cnt) / (tms / cnt / 1e3) / 1e9
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tf):
-        try:
-            rec = json.load(open(tf))
-            k = rec.get("kernels", {}).get(nm)
-            if k and rec.get("source_hash") == kernel_source_hash():
-                traffic = k.get("hbm_bytes_per_launch")
-        except Exception:
-            traffic = None
-    roof = {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "avg_launch_ms": round(tms / cnt, 4), "algorithmic_bytes_per_launch": round(by / cnt)}
+    WORKLOAD_TAG[0] = "rmat18"
+    roof = roofline_of(prof)
     out = {"metric": METRIC, "value": value, "unit": "semiring-ops/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -339,9 +551,18 @@ def run_batch512(args):
         host.append((src, dst, w, sources))
     nnz = [A.nnz for A in As]
     log(f"sum n={int(ns.sum())} sum nnz={sum(nnz)} products={products}")
+    # SpGEMM schedules: one forced for every instance, or each instance's
+    # own from the exhaustive tuner (median of 3 timed runs after a warm-up)
+    if args.schedule >= 0:
+        scheds = [args.schedule] * ninst
+    else:
+        t0 = time.perf_counter()
+        scheds = [int(ctx.autotune("min_plus", A, A, reps=3)[0]) for A in As]
+        log(f"per-instance autotune: {time.perf_counter() - t0:.1f} s; schedules used "
+            f"{dict(zip(*np.unique(scheds, return_counts=True)))}")
 
     def batched():
-        Cs = ctx.batch_contract("min_plus", As, As)
+        Cs = ctx.batch_contract("min_plus", As, As, schedules=scheds)
         Xs = [x.clone() for x in X0s]
         its = ctx.batch_fixpoint("min_plus", As, Xs, steps_per_check=4)
         del Cs, Xs
@@ -349,8 +570,8 @@ def run_batch512(args):
 
     def single():
         its = []
-        for A, x0 in zip(As, X0s):
-            C = ctx.contract("min_plus", "ik", A, "kj", A, "ij")
+        for A, x0, sch in zip(As, X0s, scheds):
+            C = ctx.contract("min_plus", "ik", A, "kj", A, "ij", schedule=sch)
             X = x0.clone()
             its.append(ctx.fixpoint("min_plus", A, X, steps_per_check=4))
             del C, X
@@ -386,7 +607,8 @@ def run_batch512(args):
            "config": {"workload": "batch512_er_minplus_AxA+8src_bellman_ford", "instances": ninst,
                       "sum_n": int(ns.sum()), "sum_nnz": int(sum(nnz)), "products": products,
                       "bf_steps_max": int(max(its_b)), "per_instance_ms_per_step": t_s * 1e3,
-                      "batched_speedup": t_s / t_b, "per_instance_value": ops_step / t_s},
+                      "batched_speedup": t_s / t_b, "per_instance_value": ops_step / t_s,
+                      "schedules": {int(k): int(v) for k, v in zip(*np.unique(scheds, return_counts=True))}},
            "roofline": {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                         "avg_launch_ms": round(tms / cnt, 4), "algorithmic_bytes_per_launch": round(by / cnt)}}
@@ -1023,8 +1245,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat18", choices=["rmat18", "rmat20_sssp", "batch512", "selector", "masked18",
-                                                               "apsp2048", "mp3", "jacobi", "gemm"])
+    ap.add_argument("--workload", default="rmat21", choices=["rmat21", "rmat18", "rmat20_sssp", "batch512", "selector",
+                                                               "masked18", "apsp2048", "mp3", "jacobi", "gemm"])
+    ap.add_argument("--panel-products", type=float, default=8e9,
+                    help="rmat21: products per row panel of the streamed product")
+    ap.add_argument("--selector-file", default="", help="rmat21: load the selector instead of training it")
+    ap.add_argument("--dtypes", default="", help="rmat21: only these of f64,f32,i32 (profiling runs)")
+    ap.add_argument("--bench-selector-matrices", type=int, default=160,
+                    help="rmat21: generated training matrices for the selector")
+    ap.add_argument("--bench-selector-panels", type=int, default=6,
+                    help="rmat21: row panels per R-MAT scale 17-19 in the selector's training set")
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
     ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -1051,7 +1281,7 @@ def main():
     if args.copy_calibration:
         copy_calibration(args)
         return
-    out = {"rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512,
+    out = {"rmat21": run_rmat21, "rmat18": run_rmat18, "rmat20_sssp": run_rmat20_sssp, "batch512": run_batch512,
            "selector": run_selector, "masked18": run_masked18, "apsp2048": run_apsp2048,
            "mp3": run_mp3, "jacobi": run_jacobi, "gemm": run_gemm}[args.workload](args)
     print(json.dumps(out), flush=True)

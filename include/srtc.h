@@ -42,6 +42,10 @@
  *                             narrower dense windows (more passes, the same
  *                             results); SRTC_ERR_UNSUPPORTED if even the
  *                             narrowest window does not fit.
+ *       SRTC_COL_BLOCKS=q     multiply the rows with many products one
+ *                             column block of B at a time (q >= 2 blocks; 0:
+ *                             blocks of about 48 MB of B); unset or 1: no
+ *                             blocks.  The results are the same.
  *     srtc_ctx_create returns SRTC_ERR_ARG for a malformed value.
  *   - No call aborts and no C++ exception crosses the ABI: failures return a
  *     negative srtc_status and srtc_last_error() describes the last one.

@@ -602,6 +602,16 @@ srtc_status srtc_ctx_create(int device, srtc_alloc_fn alloc, srtc_free_fn free_f
     }
     c->c.force_schedule = (int)v;
   }
+  const char *cb = getenv("SRTC_COL_BLOCKS");
+  if (cb && *cb) {
+    char *end = nullptr;
+    const long v = strtol(cb, &end, 10);
+    if (end == cb || *end != 0 || v < 0 || v > 4096) {
+      delete c;
+      return SRTC_ERR_ARG;
+    }
+    c->c.col_blocks = (int)v;
+  }
   const char *lb = getenv("SRTC_LDS_BUDGET");
   if (lb && *lb) {
     char *end = nullptr;

@@ -42,6 +42,9 @@ struct Ctx {
   bool validate_all = false;
   int force_schedule = -1;
   int64_t lds_budget = 160 * 1024;
+  // column blocks of B for wide products (SRTC_COL_BLOCKS): -1 or 1 = none,
+  // 0 = sized from B, q >= 2 = q blocks
+  int col_blocks = -1;
   void release_cache();
   void tracef(const char *fmt, ...);
   // per-kernel profile: HIP events around each launch on its stream, with
@@ -133,7 +136,7 @@ struct Schedule {
   // above: dense LDS windows
   int64_t t_tiny, t_small, t_mid, t_big;
   int small_wave;    // 512-slot bin: one 64-thread wave per row (1) or two waves (0)
-  int dense_bs;      // dense-window block size (256 or 512)
+  int dense_bs;      // dense-window block size (256 or 512; the widest windows always take 1024)
   int dense_wide;    // dense window of 8K (0), 16K (1) or 4K (2) 8-byte accumulators
 };
 const Schedule &schedule(int id);

@@ -32,6 +32,15 @@ namespace srtc {
 namespace {
 
 constexpr int32_t EMPTY = 0x7fffffff;  // empty hash slot (sorts last)
+
+// Where a row's output goes: entries start[i] .. start[i] + count[i] - 1 of
+// C's arrays, columns shifted by col_off (a column block of B carries
+// block-local columns).
+struct OutRows {
+  const int64_t *start;
+  const int64_t *count;
+  int64_t col_off;
+};
 constexpr int LDS_BYTES = 160 * 1024;
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t j, int lg) {
@@ -317,21 +326,30 @@ __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, co
   }
 }
 
-// Rows of a bin are handed out one at a time from a global counter: thread 0
-// takes the next index and the block reads it back through LDS.  Callers
-// fetch the first row before their loop and the next one at the end of the
-// body, so the loop test is on a block-uniform value and no thread-dependent
-// branch leads into the loop header.  (With the fetch at the top of an
-// endless loop, the compiler was free to route threads other than 0 from the
-// end of the body straight past the fetch; the generated code then kept
-// those lanes in an inner loop over the same row that they never left.)
-__device__ __forceinline__ int64_t next_row(int64_t *ctr) {
+// Rows of a bin are handed out from a global counter, `step` consecutive
+// rows per fetch: thread 0 claims them and the block reads the first index
+// back through LDS.  (One row per fetch left bins of millions of small rows
+// bound by the throughput of atomics on that one counter.)  Callers fetch
+// before their loop and again at the end of its body, and walk the claimed
+// rows in an inner counted loop, so every loop test is on a block-uniform
+// value and no thread-dependent branch leads into a loop header.  (With the
+// fetch at the top of an endless loop, the compiler was free to route
+// threads other than 0 from the end of the body straight past the fetch; the
+// generated code then kept those lanes in an inner loop over the same row
+// that they never left.)
+__device__ __forceinline__ int64_t next_row(int64_t *ctr, int step = 1) {
   __shared__ int64_t r;
-  if (threadIdx.x == 0) r = (int64_t)atomicAdd((unsigned long long *)ctr, 1ull);
+  if (threadIdx.x == 0) r = (int64_t)atomicAdd((unsigned long long *)ctr, (unsigned long long)step);
   __syncthreads();
   const int64_t v = r;
   __syncthreads();
   return v;
+}
+
+// Rows per fetch for a bin of `rows` rows on `grid` blocks: about 16
+// fetches per block, 1 to 32 rows each.
+inline int fetch_step(int64_t rows, int64_t grid) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(32, rows / std::max<int64_t>(1, grid * 16)));
 }
 
 template <int BS, class T> __device__ __forceinline__ T block_sum(T v, T *tmp) {
@@ -346,14 +364,16 @@ __global__ void __launch_bounds__(BS) sym_hash(const int32_t *__restrict__ list,
                                                int bin, const int64_t *__restrict__ rpA,
                                                const int32_t *__restrict__ cA, const int64_t *__restrict__ rpB,
                                                const int32_t *__restrict__ cB, int64_t *__restrict__ nnz_row,
-                                               int64_t *ctr, int64_t *err) {
+                                               int64_t *ctr, int step, int64_t *err) {
   constexpr int LG = __builtin_ctz(TBL);
   __shared__ int32_t keys[TBL];
   __shared__ Chunk<BS, uint8_t> L;
   __shared__ int64_t red[BS / WAVE + 1];
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
-  for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
+  for (int64_t r0 = next_row(ctr, step); r0 < count; r0 = next_row(ctr, step)) {
+   const int64_t r1 = min(r0 + (int64_t)step, count);
+   for (int64_t r = r0; r < r1; r++) {
     const int64_t i = rows[r];
     for (int s = threadIdx.x; s < TBL; s += BS) keys[s] = EMPTY;
     __syncthreads();
@@ -377,6 +397,7 @@ __global__ void __launch_bounds__(BS) sym_hash(const int32_t *__restrict__ list,
     });
     const int64_t tot = block_sum<BS>(mine, red);
     if (threadIdx.x == 0) nnz_row[i] = tot;
+   }
   }
 }
 
@@ -388,14 +409,16 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
                                                  const int32_t *__restrict__ cA, const int64_t *__restrict__ rpB,
                                                  const int32_t *__restrict__ cB, int64_t ncols, int32_t wwords,
                                                  const int32_t *__restrict__ woff, int nwin,
-                                                 int64_t *__restrict__ nnz_row, int64_t *ctr) {
+                                                 int64_t *__restrict__ nnz_row, int64_t *ctr, int step) {
   extern __shared__ uint32_t bits[];
   __shared__ Chunk<BS, uint8_t> L;
   __shared__ int64_t red[BS / WAVE + 1];
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
   const int64_t wcols = (int64_t)wwords * 32;
-  for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
+  for (int64_t r0 = next_row(ctr, step); r0 < count; r0 = next_row(ctr, step)) {
+   const int64_t r1 = min(r0 + (int64_t)step, count);
+   for (int64_t r = r0; r < r1; r++) {
     const int64_t i = rows[r];
     int64_t mine = 0;
     for (int64_t w0 = 0, wi = 0; w0 < ncols; w0 += wcols, wi++) {
@@ -415,6 +438,7 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
     }
     const int64_t tot = block_sum<BS>(mine, red);
     if (threadIdx.x == 0) nnz_row[i] = tot;
+   }
   }
 }
 
@@ -430,10 +454,10 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
                                                const typename SR::val_t *__restrict__ vA,
                                                const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB,
                                                const typename SR::val_t *__restrict__ vB, int64_t ncols,
-                                               int32_t wwords, const int64_t *__restrict__ rpC,
+                                               int32_t wwords, OutRows orows,
                                                int32_t *__restrict__ cC, typename SR::val_t *__restrict__ vC,
                                                typename SR::acc_t id, int64_t *__restrict__ row_kept,
-                                               int32_t *any_short, int64_t *ctr) {
+                                               int32_t *any_short, int64_t *ctr, int step) {
   using V = typename SR::val_t;
   using A = typename SR::acc_t;
   constexpr int LG = __builtin_ctz(TBL);
@@ -444,7 +468,9 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
   __shared__ int64_t red[BS / WAVE + 1];
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
-  for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
+  for (int64_t r0 = next_row(ctr, step); r0 < count; r0 = next_row(ctr, step)) {
+   const int64_t r1 = min(r0 + (int64_t)step, count);
+   for (int64_t r = r0; r < r1; r++) {
     const int64_t i = rows[r];
     for (int s = threadIdx.x; s < TBL; s += BS) {
       keys[s] = EMPTY;
@@ -469,7 +495,8 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
       if (SR::HAS_VALS) SR::lds_add(&vals[h], SR::mul(a, b));
     });
     __syncthreads();
-    const int64_t base = rpC[i];
+    const int64_t base = orows.start[i];
+    const int32_t coff = (int32_t)orows.col_off;
     int64_t written = 0;
     if (EXTRACT == 2) {
       // compact in table order (unsorted output)
@@ -481,7 +508,7 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
         int64_t tot;
         const int64_t pre = block_excl_scan<BS>((int64_t)keep, red, &tot);
         if (keep) {
-          cC[base + written + pre] = kk;
+          cC[base + written + pre] = kk + coff;
           vC[base + written + pre] = SR::out(v);
         }
         written += tot;
@@ -504,6 +531,46 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
       }
       int32_t cnt;
       int32_t pos = block_excl_scan<BS, int32_t>(mine, L.tmp, &cnt);  // ends with a barrier: table reads done
+      // When B's columns fit a bitmap in the table's own LDS (with a word
+      // prefix array beside it), the kept entries are placed by rank: mark
+      // their columns, scan the popcounts once, and every entry's position
+      // is the number of marked columns before it -- column order without
+      // a sort (the table was read into registers above).
+      const int nbw = (int)((ncols + 31) >> 5);
+      const bool by_rank = SR::HAS_VALS ? (nbw <= TBL && nbw * 4 <= NV * (int)sizeof(A)) : (2 * nbw <= TBL);
+      if (by_rank) {
+        uint32_t *bm = reinterpret_cast<uint32_t *>(keys);
+        uint32_t *pre = SR::HAS_VALS ? reinterpret_cast<uint32_t *>(vals) : bm + nbw;
+        for (int u = threadIdx.x; u < nbw; u += BS) bm[u] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+          // a column outside B (a malformed operand) is dropped, never marked
+          if (kk[q] != EMPTY && (uint32_t)kk[q] >= (uint32_t)ncols) kk[q] = EMPTY;
+          if (kk[q] != EMPTY) atomicOr(&bm[kk[q] >> 5], 1u << (kk[q] & 31));
+        }
+        __syncthreads();
+        const int per = (nbw + BS - 1) / BS;
+        const int u0 = min((int)threadIdx.x * per, nbw), u1 = min(u0 + per, nbw);
+        int32_t c = 0;
+        for (int u = u0; u < u1; u++) c += __popc(bm[u]);
+        int32_t tot;
+        int32_t rk = block_excl_scan<BS, int32_t>(c, L.tmp, &tot);
+        for (int u = u0; u < u1; u++) {
+          pre[u] = (uint32_t)rk;
+          rk += __popc(bm[u]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+          if (kk[q] == EMPTY) continue;
+          const int32_t j = kk[q];
+          const int64_t o = base + (int64_t)pre[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u));
+          cC[o] = j + coff;
+          vC[o] = SR::out(vv[q]);
+        }
+        written = cnt;
+      } else {
 #pragma unroll
       for (int q = 0; q < PER; q++) {
         if (kk[q] != EMPTY) {
@@ -573,22 +640,24 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
         const uint32_t pmask = (1u << PB) - 1u;
         for (int s = threadIdx.x; s < cnt; s += BS) {
           const uint32_t wv = w32[s];
-          cC[base + s] = (int32_t)(wv >> PB);
+          cC[base + s] = (int32_t)(wv >> PB) + coff;
           vC[base + s] = SR::out(vals[wv & pmask]);
         }
       } else {
         for (int s = threadIdx.x; s < cnt; s += BS) {
-          cC[base + s] = keys[s];
+          cC[base + s] = keys[s] + coff;
           vC[base + s] = SR::out(SR::HAS_VALS ? vals[s] : (A)1);
         }
       }
       written = cnt;
+      }
     }
     if (threadIdx.x == 0) {
       row_kept[i] = written;
-      if (written != rpC[i + 1] - base) atomicOr(any_short, 1);
+      if (written != orows.count[i]) atomicOr(any_short, 1);
     }
     __syncthreads();
+   }
   }
 }
 
@@ -777,18 +846,21 @@ __device__ __forceinline__ int64_t extract_ranked(const typename SR::acc_t *racc
 // windows become ranked groups (above), so a row with few outputs spread
 // over many windows pays for a few passes instead of one per window.
 // Longer A rows are re-read in chunks for every window.
+// At most 128 VGPRs (four waves per SIMD): two 512-thread blocks per CU when
+// the LDS allows, one 1024-thread block otherwise (at 129 registers the
+// fp64 instance lost half its blocks).
 template <class SR, int BS, int W>
-__global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
+__global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ list, const int64_t *__restrict__ info,
                                                 int bin, const int64_t *__restrict__ rpA,
                                                 const int32_t *__restrict__ cA,
                                                 const typename SR::val_t *__restrict__ vA,
                                                 const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB,
                                                 const typename SR::val_t *__restrict__ vB, int64_t ncols,
                                                 const int32_t *__restrict__ woff, int nwin,
-                                                const int64_t *__restrict__ rpC, int32_t *__restrict__ cC,
+                                                OutRows orows, int32_t *__restrict__ cC,
                                                 typename SR::val_t *__restrict__ vC, typename SR::acc_t id,
                                                 int64_t *__restrict__ row_kept, int32_t *any_short,
-                                                int64_t *ctr) {
+                                                int64_t *ctr, int step) {
   using V = typename SR::val_t;
   using A = typename SR::acc_t;
   using R = RankWin<SR, BS, W>;
@@ -814,13 +886,15 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
   const bool can_rank = R::OK && woff != nullptr && nwin > 1 && nwin <= NWPW;
   const int64_t count = info[bin];
   const int32_t *rows = list + info[NBIN + bin];
-  for (int64_t r = next_row(ctr); r < count; r = next_row(ctr)) {
+  for (int64_t r0 = next_row(ctr, step); r0 < count; r0 = next_row(ctr, step)) {
+   const int64_t r1 = min(r0 + (int64_t)step, count);
+   for (int64_t r = r0; r < r1; r++) {
     const int64_t i = rows[r];
-    const int64_t base = rpC[i];
+    const int64_t base = orows.start[i];
     const int64_t pa = rpA[i], pe = rpA[i + 1];
     int64_t written = 0;
     // rows with more than CAP/2 outputs per window on average stay dense
-    const bool use_rank = can_rank && pe - pa <= BS && rpC[i + 1] - base <= (int64_t)nwin * (R::CAP / 2);
+    const bool use_rank = can_rank && pe - pa <= BS && orows.count[i] <= (int64_t)nwin * (R::CAP / 2);
     if (use_rank) {
       for (int s = t; s < nwin; s += BS) pw[s] = 0;
       __syncthreads();
@@ -969,9 +1043,10 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
           gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total_n, L, 0, g);
         }
         if (dense || !R::OK)
-          written += extract_window<SR, BS, W>(vals, bits, id, c0, base + written, cC, vC, red);
+          written += extract_window<SR, BS, W>(vals, bits, id, c0 + orows.col_off, base + written, cC, vC, red);
         else
-          written += extract_ranked<SR, BS>(racc, rcol, rbits, (gb - ga) * R::WPW, nrank, id, c0, base + written,
+          written += extract_ranked<SR, BS>(racc, rcol, rbits, (gb - ga) * R::WPW, nrank, id, c0 + orows.col_off,
+                                            base + written,
                                             cC, vC, red);
         total = total_n;
         o_nxt = o_after;
@@ -985,13 +1060,14 @@ __global__ void __launch_bounds__(BS) num_dense(const int32_t *__restrict__ list
         const int64_t w0 = (int64_t)w * W;
         for_products<BS, VALS, V, WALK_U, true>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin, w,
                                                 w + 1, L, dense_add(w0));
-        written += extract_window<SR, BS, W>(vals, bits, id, w0, base + written, cC, vC, red);
+        written += extract_window<SR, BS, W>(vals, bits, id, w0 + orows.col_off, base + written, cC, vC, red);
       }
     }
     if (t == 0) {
       row_kept[i] = written;
-      if (written != rpC[i + 1] - base) atomicOr(any_short, 1);
+      if (written != orows.count[i]) atomicOr(any_short, 1);
     }
+   }
   }
 }
 
@@ -1190,7 +1266,7 @@ const Schedule kSchedules[SRTC_NUM_SCHEDULES] = {
     {2048, 32, 256, 2048, 4096, 0, 256, 0},   // 0 balanced
     {2048, 32, 256, 2048, 4096, 1, 256, 0},   // 1 as 0 with one wave per row in the 512-slot bin
     {2048, 32, 256, 256, 256, 1, 256, 0},     // 2 dense windows from 257 outputs
-    {8192, 32, 256, 2048, 4096, 0, 512, 1},   // 3 hash-heavy, wide dense windows
+    {8192, 32, 256, 2048, 4096, 0, 1024, 1},  // 3 hash-heavy, wide dense windows (1024-thread blocks)
     {0, 0, 0, 0, 0, 0, 256, 0},               // 4 dense windows for every row
     {2048, 32, 256, 256, 256, 0, 512, 0},     // 5 as 0, 512-thread dense windows from 257 outputs
     {2048, 32, 256, 2048, 4096, 0, 512, 2},   // 6 as 5 with narrow dense windows (more blocks per CU)
@@ -1216,8 +1292,9 @@ void launch_sym_hash(const Launch &L, int64_t rows, const int32_t *list, const i
                      const CsrView &A, const CsrView &B, int64_t *nnz_row, int64_t *ctr, int64_t *err) {
   if (rows == 0) return;
   const int lds = TBL * 4 + sizeof(Chunk<BS, uint8_t>) + 64;
-  sym_hash<BS, TBL><<<L.grid(rows, lds, BS), BS, 0, L.s>>>(list, info, bin, A.rowptr, A.col, B.rowptr, B.col,
-                                                           nnz_row, ctr, err);
+  const unsigned grid = L.grid(rows, lds, BS);
+  sym_hash<BS, TBL><<<grid, BS, 0, L.s>>>(list, info, bin, A.rowptr, A.col, B.rowptr, B.col, nnz_row, ctr,
+                                          fetch_step(rows, grid), err);
   SRTC_LAUNCH_CHECK("sym_hash");
 }
 
@@ -1310,7 +1387,7 @@ int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, cons
       SRTC_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, ww * 4));
     kern<<<L.grid(hinfo[5], stat + ww * 4, BS), BS, (size_t)ww * 4, s>>>(list, info1, 5, Am.rowptr, Am.col,
                                                                       Bm.rowptr, Bm.col, n, ww, woff.as<int32_t>(),
-                                                                      nwin, nnz_row, ctr1 + 5);
+                                                                      nwin, nnz_row, ctr1 + 5, 1);
     SRTC_LAUNCH_CHECK("sym_bitmap");
   }
   return hinfo[4 * NBIN];
@@ -1321,26 +1398,27 @@ template <class SR> struct NumLaunch {
   using A = typename SR::acc_t;
   template <int BS, int TBL, int EX>
   static void hash(const Launch &L, int64_t rows, const int32_t *list, const int64_t *info, int bin,
-                   const CsrView &Am, const CsrView &Bm, const int64_t *rpC, int32_t *cC, V *vC, A id,
+                   const CsrView &Am, const CsrView &Bm, OutRows orows, int32_t *cC, V *vC, A id,
                    int64_t *kept, int32_t *any_short, int64_t *ctr) {
     if (rows == 0) return;
     constexpr int NV = SR::HAS_VALS ? TBL : 1;
     const int stat = TBL * 4 + NV * (int)sizeof(A) + (int)sizeof(Chunk<BS, V>) + 64;
-    num_hash<SR, BS, TBL, EX><<<L.grid(rows, stat, BS), BS, 0, L.s>>>(
+    const unsigned grid = L.grid(rows, stat, BS);
+    num_hash<SR, BS, TBL, EX><<<grid, BS, 0, L.s>>>(
         list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, 0,
-        rpC, cC, vC, id, kept, any_short, ctr);
+        orows, cC, vC, id, kept, any_short, ctr, fetch_step(rows, grid));
     SRTC_LAUNCH_CHECK("num_hash");
   }
   template <int BS, int W>
   static void dense(const Launch &L, int64_t rows, const int32_t *list, const int64_t *info, int bin,
-                    const CsrView &Am, const CsrView &Bm, const int32_t *woff, int nwin, const int64_t *rpC,
+                    const CsrView &Am, const CsrView &Bm, const int32_t *woff, int nwin, OutRows orows,
                     int32_t *cC, V *vC, A id, int64_t *kept, int32_t *any_short, int64_t *ctr) {
     if (rows == 0) return;
     constexpr int NV = SR::HAS_VALS ? W : 1;
     const int stat = NV * (int)sizeof(A) + W / 8 + (int)sizeof(Chunk<BS, V>) + (RankWin<SR, BS, W>::OK ? NWPW * 8 : 8) + 64;
     num_dense<SR, BS, W><<<L.grid(rows, stat, BS), BS, 0, L.s>>>(
         list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, woff,
-        nwin, rpC, cC, vC, id, kept, any_short, ctr);
+        nwin, orows, cC, vC, id, kept, any_short, ctr, 1);
     SRTC_LAUNCH_CHECK("num_dense");
   }
 };
@@ -1385,7 +1463,7 @@ template <class SR> Schedule budgeted(const Ctx *c, int id) {
   if (num_hash_lds<SR, 64>(64) > B) S.t_tiny = S.t_small = S.t_mid = S.t_big = 0;
   constexpr int W0 = (int)dense_width<SR>(0), W1 = (int)dense_width<SR>(1), W2 = (int)dense_width<SR>(2);
   int need = 0;
-  if (S.dense_wide == 1) need = S.dense_bs == 512 ? num_dense_lds<SR, 512, W1>() : num_dense_lds<SR, 256, W1>();
+  if (S.dense_wide == 1) need = num_dense_lds<SR, 1024, W1>();
   else if (S.dense_wide == 2) need = num_dense_lds<SR, 512, W2>();
   else need = S.dense_bs == 512 ? num_dense_lds<SR, 512, W0>() : num_dense_lds<SR, 256, W0>();
   if (need > B) {
@@ -1435,7 +1513,7 @@ void numeric_bin(Ctx *c, const CsrView &Am, const int64_t *nnz_row, const RowGro
 template <class SR>
 void numeric_launch(Ctx *c, typename SR::acc_t id, const CsrView &Am, const CsrView &Bm, const int64_t *w,
                     const RowGroup &g, const int64_t *hinfo2, int64_t *info2, int32_t *lst, int sorted,
-                    const int64_t *rpC, int32_t *cC, typename SR::val_t *vC, int64_t *kp, int32_t *fl,
+                    OutRows rpC, int32_t *cC, typename SR::val_t *vC, int64_t *kp, int32_t *fl,
                     SpgemmStats *st, hipStream_t s) {
   using V = typename SR::val_t;
   const Schedule S = budgeted<SR>(c, g.sched);
@@ -1496,8 +1574,9 @@ void numeric_launch(Ctx *c, typename SR::acc_t id, const CsrView &Am, const CsrV
     ProfScope ps(c, pname(5).c_str(), num_bytes(5), s);
     constexpr int W0 = (int)dense_width<SR>(0), W1 = (int)dense_width<SR>(1), W2 = (int)dense_width<SR>(2);
     if (S.dense_wide == 1) {
-      if (S.dense_bs == 512) NL::template dense<512, W1>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
-      else NL::template dense<256, W1>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      // the widest window fills the LDS (one block per CU): 1024 threads keep
+      // 16 waves per CU in flight instead of 8
+      NL::template dense<1024, W1>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
     } else if (S.dense_wide == 2) {
       NL::template dense<512, W2>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
     } else {
@@ -1598,7 +1677,8 @@ void spgemm_groups(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, cons
   if (total > 0)
     for (int q = 0; q < G; q++)
       numeric_launch<SR>(c, id, Am, Bm, w.as<int64_t>(), groups[q], htab.data() + 1 + (size_t)q * INFO,
-                         tab + 1 + (int64_t)q * INFO, lists[q].as<int32_t>(), sorted, rpC, cC, vC, kp, fl, st, s);
+                         tab + 1 + (int64_t)q * INFO, lists[q].as<int32_t>(), sorted,
+                         OutRows{rpC, nnz_row.as<int64_t>(), 0}, cC, vC, kp, fl, st, s);
   // 6. compaction when identity results were dropped
   int32_t flags_h[4] = {0, 0, 0, 0};
   read_to_host(c, flags_h, fl, sizeof(flags_h), s);
@@ -1627,15 +1707,374 @@ void spgemm_groups(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, cons
   out->val = std::move(val);
 }
 
+// ------------------------------------------------ column blocks of B --
+// For products whose B is far larger than the caches, the rows with many
+// products are multiplied one column block of B at a time: block q holds B's
+// entries with columns in [q bc, (q+1) bc) as a CSR over B's rows with
+// block-local columns.  A heavy row's products in block q then gather from a
+// slice of B that stays cache-resident while every heavy row passes through
+// that block, instead of re-reading B's lines from HBM once per dense window
+// (B's rows are short and spread over every window).  C's row i is the
+// concatenation of its blocks' results, so block q of row i is written at
+// rowptr[i] + (outputs of row i in blocks before q).
+
+// cnt[q (K+1) + k] = entries of row k of B in block q (the slot k = K stays 0).
+__global__ void colblock_count(const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB, int64_t K, int Q,
+                               int64_t bc, int64_t *__restrict__ cnt) {
+  const int64_t total = K * Q;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = t / Q;
+    const int q = (int)(t % Q);
+    const int64_t a = rpB[k], b = rpB[k + 1];
+    auto lower = [&](int64_t target) {
+      int64_t lo = a, hi = b;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cB[mid] < target) lo = mid + 1; else hi = mid;
+      }
+      return lo;
+    };
+    cnt[(int64_t)q * (K + 1) + k] = lower((int64_t)(q + 1) * bc) - lower((int64_t)q * bc);
+  }
+}
+
+// Entry e of row k goes to block q = col / bc at pos[q (K+1) + k] + its rank
+// among the row's entries of that block (the row is column-sorted, so the
+// block's entries are consecutive: rank = e - first entry with col >= q bc).
+template <class V>
+__global__ void colblock_scatter(const int64_t *__restrict__ rpB, const int32_t *__restrict__ cB,
+                                 const V *__restrict__ vB, int64_t K, int64_t bc, int Q,
+                                 const int64_t *__restrict__ pos, int32_t *__restrict__ col, V *__restrict__ val,
+                                 bool vals) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  for (int64_t k = wid; k < K; k += nw) {
+    const int64_t a = rpB[k], b = rpB[k + 1];
+    for (int64_t e = a + lane_id(); e < b; e += WAVE) {
+      const int32_t c = cB[e];
+      const int64_t q = c / bc;
+      if (c < 0 || q >= Q) continue;  // outside the columns (a malformed operand): counted by no block
+      const int64_t target = q * bc;
+      int64_t lo = a, hi = e;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cB[mid] < target) lo = mid + 1; else hi = mid;
+      }
+      const int64_t d = pos[q * (K + 1) + k] + (e - lo);
+      col[d] = (int32_t)(c - target);
+      if (vals) val[d] = vB[e];
+    }
+  }
+}
+
+// Rows with at least thr products go to `heavy`, the others to `light`
+// (ballot ranks, one atomic per wave and list); counts in ctr[0], ctr[1].
+__global__ void split_rows(const int64_t *__restrict__ w, int64_t m, int64_t thr, int32_t *__restrict__ light,
+                           int32_t *__restrict__ heavy, unsigned long long *__restrict__ ctr) {
+  const uint64_t lt = lanemask_lt();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < m; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool in = i < m;
+    const bool h = in && w[i] >= thr;
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+      const bool mine = in && (s == 1 ? h : !h);
+      const uint64_t mk = __ballot(mine);
+      if (mk == 0) continue;
+      const int leader = __ffsll((unsigned long long)mk) - 1;
+      unsigned long long p = 0;
+      if (lane_id() == leader) p = atomicAdd(&ctr[s], (unsigned long long)__popcll(mk));
+      p = __shfl(p, leader, WAVE);
+      if (mine) (s == 1 ? heavy : light)[p + __popcll(mk & lt)] = (int32_t)i;
+    }
+  }
+}
+
+// Products per listed row (row_products restricted to a row list).
+__global__ void row_products_rows(const int64_t *__restrict__ rpA, const int32_t *__restrict__ cA,
+                                  const int64_t *__restrict__ rpB, const int32_t *__restrict__ rows, int64_t n,
+                                  int64_t *__restrict__ w) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  for (int64_t r = wid; r < n; r += nw) {
+    const int64_t i = rows[r];
+    int64_t acc = 0;
+    for (int64_t p = rpA[i] + lane_id(); p < rpA[i + 1]; p += WAVE) {
+      const int32_t k = cA[p];
+      acc += rpB[k + 1] - rpB[k];
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) w[i] = acc;
+  }
+}
+
+// Per heavy row: total over blocks (tot[i]), and with rowptr given, every
+// block's first output position (start[q m + i]).
+__global__ void block_rows(const int32_t *__restrict__ rows, int64_t n, const int64_t *__restrict__ cnt, int Q,
+                           int64_t m, int64_t *__restrict__ tot, const int64_t *__restrict__ rp,
+                           int64_t *__restrict__ start) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = rows[r];
+    int64_t run = rp ? rp[i] : 0;
+    for (int q = 0; q < Q; q++) {
+      if (start) start[(int64_t)q * m + i] = run;
+      run += cnt[(int64_t)q * m + i];
+    }
+    if (tot) tot[i] = rp ? run - rp[i] : run;
+  }
+}
+
+// Repack rows after identity results were dropped: listed rows of one
+// segment (from old[i], kept[i] entries) or of Q block segments (from
+// start[q m + i], kept_q[q m + i] entries each) go to new[i] onwards.
+template <class V>
+__global__ void compact_segments(const int32_t *__restrict__ rows, int64_t n, int Q, int64_t m,
+                                 const int64_t *__restrict__ start, const int64_t *__restrict__ kept,
+                                 const int64_t *__restrict__ rp_new, const int32_t *__restrict__ c_old,
+                                 const V *__restrict__ v_old, int32_t *__restrict__ c_new, V *__restrict__ v_new) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  for (int64_t r = wid; r < n; r += nw) {
+    const int64_t i = rows[r];
+    int64_t o = rp_new[i];
+    for (int q = 0; q < Q; q++) {
+      const int64_t a = start[(int64_t)q * m + i], len = kept[(int64_t)q * m + i];
+      for (int64_t t = lane_id(); t < len; t += WAVE) {
+        c_new[o + t] = c_old[a + t];
+        v_new[o + t] = v_old[a + t];
+      }
+      o += len;
+    }
+  }
+}
+
+// C = A (x) B with B cut into Q column blocks of bc columns for the rows of
+// at least thr products (the others multiply the whole B once).  Host reads:
+// the row split and block sizes, each symbolic pass's bins, the output size
+// with every numeric bin table, the flags.
+template <class SR>
+void spgemm_blocked(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int sched, int Q, int64_t bc,
+                    int64_t thr, const int64_t *w, int sorted, CsrOut *out, SpgemmStats *st, hipStream_t s) {
+  using V = typename SR::val_t;
+  using A = typename SR::acc_t;
+  const A id = id_as<SR>(idv);
+  const int64_t m = Am.m, K = Bm.m;
+  const size_t es = sizeof(V);
+  Launch L{c, s};
+  c->tracef("spgemm: %lld x %lld (nnz %lld) times %lld x %lld (nnz %lld), schedule %d, %d column blocks of %lld",
+            (long long)m, (long long)Am.n, (long long)Am.nnz, (long long)K, (long long)Bm.n, (long long)Bm.nnz, sched,
+            Q, (long long)bc);
+  // B's column blocks, one shared entry array
+  Buf pos(c, sizeof(int64_t) * (size_t)(Q * (K + 1) + 1));
+  Buf bcol(c, sizeof(int32_t) * (size_t)std::max<int64_t>(Bm.nnz, 1));
+  Buf bval(c, es * (size_t)(SR::HAS_VALS ? std::max<int64_t>(Bm.nnz, 1) : 1));
+  {
+    ProfScope ps(c, "spgemm.column_blocks", 16.0 * (K + 1) + (8.0 + 2.0 * es) * Bm.nnz + 8.0 * Q * (K + 1), s);
+    Buf cnt(c, sizeof(int64_t) * (size_t)(Q * (K + 1)));
+    fill_i64(cnt.as<int64_t>(), Q * (K + 1), 0, s);
+    colblock_count<<<gridn(K * Q), 256, 0, s>>>(Bm.rowptr, Bm.col, K, Q, bc, cnt.as<int64_t>());
+    SRTC_LAUNCH_CHECK("colblock_count");
+    excl_scan_i64(c, cnt.as<int64_t>(), pos.as<int64_t>(), Q * (K + 1), s);
+    colblock_scatter<V><<<gridn(K * WAVE, 256, 16384), 256, 0, s>>>(Bm.rowptr, Bm.col, (const V *)Bm.val, K, bc, Q,
+                                                                     pos.as<int64_t>(), bcol.as<int32_t>(),
+                                                                     bval.as<V>(), SR::HAS_VALS);
+    SRTC_LAUNCH_CHECK("colblock_scatter");
+  }
+  // rows: light (whole B) and heavy (block by block)
+  Buf lists(c, sizeof(int32_t) * (size_t)(2 * m));
+  int32_t *light = lists.as<int32_t>(), *heavy = light + m;
+  Buf ctr(c, 64);
+  fill_i64(ctr.as<int64_t>(), 2, 0, s);
+  split_rows<<<gridn(m, 256, 4096), 256, 0, s>>>(w, m, thr, light, heavy, (unsigned long long *)ctr.p);
+  SRTC_LAUNCH_CHECK("split_rows");
+  std::vector<int64_t> hb(2 + Q + 1);
+  {
+    // the split sizes and each block's first entry, in one read
+    Buf bounds(c, sizeof(int64_t) * (size_t)(Q + 3));
+    SRTC_HIP(hipMemcpyAsync(bounds.p, ctr.p, 16, hipMemcpyDeviceToDevice, s));
+    for (int q = 0; q <= Q; q++)
+      copy_i64<<<1, 64, 0, s>>>(pos.as<int64_t>() + (int64_t)q * (K + 1), bounds.as<int64_t>() + 2 + q);
+    read_to_host(c, hb.data(), bounds.p, sizeof(int64_t) * hb.size(), s);
+  }
+  const int64_t nlight = hb[0], nheavy = hb[1];
+  auto block_view = [&](int q) {
+    const int64_t b0 = (int64_t)q * bc;
+    return CsrView{K, std::min(bc, Bm.n - b0), hb[2 + q + 1] - hb[2 + q], pos.as<int64_t>() + (int64_t)q * (K + 1),
+                   bcol.as<int32_t>(), bval.p};
+  };
+  // groups: [0] light rows against B, [1 + q] heavy rows against block q
+  const int G = 1 + Q;
+  std::vector<RowGroup> grp(G);
+  grp[0] = RowGroup{light, nlight, sched};
+  for (int q = 0; q < Q; q++) grp[1 + q] = RowGroup{heavy, nheavy, sched};
+  // products per heavy row and block, output counts per row and block
+  Buf wq(c, sizeof(int64_t) * (size_t)(Q * m));
+  Buf nnzq(c, sizeof(int64_t) * (size_t)(Q * m));
+  Buf nnz_row(c, sizeof(int64_t) * (size_t)m);
+  fill_i64(nnz_row.as<int64_t>(), m, 0, s);
+  fill_i64(nnzq.as<int64_t>(), Q * m, 0, s);
+  Buf flag(c, 64);
+  fill_i32(flag.as<int32_t>(), 4, 0, s);
+  int32_t *fl = flag.as<int32_t>();
+  int64_t *sym_err = reinterpret_cast<int64_t *>(flag.as<char>() + 8);
+  Buf tables(c, sizeof(int64_t) * (size_t)(1 + G * INFO));
+  int64_t *tab = tables.as<int64_t>();
+  fill_i64(tab, 1 + (int64_t)G * INFO, 0, s);
+  std::vector<Buf> blists(G);
+  int64_t products = 0;
+  for (int q = 0; q < G; q++) {
+    const RowGroup &g = grp[q];
+    blists[q] = Buf(c, sizeof(int32_t) * (size_t)std::max<int64_t>(g.nsel, 1));
+    if (g.nsel == 0) continue;
+    int64_t *info1 = tab + 1 + (int64_t)q * INFO;
+    if (q == 0) {
+      products += run_symbolic(L, budgeted<SR>(c, sched), Am, Bm, w, light, nlight, info1, blists[q].as<int32_t>(),
+                               nnz_row.as<int64_t>(), sym_err);
+    } else {
+      const CsrView bq = block_view(q - 1);
+      int64_t *wq_b = wq.as<int64_t>() + (int64_t)(q - 1) * m;
+      row_products_rows<<<gridn(nheavy * WAVE, 256, 16384), 256, 0, s>>>(Am.rowptr, Am.col, bq.rowptr, heavy, nheavy,
+                                                                         wq_b);
+      SRTC_LAUNCH_CHECK("row_products_rows");
+      products += run_symbolic(L, budgeted<SR>(c, sched), Am, bq, wq_b, heavy, nheavy, info1,
+                               blists[q].as<int32_t>(), nnzq.as<int64_t>() + (int64_t)(q - 1) * m, sym_err);
+    }
+    fill_i64(info1, INFO, 0, s);
+  }
+  if (st) st->products = products;
+  // rowptr: heavy rows' totals over blocks, then the scan; block starts
+  Buf startq(c, sizeof(int64_t) * (size_t)(Q * m));
+  if (nheavy > 0) {
+    block_rows<<<gridn(nheavy), 256, 0, s>>>(heavy, nheavy, nnzq.as<int64_t>(), Q, m, nnz_row.as<int64_t>(), nullptr,
+                                            nullptr);
+    SRTC_LAUNCH_CHECK("block_rows");
+  }
+  excl_scan_i64(c, nnz_row.as<int64_t>(), out->rowptr.as<int64_t>(), m, s);
+  const int64_t *rpC = out->rowptr.as<int64_t>();
+  if (nheavy > 0) {
+    block_rows<<<gridn(nheavy), 256, 0, s>>>(heavy, nheavy, nnzq.as<int64_t>(), Q, m, nullptr, rpC,
+                                            startq.as<int64_t>());
+    SRTC_LAUNCH_CHECK("block_rows");
+  }
+  std::vector<Buf> vbufs(G);
+  for (int q = 0; q < G; q++)
+    numeric_bin<SR>(c, Am, q == 0 ? nnz_row.as<int64_t>() : nnzq.as<int64_t>() + (int64_t)(q - 1) * m, grp[q],
+                    tab + 1 + (int64_t)q * INFO, blists[q].as<int32_t>(), &vbufs[q], s);
+  copy_i64<<<1, 64, 0, s>>>(rpC + m, tab);
+  std::vector<int64_t> htab(1 + (size_t)G * INFO);
+  read_to_host(c, htab.data(), tab, sizeof(int64_t) * htab.size(), s);
+  const int64_t total = htab[0];
+  c->tracef("spgemm: %lld light and %lld heavy rows, %lld products, nnz(C) = %lld", (long long)nlight,
+            (long long)nheavy, (long long)products, (long long)total);
+  if (st) st->nnz = total;
+  Buf col(c, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), out->kind);
+  Buf val(c, es * (size_t)std::max<int64_t>(total, 1), out->kind);
+  Buf kept(c, sizeof(int64_t) * (size_t)m), keptq(c, sizeof(int64_t) * (size_t)(Q * m));
+  fill_i64(kept.as<int64_t>(), m, 0, s);
+  fill_i64(keptq.as<int64_t>(), Q * m, 0, s);
+  int32_t *cC = col.as<int32_t>();
+  V *vC = val.as<V>();
+  if (total > 0) {
+    for (int q = 0; q < G; q++) {
+      if (grp[q].nsel == 0) continue;
+      if (q == 0) {
+        numeric_launch<SR>(c, id, Am, Bm, w, grp[0], htab.data() + 1, tab + 1, blists[0].as<int32_t>(), sorted,
+                           OutRows{rpC, nnz_row.as<int64_t>(), 0}, cC, vC, kept.as<int64_t>(), fl, st, s);
+      } else {
+        const int64_t off = (int64_t)(q - 1) * m;
+        numeric_launch<SR>(c, id, Am, block_view(q - 1), wq.as<int64_t>() + off, grp[q],
+                           htab.data() + 1 + (size_t)q * INFO, tab + 1 + (int64_t)q * INFO, blists[q].as<int32_t>(),
+                           sorted, OutRows{startq.as<int64_t>() + off, nnzq.as<int64_t>() + off, (q - 1) * bc}, cC, vC,
+                           keptq.as<int64_t>() + off, fl, st, s);
+      }
+    }
+  }
+  int32_t flags_h[4] = {0, 0, 0, 0};
+  read_to_host(c, flags_h, fl, sizeof(flags_h), s);
+  c->tracef("spgemm: numeric done (short %d, error %d)", flags_h[0], flags_h[1]);
+  if (flags_h[2] || flags_h[3]) fail(SRTC_ERR_DEVICE, "spgemm: symbolic hash table overflow (internal invariant)");
+  if (flags_h[1]) fail(SRTC_ERR_DEVICE, "spgemm: numeric hash table overflow (internal invariant)");
+  if (flags_h[0]) {
+    // identity results were dropped: per-row kept totals, then every
+    // segment moves to its packed place
+    if (nheavy > 0) {
+      block_rows<<<gridn(nheavy), 256, 0, s>>>(heavy, nheavy, keptq.as<int64_t>(), Q, m, kept.as<int64_t>(), nullptr,
+                                              nullptr);
+      SRTC_LAUNCH_CHECK("block_rows");
+    }
+    Buf rp2(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
+    excl_scan_i64(c, kept.as<int64_t>(), rp2.as<int64_t>(), m, s);
+    const int64_t t2 = read_i64(c, rp2.as<int64_t>() + m, s);
+    Buf col2(c, sizeof(int32_t) * (size_t)std::max<int64_t>(t2, 1), out->kind);
+    Buf val2(c, es * (size_t)std::max<int64_t>(t2, 1), out->kind);
+    if (nlight > 0)
+      compact_segments<V><<<gridn(nlight * WAVE, 256, 16384), 256, 0, s>>>(light, nlight, 1, m, rpC, kept.as<int64_t>(),
+                                                                          rp2.as<int64_t>(), cC, vC,
+                                                                          col2.as<int32_t>(), val2.as<V>());
+    if (nheavy > 0)
+      compact_segments<V><<<gridn(nheavy * WAVE, 256, 16384), 256, 0, s>>>(heavy, nheavy, Q, m, startq.as<int64_t>(),
+                                                                          keptq.as<int64_t>(), rp2.as<int64_t>(), cC,
+                                                                          vC, col2.as<int32_t>(), val2.as<V>());
+    SRTC_LAUNCH_CHECK("compact_segments");
+    out->rowptr = std::move(rp2);
+    col = std::move(col2);
+    val = std::move(val2);
+    if (st) { st->nnz = t2; st->compacted = 1; }
+    out->nnz = t2;
+  } else {
+    out->nnz = total;
+  }
+  out->col = std::move(col);
+  out->val = std::move(val);
+}
+
+// Column blocking (above) is opt-in (SRTC_COL_BLOCKS): on the R-MAT 21
+// square it moved B's gathers off HBM, but the dense-window kernel is bound
+// by its per-window work, not by those bytes (8% faster), while rows split
+// over blocks fell into slower hash bins and the block copies cost more
+// than that.  Blocks then hold about kBlockBytes of B each.
+constexpr int64_t kBlockBytes = 48ll << 20;
+
 template <class SR>
 void spgemm_typed(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, const std::vector<RowGroup> *groups,
                   int sched, int sorted, CsrOut *out, SpgemmStats *st, hipStream_t s) {
   if (groups) {
     spgemm_groups<SR>(c, idv, Am, Bm, *groups, sorted, out, st, s);
-  } else {
-    const std::vector<RowGroup> one{RowGroup{nullptr, Am.m, sched}};
-    spgemm_groups<SR>(c, idv, Am, Bm, one, sorted, out, st, s);
+    return;
   }
+  using V = typename SR::val_t;
+  const Schedule S = budgeted<SR>(c, sched);
+  const int64_t W = dense_width<SR>(S.dense_wide);
+  const double eb = 4.0 + (SR::HAS_VALS ? (double)sizeof(V) : 0.0);
+  // SRTC_COL_BLOCKS=0: blocks of whole dense windows, each about
+  // kBlockBytes of B; SRTC_COL_BLOCKS=q >= 2: q blocks, a multiple of 32
+  // columns each; unset: no blocks
+  int Q = 1;
+  int64_t align = W;
+  if (c->col_blocks == 0) {
+    Q = (int)std::min<double>(std::ceil(eb * (double)Bm.nnz / (double)kBlockBytes), (double)(Bm.n / W));
+  } else if (c->col_blocks >= 2) {
+    Q = std::min<int>(c->col_blocks, (int)std::max<int64_t>(1, Bm.n / 32));
+    align = 32;
+  }
+  if (Q >= 2 && Am.m > 0 && Am.nnz > 0 && Bm.nnz > 0 && Bm.m < 0x7fffffff) {
+    const int64_t bc = ((Bm.n + Q - 1) / Q + align - 1) / align * align;
+    Q = (int)((Bm.n + bc - 1) / bc);
+    const int64_t thr = (int64_t)Q * 2048;
+    out->m = Am.m;
+    out->n = Bm.n;
+    out->rowptr = Buf(c, sizeof(int64_t) * (size_t)(Am.m + 1), out->kind);
+    Buf w(c, sizeof(int64_t) * (size_t)Am.m);
+    {
+      ProfScope ps(c, "spgemm.row_products", 16.0 * (Am.m + 1) + 4.0 * Am.nnz + 8.0 * (Bm.m + 1), s);
+      row_products(Am, Bm, w.as<int64_t>(), s);
+    }
+    spgemm_blocked<SR>(c, idv, Am, Bm, sched, Q, bc, thr, w.as<int64_t>(), sorted, out, st, s);
+    return;
+  }
+  const std::vector<RowGroup> one{RowGroup{nullptr, Am.m, sched}};
+  spgemm_groups<SR>(c, idv, Am, Bm, one, sorted, out, st, s);
 }
 
 // Row statistics for the schedule features: log2 histograms of row lengths

@@ -123,16 +123,22 @@ def test_adam_step_matches_oracle():
     # the kernel's hyperparameters are fp32 values: the oracle takes the same
     # numbers (0.999 itself is not representable in fp32)
     lr, b1, b2, eps = (float(np.float32(x)) for x in (3e-3, 0.9, 0.999, 1e-8))
+    u = 2.0 ** -24
+    mag = np.zeros(npar)  # the first-moment recurrence on magnitudes
     for t in range(1, 6):
         g = rng.normal(scale=10.0 ** rng.uniform(-3, 1), size=npar).astype(np.float32)
         g[::7] = 0.0
         ctx.mlp_adam_step(P, torch.as_tensor(g, device="cuda"), M1, M2, t, lr, b1, b2, eps)
         rp, rm, rv = omlp.adam_step(rp, g.astype(np.float64), rm, rv, t, lr, b1, b2, eps)
+        mag = b1 * mag + (1 - b1) * np.abs(g.astype(np.float64))
         gp, gm, gv = (x.cpu().numpy().astype(np.float64) for x in (P, M1, M2))
-        # fp32 arithmetic: a few roundings per update on |p| and on the step lr
-        assert np.all(np.abs(gp - rp) <= 1e-5 * np.abs(rp) + 4e-6 * lr * t), t
-        assert np.all(np.abs(gm - rm) <= 1e-5 * np.abs(rm) + 1e-30)
-        assert np.all(np.abs(gv - rv) <= 1e-5 * np.abs(rv) + 1e-30)
+        # fp32 arithmetic, a few roundings per step: the first moment can
+        # cancel, so its error is bounded by the recurrence on magnitudes;
+        # the second moment has no cancellation; a parameter moves by at most
+        # about lr per step
+        assert np.all(np.abs(gm - rm) <= 3 * u * t * mag), t
+        assert np.all(np.abs(gv - rv) <= 3 * u * t * np.abs(rv)), t
+        assert np.all(np.abs(gp - rp) <= 4 * u * np.abs(rp) + 1e-5 * lr * t), t
 
 
 def test_features_match_oracle():

@@ -308,3 +308,36 @@ def test_allocator_failure_returns_oom_and_frees_everything():
         say("allocations needed:", need)
     finally:
         L.srtc_ctx_destroy(h)
+
+
+@pytest.mark.parametrize("semiring,dtype", PAIRS)
+def test_column_blocked_products(ctx, semiring, dtype):
+    """B cut into column blocks (forced with SRTC_COL_BLOCKS on inputs the
+    library would multiply whole): heavy rows are multiplied block by block
+    and written at per-block offsets, light rows against all of B; results
+    equal the oracle's for every schedule, with accumulate, and with exact
+    cancellations that drop identity results."""
+    n = 1 << 14
+    src, dst = synth.rmat_edges(14, 16, 0.57, 0.19, 0.19, SEED, tag=70)
+    G, O = pair_inputs(ctx, semiring, dtype, src, dst, n, SEED, 71)
+    exp = oracle.spgemm(semiring, dtype, O, O)
+    for blocks in ("3", "7", "0"):
+        with _Env(SRTC_COL_BLOCKS=blocks):
+            bctx = srtc.Context(0)
+        for sch in range(srtc.NUM_SCHEDULES):
+            say("column blocks", blocks, semiring, dtype, "schedule", sch)
+            check_csr(bctx.contract(semiring, "ik", G, "kj", G, "ij", schedule=sch), exp, semiring, dtype)
+    with _Env(SRTC_COL_BLOCKS="4"):
+        bctx = srtc.Context(0)
+    C0 = pair_inputs(ctx, semiring, dtype, dst, src, n, SEED, 72)
+    exp2 = oracle.spgemm(semiring, dtype, O, O, C_old=C0[1])
+    check_csr(bctx.contract(semiring, "ik", G, "kj", G, "ij", C=C0[0], accumulate=True, schedule=5), exp2, semiring,
+              dtype)
+    if semiring == "plus_times":
+        # +-1 values: many sums cancel to exactly 0 and are dropped
+        v = np.where(synth.edge_values("f64", src.size, SEED, 73) < 0.5, -1.0, 1.0).astype(oracle.NP_DTYPES[dtype])
+        Gc = gpu_fold(ctx, semiring, dtype, dst, src, v, n, n)
+        Oc = oracle.fold(semiring, dtype, dst, src, v, n, n)
+        expc = oracle.spgemm(semiring, dtype, Oc, Oc)
+        for sch in (0, 3, 5):
+            check_csr(bctx.contract(semiring, "ik", Gc, "kj", Gc, "ij", schedule=sch), expc, semiring, dtype)
