@@ -77,7 +77,9 @@ typedef enum srtc_status {
   SRTC_ERR_OOM = -7,           /* the allocator returned NULL */
   SRTC_ERR_NOT_CONVERGED = -8, /* fixpoint still changing after max_iters */
   SRTC_ERR_UNSUPPORTED = -9,   /* well-formed request outside this library */
-  SRTC_ERR_DEVICE = -10        /* HIP runtime error (message has the text) */
+  SRTC_ERR_DEVICE = -10,       /* HIP runtime error (message has the text) */
+  SRTC_ERR_TOO_LARGE = -11     /* request exceeds a fixed-size buffer
+                                  (srtc_contract_noalloc) */
 } srtc_status;
 
 /* ------------------------------------------------------------ semirings -- */
@@ -242,6 +244,33 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
                           const char *ia, const srtc_tensor *A, const char *ib,
                           const srtc_tensor *B, const char *ic, srtc_tensor *C,
                           const srtc_opts *opts, void *stream);
+
+/* srtc_contract's sparse x dense -> dense form for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): no allocator callback, hipMalloc,
+ * hipFree or allocating library routine is called.  The work-item plan and
+ * the partial results of long rows live in one fixed device buffer of the
+ * library (64 MiB per device, looked up when a context is created and kept
+ * until the process ends).  Arguments and results as srtc_contract with
+ * opts = NULL, restricted to the layouts that need no rearrangement:
+ *   A  CSR; ia = C's row letters (in C's order) then the contracted
+ *      letters; split = number of row letters;
+ *   B  dense; ib = the contracted letters in A's order, then C's column
+ *      letters in C's order;
+ *   C  dense, caller-allocated; ic = row letters then column letters;
+ *   no letter in all three tensors.
+ * Any other layout: SRTC_ERR_UNSUPPORTED.  The plan takes about
+ *   40 m + 32 (m + nnz/T) + 16 (nnz/T) s
+ * bytes (m rows of A, s columns of C, T = 32..256 nonzeros per work item);
+ * a product needing more than the buffer returns SRTC_ERR_TOO_LARGE.
+ * SRTC_VALIDATE is not applied here (validation allocates).  Fully
+ * asynchronous.  Every call on a device shares that device's buffer and
+ * leaves its contents behind; calls that overlap on one device (two
+ * streams, two threads or two contexts) race and must be ordered by the
+ * caller. */
+srtc_status srtc_contract_noalloc(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int accumulate,
+                                  const char *ia, const srtc_tensor *A, const char *ib, const srtc_tensor *B,
+                                  const char *ic, srtc_tensor *C, void *stream);
 
 /* Contraction into a given output pattern (the output with predefined
  * sparsity that Sections 1 and 7 name as an extension):

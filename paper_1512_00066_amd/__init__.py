@@ -41,7 +41,7 @@ _DT_CTYPE = {F64: ctypes.c_double, F32: ctypes.c_float, I32: ctypes.c_int32, BOO
 STATUS = {0: "ok", -1: "invalid argument", -2: "invalid index string", -3: "dimension mismatch",
           -4: "value type not defined for the semiring", -5: "malformed sparse operand",
           -6: "output overlaps an input", -7: "out of memory", -8: "fixpoint not reached",
-          -9: "unsupported", -10: "device error"}
+          -9: "unsupported", -10: "device error", -11: "request exceeds a fixed-size buffer"}
 
 
 class SrtcError(RuntimeError):
@@ -101,6 +101,7 @@ def lib():
             "srtc_fold": ([P, ctypes.c_int, P, S, T, S, S, T, P], ctypes.c_int),
             "srtc_contract": ([P, ctypes.c_int, P, ctypes.c_int, S, T, S, T, S, T, ctypes.POINTER(_Opts), P],
                               ctypes.c_int),
+            "srtc_contract_noalloc": ([P, ctypes.c_int, P, ctypes.c_int, S, T, S, T, S, T, P], ctypes.c_int),
             "srtc_fixpoint": ([P, ctypes.c_int, P, T, T, I64_, I32_, ctypes.POINTER(I64_), P], ctypes.c_int),
             "srtc_fixpoint_ex": ([P, ctypes.c_int, P, T, T, I64_, I32_, I32_, ctypes.POINTER(I64_), P], ctypes.c_int),
             "srtc_contract_masked": ([P, ctypes.c_int, P, S, T, S, T, S, T, T, ctypes.POINTER(_Opts), P], ctypes.c_int),
@@ -261,11 +262,15 @@ class Context:
         self._live = {}
         live = self._live
         dev = self.device
+        # number of allocator callbacks so far (tests check calls that must
+        # allocate nothing)
+        self._nalloc = nalloc = [0]
 
         def _a(user, nbytes):
             t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
             p = t.data_ptr()
             live[p] = t
+            nalloc[0] += 1
             return p
 
         def _f(user, ptr):
@@ -283,6 +288,11 @@ class Context:
         if h is not None and _lib is not None:
             _lib.srtc_ctx_destroy(h)
             self._h = None
+
+    @property
+    def allocations(self) -> int:
+        """Device allocations the library has requested from this context."""
+        return self._nalloc[0]
 
     # -------------------------------------------------------- internals --
     def _stream(self):
@@ -359,6 +369,19 @@ class Context:
         self._check(st)
         if C is None or isinstance(C, CSR):
             return self._csr_out(cd)
+        return C
+
+    def contract_noalloc(self, semiring, ia: str, A, ib: str, B, ic: str, C, accumulate=False, add_id=None):
+        """C[ic] (+)= A[ia] (x) B[ib] for CSR A and dense B and C, with no
+        device allocation (the library's fixed per-device buffer holds the
+        plan).  Layouts: ia = C's row letters then the inner ones, ib = the
+        inner letters then C's column letters, ic = rows then columns.
+        Returns C."""
+        ad, bd, cd = _desc(A), _desc(B), _desc(C)
+        st = lib().srtc_contract_noalloc(self._h, _sr(semiring), _add_id(add_id, ad.dtype), int(bool(accumulate)),
+                                         ia.encode(), ctypes.byref(ad), ib.encode(), ctypes.byref(bd), ic.encode(),
+                                         ctypes.byref(cd), self._stream())
+        self._check(st)
         return C
 
     def contract_panels(self, semiring, ia: str, A, ib: str, B, ic: str, consume, panel_products: int = 0,

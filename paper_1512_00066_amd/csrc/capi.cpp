@@ -567,6 +567,7 @@ const char *srtc_status_string(srtc_status st) {
     case SRTC_ERR_NOT_CONVERGED: return "fixpoint not reached";
     case SRTC_ERR_UNSUPPORTED: return "unsupported";
     case SRTC_ERR_DEVICE: return "device error";
+    case SRTC_ERR_TOO_LARGE: return "request exceeds a fixed-size buffer";
   }
   return "unknown status";
 }
@@ -587,6 +588,26 @@ srtc_status srtc_ctx_create(int device, srtc_alloc_fn alloc, srtc_free_fn free_f
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
     c->c.num_cus = prop.multiProcessorCount;
     c->c.lds_per_block = prop.sharedMemPerBlock;
+  }
+  {
+    // the fixed buffer of srtc_contract_noalloc: its address on this device,
+    // looked up once per device with the device current
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) {
+      delete c;
+      return SRTC_ERR_DEVICE;
+    }
+    srtc_status st = SRTC_OK;
+    try {
+      c->c.fixed_scratch = spmm_fixed_scratch_init(device);
+    } catch (const Error &e) {
+      st = e.st;
+    }
+    (void)hipSetDevice(prev);
+    if (st != SRTC_OK) {
+      delete c;
+      return st;
+    }
   }
   const char *tr = getenv("SRTC_TRACE");
   c->c.trace = tr && *tr && *tr != '0';
@@ -934,6 +955,38 @@ srtc_status srtc_contract_panels(srtc_ctx *ctx, srtc_semiring sr, const void *ad
       if (rc != 0) fail(SRTC_ERR_ARG, "panels: stopped by the consumer");
       r0 = r1;
     }
+  });
+}
+
+srtc_status srtc_contract_noalloc(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int accumulate,
+                                  const char *ia, const srtc_tensor *A, const char *ib, const srtc_tensor *B,
+                                  const char *ic, srtc_tensor *C, void *stream) {
+  return guard(ctx, [&] {
+    check_tensor(A, "A");
+    check_tensor(B, "B");
+    check_tensor(C, "C");
+    const std::string a = letters(ia, A, "A"), b = letters(ib, B, "B"), cidx = letters(ic, C, "C");
+    if (A->dtype != B->dtype) fail(SRTC_ERR_DTYPE, "A and B value types differ");
+    const int dt = A->dtype;
+    const IdVal id = make_id(sr, dt, add_id);
+    const Plan p = plan_contraction(a, A, b, B, cidx, C);
+    if (A->format != SRTC_CSR || B->format != SRTC_DENSE || C->format != SRTC_DENSE)
+      fail(SRTC_ERR_UNSUPPORTED, "no-allocation contraction: A must be CSR, B and C dense");
+    if (!p.batch.empty()) fail(SRTC_ERR_UNSUPPORTED, "no-allocation contraction: a letter in all three tensors");
+    if (a != p.M + p.K || A->split != (int)p.M.size())
+      fail(SRTC_ERR_UNSUPPORTED, "no-allocation contraction: A must be CSR over C's row letters then the inner ones");
+    if (b != p.K + p.N) fail(SRTC_ERR_UNSUPPORTED, "no-allocation contraction: B must list A's inner letters first");
+    if (cidx != p.M + p.N) fail(SRTC_ERR_UNSUPPORTED, "no-allocation contraction: C must list its row letters first");
+    if (C->dtype != dt) fail(SRTC_ERR_DTYPE, "C value type differs");
+    const size_t cbytes = tensor_value_bytes(C);
+    if (overlaps(C->vals, cbytes, A->vals, tensor_value_bytes(A)) ||
+        overlaps(C->vals, cbytes, B->vals, tensor_value_bytes(B)))
+      fail(SRTC_ERR_ALIAS, "C overlaps an operand");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    ctx->c.tracef("srtc_contract_noalloc %s,%s->%s semiring %d dtype %d", a.c_str(), b.c_str(), cidx.c_str(), (int)sr,
+                  dt);
+    spmm_fixed(&ctx->c, sr, dt, id, csr_view(A), B->vals, extent(p, p.N), C->vals, accumulate ? 1 : 0, s);
   });
 }
 

@@ -45,6 +45,8 @@ struct Ctx {
   // column blocks of B for wide products (SRTC_COL_BLOCKS): -1 or 1 = none,
   // 0 = sized from B, q >= 2 = q blocks
   int col_blocks = -1;
+  // this device's fixed buffer of srtc_contract_noalloc (device address)
+  void *fixed_scratch = nullptr;
   void release_cache();
   void tracef(const char *fmt, ...);
   // per-kernel profile: HIP events around each launch on its stream, with
@@ -103,6 +105,10 @@ struct CsrOut {
 // or int64.  Returns nothing; total stays on device.
 void excl_scan_i64(Ctx *c, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 void excl_scan_i32(Ctx *c, const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+// The same scan with its tile sums in caller memory (excl_scan_workspace(n)
+// int64 values); allocates nothing.
+int64_t excl_scan_workspace(int64_t n);
+void excl_scan_i64_ws(const int64_t *in, int64_t *out, int64_t n, int64_t *sums, hipStream_t s);
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 void fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 void fill_bytes_value(void *p, int64_t n, int dtype, IdVal v, hipStream_t s);

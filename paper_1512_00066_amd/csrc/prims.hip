@@ -76,19 +76,24 @@ __global__ void __launch_bounds__(SCAN_BS) scan_tile_down(const In *in, int64_t 
 // The tile-sum kernel must sum the same elements the down-sweep assigns to
 // a tile; both cover [base, base + SCAN_TILE), in different orders.
 template <class In>
-void excl_scan_impl(Ctx *c, const In *in, int64_t *out, int64_t n, hipStream_t s) {
+void excl_scan_into(const In *in, int64_t *out, int64_t n, int64_t *sums, hipStream_t s) {
   if (n <= 0) {
     fill_i64(out, 1, 0, s);
     return;
   }
   const int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
-  Buf sums(c, sizeof(int64_t) * (size_t)nt);
-  scan_tile_sums<In><<<(unsigned)nt, SCAN_BS, 0, s>>>(in, n, sums.as<int64_t>());
+  scan_tile_sums<In><<<(unsigned)nt, SCAN_BS, 0, s>>>(in, n, sums);
   SRTC_LAUNCH_CHECK("scan_tile_sums");
-  scan_sums_single<<<1, SCAN_BS, 0, s>>>(sums.as<int64_t>(), nt, out + n);
+  scan_sums_single<<<1, SCAN_BS, 0, s>>>(sums, nt, out + n);
   SRTC_LAUNCH_CHECK("scan_sums_single");
-  scan_tile_down<In><<<(unsigned)nt, SCAN_BS, 0, s>>>(in, n, sums.as<int64_t>(), out);
+  scan_tile_down<In><<<(unsigned)nt, SCAN_BS, 0, s>>>(in, n, sums, out);
   SRTC_LAUNCH_CHECK("scan_tile_down");
+}
+
+template <class In>
+void excl_scan_impl(Ctx *c, const In *in, int64_t *out, int64_t n, hipStream_t s) {
+  Buf sums(c, sizeof(int64_t) * (size_t)std::max<int64_t>(excl_scan_workspace(n), 1));
+  excl_scan_into<In>(in, out, n, sums.as<int64_t>(), s);
 }
 
 template <class T>
@@ -108,8 +113,12 @@ template <class T> void fill_any(T *p, int64_t n, T v, hipStream_t s) {
 
 }  // namespace
 
+int64_t excl_scan_workspace(int64_t n) { return n <= 0 ? 0 : (n + SCAN_TILE - 1) / SCAN_TILE; }
 void excl_scan_i64(Ctx *c, const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
   excl_scan_impl<int64_t>(c, in, out, n, s);
+}
+void excl_scan_i64_ws(const int64_t *in, int64_t *out, int64_t n, int64_t *sums, hipStream_t s) {
+  excl_scan_into<int64_t>(in, out, n, sums, s);
 }
 void excl_scan_i32(Ctx *c, const int32_t *in, int64_t *out, int64_t n, hipStream_t s) {
   excl_scan_impl<int32_t>(c, in, out, n, s);

@@ -15,9 +15,19 @@
 // second kernel combines in item order, which keeps every semiring,
 // including fp (+), deterministic.
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "internal.hpp"
 #include "spmm_plan.hpp"
+
+// The one device buffer of the product that allocates nothing: its work-item
+// plan and the partial results of split rows.  Each device holds its own copy
+// from the first look-up until the process ends.  Host code never passes this
+// name to a kernel (on the host it is a stand-in, not a device address): it
+// uses the address hipGetSymbolAddress returns for the current device.
+static constexpr size_t kFixedScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
 
 namespace srtc {
 
@@ -316,46 +326,113 @@ __global__ void __launch_bounds__(256) bfs_step_kernel(const int64_t *__restrict
 
 }  // namespace
 
-void SpmmPlan::build(Ctx *c, const CsrView &A, int64_t s_width, hipStream_t st) {
+void SpmmPlan::shape(Ctx *c, const CsrView &A, int64_t s_width) {
   ctx = c;
+  rows = A.m;
   int g = 1;
   while (g < s_width && g < WAVE) g <<= 1;
   G = g;
   // a work unit is one item times one chunk of G columns: wider operands
   // have more chunks per item, so shorter items keep the units short
   T = s_width > 128 ? 64 : (G >= 64 ? 256 : (G >= 8 ? 64 : 32));
+  max_items = A.m + A.nnz / T + 1;
+  // a split row of z > T nonzeros has ceil(z / T) < 2 z / T items
+  max_partial = 2 * (A.nnz / T) + 1;
+  may_split = true;
+  grid_cap = (int64_t)c->num_cus * 16;
+}
+
+void SpmmPlan::fill(const CsrView &A, int64_t *cnt_p, int64_t *pcnt_p, int64_t *ioff_p, int64_t *poff_p,
+                    int64_t *sums, int32_t *irow_p, int64_t *ibeg_p, int64_t *iend_p, int64_t *ipidx_p,
+                    void *partial_p, hipStream_t st) {
   const int64_t m = A.m;
-  max_items = m + A.nnz / T + 1;
-  cnt = Buf(c, sizeof(int64_t) * (size_t)std::max<int64_t>(m, 1));
-  pcnt = Buf(c, sizeof(int64_t) * (size_t)std::max<int64_t>(m, 1));
+  if (m > 0) {
+    items_count<<<gridn(m), 256, 0, st>>>(A.rowptr, m, T, cnt_p, pcnt_p);
+    SRTC_LAUNCH_CHECK("items_count");
+  }
+  // the two scans run one after the other on st and share the tile sums
+  excl_scan_i64_ws(cnt_p, ioff_p, m, sums, st);
+  excl_scan_i64_ws(pcnt_p, poff_p, m, sums, st);
+  if (m > 0) {
+    items_fill<<<gridn(m), 256, 0, st>>>(A.rowptr, m, T, ioff_p, poff_p, irow_p, ibeg_p, iend_p, ipidx_p);
+    SRTC_LAUNCH_CHECK("items_fill");
+  }
+  irow = irow_p;
+  ibeg = ibeg_p;
+  iend = iend_p;
+  ipidx = ipidx_p;
+  nitems = ioff_p + m;
+  partial = partial_p;
+}
+
+void SpmmPlan::build(Ctx *c, const CsrView &A, int64_t s_width, hipStream_t st) {
+  shape(c, A, s_width);
+  const int64_t m = A.m;
+  const size_t rows = (size_t)std::max<int64_t>(m, 1);
+  cnt = Buf(c, sizeof(int64_t) * rows);
+  pcnt = Buf(c, sizeof(int64_t) * rows);
   ioff = Buf(c, sizeof(int64_t) * (size_t)(m + 1));
   poff = Buf(c, sizeof(int64_t) * (size_t)(m + 1));
+  Buf sums(c, sizeof(int64_t) * (size_t)std::max<int64_t>(excl_scan_workspace(m), 1));
   irow_b = Buf(c, sizeof(int32_t) * (size_t)max_items);
   ibeg_b = Buf(c, sizeof(int64_t) * (size_t)max_items);
   iend_b = Buf(c, sizeof(int64_t) * (size_t)max_items);
   ipidx_b = Buf(c, sizeof(int64_t) * (size_t)max_items);
-  const int64_t maxpart = 2 * (A.nnz / T) + 1;
-  may_split = true;
-  partial_b = Buf(c, (size_t)maxpart * (size_t)s_width * 8);
-  if (m > 0) {
-    items_count<<<gridn(m), 256, 0, st>>>(A.rowptr, m, T, cnt.as<int64_t>(), pcnt.as<int64_t>());
-    SRTC_LAUNCH_CHECK("items_count");
+  partial_b = Buf(c, (size_t)max_partial * (size_t)s_width * 8);
+  fill(A, cnt.as<int64_t>(), pcnt.as<int64_t>(), ioff.as<int64_t>(), poff.as<int64_t>(), sums.as<int64_t>(),
+       irow_b.as<int32_t>(), ibeg_b.as<int64_t>(), iend_b.as<int64_t>(), ipidx_b.as<int64_t>(), partial_b.p, st);
+}
+
+namespace {
+// Consecutive 256-byte aligned regions of one buffer, in the order they are
+// taken; the same sequence sizes the buffer (base = null) and lays it out.
+struct Carve {
+  char *base;
+  int64_t off = 0;
+  template <class T> T *take(int64_t count) {
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += (int64_t)(((uint64_t)std::max<int64_t>(count, 1) * sizeof(T) + 255) & ~(uint64_t)255);
+    return p;
   }
-  excl_scan_i64(c, cnt.as<int64_t>(), ioff.as<int64_t>(), m, st);
-  excl_scan_i64(c, pcnt.as<int64_t>(), poff.as<int64_t>(), m, st);
-  if (m > 0) {
-    items_fill<<<gridn(m), 256, 0, st>>>(A.rowptr, m, T, ioff.as<int64_t>(), poff.as<int64_t>(),
-                                         irow_b.as<int32_t>(), ibeg_b.as<int64_t>(), iend_b.as<int64_t>(),
-                                         ipidx_b.as<int64_t>());
-    SRTC_LAUNCH_CHECK("items_fill");
-  }
-  irow = irow_b.as<int32_t>();
-  ibeg = ibeg_b.as<int64_t>();
-  iend = iend_b.as<int64_t>();
-  ipidx = ipidx_b.as<int64_t>();
-  nitems = ioff.as<int64_t>() + m;
-  partial = partial_b.p;
-  grid_cap = (int64_t)c->num_cus * 16;
+};
+
+struct PlanParts {
+  int64_t *cnt, *pcnt, *ioff, *poff, *sums;
+  int32_t *irow;
+  int64_t *ibeg, *iend, *ipidx;
+  double *partial;
+};
+
+int64_t carve_plan(const SpmmPlan &pl, int64_t m, int64_t s_width, char *base, PlanParts *out) {
+  Carve cv{base};
+  PlanParts q;
+  q.cnt = cv.take<int64_t>(m);
+  q.pcnt = cv.take<int64_t>(m);
+  q.ioff = cv.take<int64_t>(m + 1);
+  q.poff = cv.take<int64_t>(m + 1);
+  q.sums = cv.take<int64_t>(excl_scan_workspace(m));
+  q.irow = cv.take<int32_t>(pl.max_items);
+  q.ibeg = cv.take<int64_t>(pl.max_items);
+  q.iend = cv.take<int64_t>(pl.max_items);
+  q.ipidx = cv.take<int64_t>(pl.max_items);
+  q.partial = cv.take<double>(pl.max_partial * s_width);
+  if (out) *out = q;
+  return cv.off;
+}
+}  // namespace
+
+int64_t SpmmPlan::workspace_bytes(int64_t s_width) const {
+  // sizes far beyond any device memory are reported as INT64_MAX instead of
+  // overflowing
+  const double approx = 40.0 * (double)rows + 32.0 * (double)max_items + 8.0 * (double)max_partial * (double)s_width;
+  if (approx > 0x1p60) return INT64_MAX;
+  return carve_plan(*this, rows, s_width, nullptr, nullptr);
+}
+
+void SpmmPlan::build_in(const CsrView &A, int64_t s_width, void *ws, hipStream_t st) {
+  PlanParts q;
+  carve_plan(*this, A.m, s_width, static_cast<char *>(ws), &q);
+  fill(A, q.cnt, q.pcnt, q.ioff, q.poff, q.sums, q.irow, q.ibeg, q.iend, q.ipidx, q.partial, st);
 }
 
 void spmm_with_plan(const SpmmPlan &pl, int sr, int dt, IdVal id, const CsrView &A, const void *X,
@@ -377,6 +454,42 @@ void spmm(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const void *X, int
   if (A.m == 0 || s_width == 0) return;
   SpmmPlan pl;
   pl.build(c, A, s_width, st);
+  spmm_with_plan(pl, sr, dt, id, A, X, s_width, Y, 0, accumulate, nullptr, nullptr, nullptr, nullptr, st);
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void *g_fixed_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t spmm_fixed_scratch_bytes() { return kFixedScratchBytes; }
+
+void *spmm_fixed_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(SRTC_ERR_DEVICE, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_fixed_mu);
+  if (!g_fixed_ptr[device]) {
+    void *p = nullptr;
+    SRTC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(SRTC_ERR_DEVICE, "no device address for the fixed buffer");
+    g_fixed_ptr[device] = p;
+  }
+  return g_fixed_ptr[device];
+}
+
+void spmm_fixed(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const void *X, int64_t s_width, void *Y,
+                int accumulate, hipStream_t st) {
+  if (A.m == 0 || s_width == 0) return;
+  if (!c->fixed_scratch) fail(SRTC_ERR_DEVICE, "the fixed buffer was not set up for this device");
+  SpmmPlan pl;
+  pl.shape(c, A, s_width);
+  const int64_t need = pl.workspace_bytes(s_width);
+  if (need > (int64_t)kFixedScratchBytes)
+    fail(SRTC_ERR_TOO_LARGE, "the product's plan needs " + std::to_string(need) + " bytes; the fixed buffer holds " +
+                                 std::to_string(kFixedScratchBytes) + " (call srtc_contract)");
+  // every plan array is written before it is read, so the previous call's
+  // contents need no clearing
+  pl.build_in(A, s_width, c->fixed_scratch, st);
   spmm_with_plan(pl, sr, dt, id, A, X, s_width, Y, 0, accumulate, nullptr, nullptr, nullptr, nullptr, st);
 }
 
