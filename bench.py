@@ -394,7 +394,7 @@ def run_rmat18(args):
         for coo in (coo64, coo32):
             A = ctx.fold("plus_times", coo, "ij", "i", "j")
             C = ctx.contract("plus_times", "ik", A, "kj", A, "ij", schedule=-1 if not sched else
-                             sched["f64" if coo is coo64 else "f32"])
+                             sched["f64" if coo is coo64 else "f32"], hub_tile=args.hub_tile)
             outs.append(C.nnz)
             del A, C
         ctx.contract("plus_times", "ijk", T, "kl", Md, "ijl", C=Cd)
@@ -426,7 +426,7 @@ def run_rmat18(args):
            "config": {"workload": "rmat18_AxA_f64_f32+tensor512_fold_contraction", "rmat_scale": 18,
                       "edge_factor": 16, "abcd": [0.57, 0.19, 0.19, 0.05], "tensor_dims": [512, 512, 512],
                       "tensor_density": 1e-3, "dense_M": [512, 64], "products_per_AxA": products,
-                      "schedules": sched},
+                      "schedules": sched, "hub_tile": args.hub_tile},
            "roofline": roof}
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
@@ -1258,6 +1258,7 @@ def main():
     ap.add_argument("--schedule", type=int, default=-1, help="force one SpGEMM schedule")
     ap.add_argument("--schedules", default="", help="SpGEMM schedules for fp64,fp32 (e.g. 0,5)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--hub-tile", type=int, default=0, help="rmat18: hub block formed on the matrix cores")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--selector-matrices", type=int, default=2000)

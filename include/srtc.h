@@ -42,6 +42,8 @@
  *                             narrower dense windows (more passes, the same
  *                             results); SRTC_ERR_UNSUPPORTED if even the
  *                             narrowest window does not fit.
+ *       SRTC_HUB_TILE=k       opts.hub_tile for calls that leave it 0
+ *                             (1..16384);
  *       SRTC_COL_BLOCKS=q     multiply the rows with many products one
  *                             column block of B at a time (q >= 2 blocks; 0:
  *                             blocks of about 48 MB of B); unset or 1: no
@@ -168,7 +170,12 @@ typedef struct srtc_opts {
                        else the default); 0..SRTC_NUM_SCHEDULES-1: force */
   int32_t sorted;   /* 1: output rows list columns ascending (default) */
   int32_t validate; /* 1: check operand structure (SRTC_ERR_FORMAT) */
-  int32_t reserved;
+  int32_t hub_tile; /* > 0 (at most 16384): sparse x sparse (+,x) products
+                       on F64/F32 form the block of the hub_tile rows of A,
+                       inner indices and columns of B with the most entries
+                       as one dense product on the matrix cores (Section 6.2's
+                       small dense blocks, see srtc_contract); 0: the
+                       environment's SRTC_HUB_TILE, else none */
 } srtc_opts;
 
 /* ------------------------------------------------------------- context -- */
@@ -239,7 +246,18 @@ srtc_status srtc_fold(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const
  * CSR rows are C's first |row letters| letters).  Sparse operands may be
  * COO (folded on the fly) or CSR whose split matches the fold.
  * Right-hand sides are read before C is written (out-of-place); C may not
- * share storage with A or B (SRTC_ERR_ALIAS). */
+ * share storage with A or B (SRTC_ERR_ALIAS).
+ * Hub tiles (opts->hub_tile = k > 0, (+,x) on F64/F32, sparse x sparse, no
+ * letter in all three tensors, no old C entries to merge): H_i, H_k, H_j are
+ * the k rows of A, inner indices and columns of B with the most entries
+ * (A's row lengths; A's column counts plus B's row lengths; B's column
+ * counts; ties to the smaller index).  D = A[H_i,H_k] B[H_k,H_j] is formed
+ * densely on the matrix cores (F32: fp32 multiply-adds of at most 128 terms
+ * each added into fp64, as for dense x dense) and the rest sparsely, as one
+ * product [A_x | A_h | I] x [B ; B_x ; D] (A_h = A's entries in H_i x H_k,
+ * A_x the others, B_x = B's rows in H_k without the H_j columns).  The
+ * pattern of C is the same; values differ from the sparse path only by
+ * summation order (and, for F32, the tile's rounding). */
 srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int accumulate,
                           const char *ia, const srtc_tensor *A, const char *ib,
                           const srtc_tensor *B, const char *ic, srtc_tensor *C,

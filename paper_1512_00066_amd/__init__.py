@@ -66,7 +66,7 @@ class _Tensor(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("sorted", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("hub_tile", ctypes.c_int32)]
 
 
 class _TrainCfg(ctypes.Structure):
@@ -342,12 +342,15 @@ class Context:
         return self._csr_out(out)
 
     def contract(self, semiring, ia: str, A, ib: str, B, ic: str, C=None, accumulate=False, add_id=None,
-                 schedule: int = -1, sorted: bool = True, out_dims=None, validate: bool = False):
+                 schedule: int = -1, sorted: bool = True, out_dims=None, validate: bool = False,
+                 hub_tile: int = 0):
         """C[ic] (+)= A[ia] (x) B[ib].  Sparse x sparse returns a CSR; with a
         dense operand C must be a preallocated dense tensor (returned).
-        validate: check the sparse operands' structure first."""
+        validate: check the sparse operands' structure first.  hub_tile: the
+        size of the dense hub block formed on the matrix cores ((+,x) sparse
+        products; 0 = none)."""
         ad, bd = _desc(A), _desc(B)
-        opts = _Opts(schedule, 1 if sorted else 0, 1 if validate else 0, 0)
+        opts = _Opts(schedule, 1 if sorted else 0, 1 if validate else 0, int(hub_tile))
         if C is None:
             # sparse result: dims of C from the index strings
             ext = {}

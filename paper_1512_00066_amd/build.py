@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libsrtc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SRTC_ARCH", "gfx950")
 
-SOURCES = ["prims.hip", "fold.hip", "spgemm.hip", "spmm.hip", "dense.hip", "mlp.hip", "validate.hip", "apsp.hip", "transform.hip", "ewise.cpp",
+SOURCES = ["prims.hip", "fold.hip", "spgemm.hip", "spmm.hip", "dense.hip", "mlp.hip", "validate.hip", "apsp.hip", "transform.hip", "hubs.hip", "ewise.cpp",
            "capi.cpp", "sched.cpp", "batch.cpp"]
 
 FLAGS = [

@@ -633,6 +633,16 @@ srtc_status srtc_ctx_create(int device, srtc_alloc_fn alloc, srtc_free_fn free_f
     }
     c->c.col_blocks = (int)v;
   }
+  const char *ht = getenv("SRTC_HUB_TILE");
+  if (ht && *ht) {
+    char *end = nullptr;
+    const long v = strtol(ht, &end, 10);
+    if (end == ht || *end != 0 || v < 0 || v > 16384) {
+      delete c;
+      return SRTC_ERR_ARG;
+    }
+    c->c.hub_tile = (int)v;
+  }
   const char *lb = getenv("SRTC_LDS_BUDGET");
   if (lb && *lb) {
     char *end = nullptr;
@@ -725,6 +735,7 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
     const Plan p = plan_contraction(a, A, b, B, cidx, C);
     srtc_opts o{-1, 1, 0, 0};
     if (opts) o = *opts;
+    if (o.hub_tile < 0 || o.hub_tile > 16384) fail(SRTC_ERR_ARG, "opts.hub_tile out of range (0..16384)");
     hipStream_t s = (hipStream_t)stream;
     ctx->c.stream = s;
     Ctx *c = &ctx->c;
@@ -761,6 +772,16 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
         Augmented g;
         augment(c, sr, dt, fa.view, fb.view, cv, &g, s);
         spgemm(c, sr, dt, id, g.a, g.b, sched, o.sorted, &t, &st, s);
+        int64_t dims[SRTC_MAX_ORDER];
+        for (size_t q = 0; q < cidx.size(); q++) dims[q] = p.dim.at(cidx[q]);
+        set_csr_out(C, t, (int)cidx.size(), dims, (int)crow.size(), dt);
+        return;
+      }
+      const int64_t hub = o.hub_tile > 0 ? o.hub_tile : c->hub_tile;
+      const bool merge_old = accumulate && C->format == SRTC_CSR && C->nnz > 0;
+      if (!merge_old && p.batch.empty() && crow + p.N == cidx && hub_product_applies(sr, dt, fa.view, fb.view, hub)) {
+        if (fa.view.n != fb.view.m) fail(SRTC_ERR_DIM, "inner dimensions differ");
+        spgemm_hubs(c, dt, id, fa.view, fb.view, hub, sched, o.sorted, &t, &st, s);
         int64_t dims[SRTC_MAX_ORDER];
         for (size_t q = 0; q < cidx.size(); q++) dims[q] = p.dim.at(cidx[q]);
         set_csr_out(C, t, (int)cidx.size(), dims, (int)crow.size(), dt);

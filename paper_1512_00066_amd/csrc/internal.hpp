@@ -45,6 +45,8 @@ struct Ctx {
   // column blocks of B for wide products (SRTC_COL_BLOCKS): -1 or 1 = none,
   // 0 = sized from B, q >= 2 = q blocks
   int col_blocks = -1;
+  // hub tile size of sparse x sparse (+,x) products (SRTC_HUB_TILE): 0 = none
+  int hub_tile = 0;
   // this device's fixed buffer of srtc_contract_noalloc (device address)
   void *fixed_scratch = nullptr;
   void release_cache();
@@ -172,6 +174,12 @@ void spgemm_grouped(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const Cs
 // C = M (.) (A (x) B) over M's pattern (sorted rows; identity results dropped).
 void spgemm_masked(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const CsrView &B, const CsrView &M,
                    CsrOut *out, hipStream_t s);
+// C = A (x) B over (+,x) with the block of the `hub` densest rows of A,
+// inner indices and columns of B formed on the matrix cores and the rest
+// sparsely (one augmented product); the same output as spgemm().
+bool hub_product_applies(int sr, int dt, const CsrView &A, const CsrView &B, int64_t hub);
+void spgemm_hubs(Ctx *c, int dt, IdVal id, const CsrView &A, const CsrView &B, int64_t hub, int sched,
+                 int sorted, CsrOut *out, SpgemmStats *st, hipStream_t s);
 // Row product counts w_i (int64, m entries).
 void row_products(const CsrView &A, const CsrView &B, int64_t *w, hipStream_t s);
 // C = X (+) Y for two CSR matrices of the same shape (sorted rows); the
