@@ -176,112 +176,72 @@ template <int BS, class V> struct Chunk {
 
 // Walking the products laid out by a chunk: L.off holds the exclusive scan of
 // the cnt segment lengths (total products), L.start each segment's first
-// position in B, L.a the A value.  The products are taken in tiles of BS*U,
-// in one of two layouts:
-//   COAL = false: thread t takes U consecutive products t*U .. t*U+U-1.  A
-//     binary search finds the segment owning the first; the next ones
-//     advance from it (one comparison with the next segment's offset, the B
-//     position otherwise just increments), so the search is paid once per
-//     batch of U products.  The u-th load of a wave reads every U-th product.
-//   COAL = true: thread t takes products t, t + BS, ..., t + (U-1)*BS, so
-//     the u-th load of a wave reads 64 consecutive products (whole cache
-//     lines of B when the segments are long); each product finds its segment
-//     by its own binary search, the U searches interleaved (the latency of
-//     one, U times the instructions).  Worth it where a product does more
-//     than set a bit: the numeric dense-window kernel.
-// Either way a lane keeps U independent loads in flight.  Gathering a batch
-// and consuming it are separate steps, so a caller can issue the loads early
-// and use them later.
+// position in B, L.a the A value.  The products are taken in tiles of BS*U;
+// in a tile, thread t takes U consecutive ones, t*U .. t*U+U-1.  A binary
+// search finds the segment owning the first; the next ones advance from it
+// (one comparison with the next segment's offset, the B position otherwise
+// just increments), so the search is paid once per batch of U products, not
+// per product, and a lane keeps U independent loads in flight.  Gathering a
+// batch and consuming it are separate steps, so a caller can issue the loads
+// early and use them later.
 template <int U, class V> struct Batch {
   int32_t j[U];
   V a[U], b[U];
 };
 
-template <int BS, int U, bool VALS, class V, bool COAL = false>
+template <int BS, int U, bool VALS, class V>
 __device__ __forceinline__ void gather_batch(const int32_t *__restrict__ cB, const V *__restrict__ vB, int cnt,
                                              int32_t total, const Chunk<BS, V> &L, int32_t base, Batch<U, V> &g) {
-  const int top = cnt > 1 ? 1 << (31 - __clz(cnt - 1)) : 0;
-  if constexpr (COAL) {
-    const int32_t q0 = base + (int32_t)threadIdx.x;
-    // largest lo with off[lo] <= q (off is non-decreasing, off[0] = 0; empty
-    // segments share the next one's offset, so the largest is non-empty)
-    int lo[U];
+  const int32_t q0 = base + (int32_t)threadIdx.x * U;
+  // largest lo with off[lo] <= q0 (off is non-decreasing, off[0] = 0)
+  int lo = 0;
+  for (int step = cnt > 1 ? 1 << (31 - __clz(cnt - 1)) : 0; step > 0; step >>= 1) {
+    const int c = lo + step;
+    if (c < cnt && L.off[c] <= q0) lo = c;
+  }
+  int32_t nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
+  int64_t pos = L.start[lo] + (q0 - L.off[lo]);
+  const int32_t *pc = cB + pos;
+  const V *pv = VALS ? vB + pos : nullptr;
+  V av = VALS ? L.a[lo] : V{};
 #pragma unroll
-    for (int u = 0; u < U; u++) lo[u] = 0;
-    for (int step = top; step > 0; step >>= 1) {
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int c = lo[u] + step;
-        if (c < cnt && L.off[c] <= q0 + u * BS) lo[u] = c;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const int32_t q = q0 + u * BS;
-      g.j[u] = 0;
-      g.a[u] = V{};
-      g.b[u] = V{};
-      if (q < total) {
-        const int64_t pos = L.start[lo[u]] + (q - L.off[lo[u]]);
-        g.j[u] = cB[pos];
-        if (VALS) {
-          g.a[u] = L.a[lo[u]];
-          g.b[u] = vB[pos];
+  for (int u = 0; u < U; u++) {
+    const int32_t q = q0 + u;
+    g.j[u] = 0;
+    g.a[u] = V{};
+    g.b[u] = V{};
+    if (q < total) {
+      if (u > 0) {
+        if (q >= nxt) {
+          // the next non-empty segment (empty ones share its offset)
+          do {
+            lo++;
+            nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
+          } while (q >= nxt);
+          pos = L.start[lo] + (q - L.off[lo]);
+          pc = cB + pos;
+          if (VALS) pv = vB + pos;
+          if (VALS) av = L.a[lo];
+        } else {
+          pc++;
+          if (VALS) pv++;
         }
       }
-    }
-  } else {
-    const int32_t q0 = base + (int32_t)threadIdx.x * U;
-    // largest lo with off[lo] <= q0 (off is non-decreasing, off[0] = 0)
-    int lo = 0;
-    for (int step = top; step > 0; step >>= 1) {
-      const int c = lo + step;
-      if (c < cnt && L.off[c] <= q0) lo = c;
-    }
-    int32_t nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
-    int64_t pos = L.start[lo] + (q0 - L.off[lo]);
-    const int32_t *pc = cB + pos;
-    const V *pv = VALS ? vB + pos : nullptr;
-    V av = VALS ? L.a[lo] : V{};
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const int32_t q = q0 + u;
-      g.j[u] = 0;
-      g.a[u] = V{};
-      g.b[u] = V{};
-      if (q < total) {
-        if (u > 0) {
-          if (q >= nxt) {
-            // the next non-empty segment (empty ones share its offset)
-            do {
-              lo++;
-              nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
-            } while (q >= nxt);
-            pos = L.start[lo] + (q - L.off[lo]);
-            pc = cB + pos;
-            if (VALS) pv = vB + pos;
-            if (VALS) av = L.a[lo];
-          } else {
-            pc++;
-            if (VALS) pv++;
-          }
-        }
-        g.j[u] = *pc;
-        if (VALS) {
-          g.a[u] = av;
-          g.b[u] = *pv;
-        }
+      g.j[u] = *pc;
+      if (VALS) {
+        g.a[u] = av;
+        g.b[u] = *pv;
       }
     }
   }
 }
 
-template <int BS, int U, class V, bool COAL = false, class F>
+template <int BS, int U, class V, class F>
 __device__ __forceinline__ void consume_batch(const Batch<U, V> &g, int32_t base, int32_t total, F &&f) {
-  const int32_t q0 = base + (int32_t)threadIdx.x * (COAL ? 1 : U);
+  const int32_t q0 = base + (int32_t)threadIdx.x * U;
 #pragma unroll
   for (int u = 0; u < U; u++)
-    if (q0 + u * (COAL ? BS : 1) < total) f(g.j[u], g.a[u], g.b[u]);
+    if (q0 + u < total) f(g.j[u], g.a[u], g.b[u]);
 }
 
 // All products of a laid-out chunk from the tile starting at product `base`
@@ -818,14 +778,12 @@ constexpr int NWPW = 256;  // most windows a row may split into for ranked group
 
 // Ranks of a marked run of nbw bitmap words: thread t takes a contiguous run
 // of words, so one block scan of the per-thread popcounts gives every word's
-// prefix; the first (touched columns) accumulators are reset.  The column of
-// each rank is filled in by the products themselves (rank_add below), so no
-// thread walks the bits of its words here: on skewed rows a few lanes would
-// hold most of the set bits.  Returns the number of touched columns (the
-// same on every thread).
+// prefix; each touched column is listed at its rank with its accumulator
+// reset.  Returns the number of touched columns (the same on every thread).
 template <class SR, int BS>
-__device__ __forceinline__ int32_t rank_run(const uint32_t *rbits, int32_t *rpre, typename SR::acc_t *racc,
-                                            int nbw, typename SR::acc_t id, int64_t *red) {
+__device__ __forceinline__ int32_t rank_run(const uint32_t *rbits, int32_t *rpre, int32_t *rcol,
+                                            typename SR::acc_t *racc, int nbw, typename SR::acc_t id,
+                                            int64_t *red) {
   const int per = (nbw + BS - 1) / BS;
   const int u0 = threadIdx.x * per, u1 = min(u0 + per, nbw);
   int64_t mine = 0;
@@ -834,44 +792,27 @@ __device__ __forceinline__ int32_t rank_run(const uint32_t *rbits, int32_t *rpre
   int32_t r = (int32_t)block_excl_scan<BS, int64_t, false>(mine, red, &tot);
   for (int u = u0; u < u1; u++) {
     rpre[u] = r;
-    r += __popc(rbits[u]);
+    uint32_t wd = rbits[u];
+    while (wd) {
+      const int b = __ffs(wd) - 1;
+      wd &= wd - 1;
+      rcol[r] = u * 32 + b;
+      racc[r] = id;
+      r++;
+    }
   }
-  for (int q = threadIdx.x; q < (int)tot; q += BS) racc[q] = id;
   return (int32_t)tot;
 }
 
-// Extraction of a ranked group: the n accumulators are in column order.
-// When none holds the identity (the usual case) rank q is output position
-// pos0 + q and thread t writes ranks t, t + BS, ... (coalesced); otherwise
-// the ones that are not the identity are written out with ranks from one
-// block scan (thread t takes a contiguous run).  The bitmap is cleared.
-// Returns the number written (the same on every thread).  n <= CAP.
-template <class SR, int BS, int CAPT>
+// Extraction of a ranked group: the n accumulators are in column order, the
+// ones that are not the identity are written out (thread t takes a
+// contiguous run, ranks from one block scan); the bitmap is cleared.
+// Returns the number written (the same on every thread).
+template <class SR, int BS>
 __device__ __forceinline__ int64_t extract_ranked(const typename SR::acc_t *racc, const int32_t *rcol,
                                                   uint32_t *rbits, int nbw, int n, typename SR::acc_t id,
                                                   int64_t col0, int64_t pos0, int32_t *__restrict__ cC,
                                                   typename SR::val_t *__restrict__ vC, int64_t *red) {
-  using A = typename SR::acc_t;
-  constexpr int PER = (CAPT + BS - 1) / BS;
-  int any = 0;
-#pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int r = (int)threadIdx.x + k * BS;
-    any |= (r < n && SR::acc_absent(racc[r], id)) ? 1 : 0;
-  }
-  if (n <= CAPT && !__syncthreads_or(any)) {
-#pragma unroll
-    for (int k = 0; k < PER; k++) {
-      const int r = (int)threadIdx.x + k * BS;
-      if (r < n) {
-        cC[pos0 + r] = (int32_t)(col0 + rcol[r]);
-        vC[pos0 + r] = SR::out(racc[r]);
-      }
-    }
-    for (int u = threadIdx.x; u < nbw; u += BS) rbits[u] = 0;
-    __syncthreads();
-    return n;
-  }
   const int per = (n + BS - 1) / BS;
   const int r0 = threadIdx.x * per, r1 = min(r0 + per, n);
   int64_t mine = 0;
@@ -879,10 +820,10 @@ __device__ __forceinline__ int64_t extract_ranked(const typename SR::acc_t *racc
   int64_t tot;
   int64_t p = pos0 + block_excl_scan<BS, int64_t, false>(mine, red, &tot);
   for (int r = r0; r < r1; r++) {
-    const A x = racc[r];
-    if (SR::acc_absent(x, id)) continue;
+    const typename SR::acc_t v = racc[r];
+    if (SR::acc_absent(v, id)) continue;
     cC[p] = (int32_t)(col0 + rcol[r]);
-    vC[p] = SR::out(x);
+    vC[p] = SR::out(v);
     p++;
   }
   for (int u = threadIdx.x; u < nbw; u += BS) rbits[u] = 0;
@@ -1036,7 +977,6 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
           if (c >= (uint32_t)span) return;
           const int q = rpre[c >> 5] + __popc(rbits[c >> 5] & ((1u << (c & 31)) - 1u));
           SR::lds_add(&racc[q], SR::mul(a, b));
-          rcol[q] = (int32_t)c;  // every product of column c stores the same value
         }
       };
     };
@@ -1069,7 +1009,7 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
       }
       int32_t total = layout_chunk<BS, VALS, V>(o_nxt - o_cur, rb + o_cur, av, L);
       Batch<WALK_U, V> g;
-      gather_batch<BS, WALK_U, VALS, V, true>(cB, vB, cnt, total, L, 0, g);
+      gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, 0, g);
       while (ga < nwin) {
         int na = nwin, nb = nwin;
         bool ndense = true;
@@ -1084,29 +1024,28 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
           for (int32_t b0 = 0; b0 < total; b0 += BS * WALK_U) {
             Batch<WALK_U, V> h = g;
             if (b0 + BS * WALK_U < total)
-              gather_batch<BS, WALK_U, VALS, V, true>(cB, vB, cnt, total, L, b0 + BS * WALK_U, h);
-            consume_batch<BS, WALK_U, V, true>(g, b0, total, dense_add(c0));
+              gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, b0 + BS * WALK_U, h);
+            consume_batch<BS, WALK_U, V>(g, b0, total, dense_add(c0));
             g = h;
           }
         } else {
           const int64_t span = (int64_t)(gb - ga) * W;
-          consume_batch<BS, WALK_U, V, true>(g, 0, total, rank_mark(c0, span));
+          consume_batch<BS, WALK_U, V>(g, 0, total, rank_mark(c0, span));
           __syncthreads();
-          nrank = rank_run<SR, BS>(rbits, rpre, racc, (gb - ga) * R::WPW, id, red);
+          nrank = rank_run<SR, BS>(rbits, rpre, rcol, racc, (gb - ga) * R::WPW, id, red);
           __syncthreads();
-          consume_batch<BS, WALK_U, V, true>(g, 0, total, rank_add(c0, span));
+          consume_batch<BS, WALK_U, V>(g, 0, total, rank_add(c0, span));
         }
         __syncthreads();  // group accumulated; L free
         int32_t total_n = 0;
         if (na < nwin) {
           total_n = layout_chunk<BS, VALS, V>(o_after - o_nxt, rb + o_nxt, av, L);
-          gather_batch<BS, WALK_U, VALS, V, true>(cB, vB, cnt, total_n, L, 0, g);
+          gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total_n, L, 0, g);
         }
         if (dense || !R::OK)
           written += extract_window<SR, BS, W>(vals, bits, id, c0 + orows.col_off, base + written, cC, vC, red);
         else
-          written += extract_ranked<SR, BS, R::CAP>(racc, rcol, rbits, (gb - ga) * R::WPW, nrank, id,
-                                                    c0 + orows.col_off,
+          written += extract_ranked<SR, BS>(racc, rcol, rbits, (gb - ga) * R::WPW, nrank, id, c0 + orows.col_off,
                                             base + written,
                                             cC, vC, red);
         total = total_n;
