@@ -2,6 +2,8 @@
 code -- brute force on tiny inputs, closed forms, library routines (scipy),
 and invariants of the algebra.  CPU only."""
 
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -786,3 +788,36 @@ def test_adam_two_steps_by_hand():
     assert abs(p1[0] - 0.9) < 1e-15 and abs(m[0] - 1.0) < 1e-15 and abs(v[0] - 1.0) < 1e-15
     p2, m, v = mlp.adam_step(p1, np.array([1.0]), m, v, 2, 0.1, 0.5, 0.75, 0.0)
     assert abs(p2[0] - (0.9 - np.sqrt(7.0) / 30.0)) < 1e-15
+
+
+def _golden_semirings():
+    path = os.path.join(os.path.dirname(__file__), "golden", "semiring_identities.txt")
+    rows = []
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            sr, dt, add_id, mul_id = line.split()
+            rows.append((sr, dt, float(add_id) if dt == "f64" else int(add_id),
+                         float(mul_id) if dt == "f64" else int(mul_id)))
+    return rows
+
+
+@pytest.mark.parametrize("semiring,dtype,add_id,mul_id", _golden_semirings())
+def test_semiring_identities_as_the_paper_defines_them(semiring, dtype, add_id, mul_id):
+    """The oracle's default identities are the ones Section 3.1 prints, and
+    they act as identities: an entry equal to the additive one is absent
+    (dropped by the fold), the multiplicative one leaves a product's other
+    factor unchanged, and two additive identities combined by the product
+    stay representable (the reason the paper halves INT_MAX)."""
+    assert oracle.default_add_id(semiring, dtype) == add_id
+    np_dt = oracle.NP_DTYPES[dtype]
+    vals = np.array([add_id, 5, 7], dtype=np_dt)
+    F = oracle.fold(semiring, dtype, np.array([0, 0, 1]), np.array([0, 1, 1]), vals, 2, 2)
+    assert F.col.tolist() == [1, 1] and F.rowptr.tolist() == [0, 1, 2]
+    # [mul_id] x [x] = [x]
+    I = oracle.fold(semiring, dtype, np.array([0]), np.array([0]), np.array([mul_id], dtype=np_dt), 1, 1)
+    for x in (3, 11):
+        X = oracle.fold(semiring, dtype, np.array([0]), np.array([0]), np.array([x], dtype=np_dt), 1, 1)
+        assert oracle.spgemm(semiring, dtype, I, X).val.tolist() == [x]
+    if dtype == "i32":
+        assert 2 * add_id <= np.iinfo(np.int32).max
