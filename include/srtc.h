@@ -281,7 +281,8 @@ srtc_status srtc_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, i
  *   40 m + 32 (m + nnz/T) + 16 (nnz/T) s
  * bytes (m rows of A, s columns of C, T = 32..256 nonzeros per work item);
  * a product needing more than the buffer returns SRTC_ERR_TOO_LARGE.
- * SRTC_VALIDATE is not applied here (validation allocates).  Fully
+ * SRTC_VALIDATE is not applied here (validation allocates), and the call
+ * leaves no srtc_profile record (it takes no HIP events).  Fully
  * asynchronous.  Every call on a device shares that device's buffer and
  * leaves its contents behind; calls that overlap on one device (two
  * streams, two threads or two contexts) race and must be ordered by the

@@ -490,6 +490,8 @@ void spmm_fixed(Ctx *c, int sr, int dt, IdVal id, const CsrView &A, const void *
   // every plan array is written before it is read, so the previous call's
   // contents need no clearing
   pl.build_in(A, s_width, c->fixed_scratch, st);
+  // no profile record: its HIP events are resources this call must not take
+  pl.ctx = nullptr;
   spmm_with_plan(pl, sr, dt, id, A, X, s_width, Y, 0, accumulate, nullptr, nullptr, nullptr, nullptr, st);
 }
 
