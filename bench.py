@@ -383,7 +383,7 @@ def run_rmat18(args):
     elif not args.no_autotune:
         A32 = ctx.fold("plus_times", coo32, "ij", "i", "j")
         for dt, A in (("f64", A64), ("f32", A32)):
-            best, times = ctx.autotune("plus_times", A, A, reps=2)
+            best, times = ctx.autotune("plus_times", A, A, reps=10)
             sched[dt] = best
             log(f"autotune {dt}: best={best} times_ms={np.round(times, 2).tolist()}")
         del A32
@@ -720,7 +720,8 @@ def run_selector(args):
                                   torch.as_tensor(v, device="cuda"), (n, n)), "ij", "i", "j")
         Ap = ctx.fold(sr, srtc.COO(torch.as_tensor(dst[sel].astype(np.int64) * n + src[sel], device="cuda"),
                                    torch.as_tensor(v[sel], device="cuda"), (prow, n)), "ij", "i", "j")
-        f, t = S.collect(ctx, sr, Ap, B, reps=2)
+        # the ground truth of the held-out regret: median of 10 after a warm-up
+        f, t = S.collect(ctx, sr, Ap, B, reps=10)
         ev = S.evaluate(ctx, f[None, :], t[None, :], fixed)
         rp = Ap.rowptr
         nb = torch.diff(B.rowptr)

@@ -97,7 +97,8 @@ def test_selector_held_out_regret_and_gain():
     Xh, Th, names = [], [], []
     held = list(_mats(ctx, range(4000, 4032))) + list(_panels(ctx, 19, range(100, 103)))
     for name, sr, dt, A, B, _ in held:
-        f, t = S.collect(ctx, sr, A, B, reps=3)
+        # ground truth for the regret: median of 10 timings after a warm-up
+        f, t = S.collect(ctx, sr, A, B, reps=10)
         Xh.append(f)
         Th.append(t)
         names.append(name)
