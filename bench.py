@@ -9,11 +9,15 @@ one batch of synthetic input already resident in HBM):
     int32 (weights U[1,100]): per product the fold of the COO edge list to
     CSR, the features and the learned selector's schedule choice, then the
     symbolic, numeric and compaction passes of every row panel (C has
-    2.4e10 entries, more than one GPU holds in fp64, so it is streamed in
+    2.65e10 entries, more than one GPU holds in fp64, so it is streamed in
     panels of at most --panel-products products and each panel is
     released once handed over)
   * the selector is trained in the same run, before the timed steps, on
-    timings of generated matrices and R-MAT 17-19 row panels
+    timings of generated matrices and R-MAT 17-19 row panels; after the
+    timed steps every schedule is timed on the full fp32 and int32 products
+    (a matrix the selector never saw), giving its regret against the
+    exhaustive tuner and its gain over the best fixed schedule
+    (config.selector.held_out_rmat21; --no-regret skips it)
 Metric: semiring ops per second (one op = one (x) and one (+); SpGEMM ops =
 products A_ik*B_kj), aggregated over the step.  Other workloads:
 --workload rmat18 | rmat20_sssp | batch512 | selector | masked18 | apsp2048 |
@@ -301,10 +305,50 @@ def run_rmat21(args):
                       "abcd": [0.57, 0.19, 0.19, 0.05], "products_per_AxA": products, "nnz_C": nnz_out,
                       "panel_products": budget, "selector": sel_info},
            "roofline": roofline_of(prof)}
+    if args.schedule < 0 and not args.no_regret:
+        sel_info["held_out_rmat21"] = held_out_regret(ctx, coo, sel_info, budget)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline_sampled(n, src, dst, vals, kinds, wrow, args.cpu_seconds, synth.SEED_CFG4)
     return out
+
+
+def held_out_regret(ctx, coo, sel_info, budget):
+    """The selector on the matrix it never saw: the full R-MAT 21 square in
+    (+,x) fp32 and (min,+) int32, every schedule timed by streaming the whole
+    product in panels (one warm-up, then the median of 3; a schedule whose
+    warm-up takes over 3x the best one so far keeps its warm-up time, which
+    cannot change the best).  Regret = T_pick / T_best - 1; gain = T_fixed /
+    T_pick with the best fixed schedule of the training set.  Untimed."""
+    import torch
+    import paper_1512_00066_amd as srtc
+    res = {}
+    for sr, dt in (("plus_times", "f32"), ("min_plus", "i32")):
+        Af = ctx.fold(sr, coo[dt], "ij", "i", "j")
+
+        def once(sch):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.contract_panels(sr, "ik", Af, "kj", Af, "ij", lambda r0, P: None, panel_products=budget,
+                                schedule=sch)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3
+
+        times = []
+        for sch in range(srtc.NUM_SCHEDULES):
+            w = once(sch)
+            best = min(times) if times else w
+            times.append(w if w > 3 * best else float(np.median([once(sch) for _ in range(3)])))
+            log(f"held-out R-MAT 21 {dt} schedule {sch}: {times[-1]:.1f} ms")
+        pick = sel_info["picks"][dt]
+        fixed = sel_info.get("fixed_schedule", pick)
+        res[dt] = {"times_ms": [round(x, 1) for x in times], "pick": pick, "best": int(np.argmin(times)),
+                   "regret": round(times[pick] / min(times) - 1.0, 4),
+                   "gain_over_fixed": round(times[fixed] / times[pick], 4)}
+        log(f"held-out R-MAT 21 {dt}: pick {pick} best {res[dt]['best']} regret {res[dt]['regret']} "
+            f"gain over fixed schedule {fixed} {res[dt]['gain_over_fixed']}")
+        del Af
+    return res
 
 
 def cpu_baseline_sampled(n, src, dst, vals, kinds, w, seconds, seed):
@@ -1261,6 +1305,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--hub-tile", type=int, default=0, help="rmat18: hub block formed on the matrix cores")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-regret", action="store_true",
+                    help="rmat21: skip timing every schedule on the full product (the selector's held-out regret)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--selector-matrices", type=int, default=2000)
     ap.add_argument("--selector-epochs", type=int, default=400)
