@@ -18,6 +18,9 @@ one batch of synthetic input already resident in HBM):
     (a matrix the selector never saw), giving its regret against the
     exhaustive tuner and its gain over the best fixed schedule
     (config.selector.held_out_rmat21; --no-regret skips it)
+  * beside it, the batched form of 512 uneven ER instances against the same
+    work as per-instance calls (config.batched_vs_plain, its own timing;
+    --no-batch-comparison skips it)
 Metric: semiring ops per second (one op = one (x) and one (+); SpGEMM ops =
 products A_ik*B_kj), aggregated over the step.  Other workloads:
 --workload rmat18 | rmat20_sssp | batch512 | selector | masked18 | apsp2048 |
@@ -307,10 +310,31 @@ def run_rmat21(args):
            "roofline": roofline_of(prof)}
     if args.schedule < 0 and not args.no_regret:
         sel_info["held_out_rmat21"] = held_out_regret(ctx, coo, sel_info, budget)
+    if not args.no_batch_comparison:
+        del coo
+        out["config"]["batched_vs_plain"] = batch_comparison(args)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline_sampled(n, src, dst, vals, kinds, wrow, args.cpu_seconds, synth.SEED_CFG4)
     return out
+
+
+def batch_comparison(args):
+    """The batched form against per-instance calls (the 512 uneven ER
+    instances of --workload batch512: a (min,+) A.A and an 8-source
+    Bellman-Ford fixpoint each, per-instance schedules from the exhaustive
+    tuner), 2 timed steps after a warm-up, reported beside the default line
+    (its own timing; not part of the line's value)."""
+    import copy
+    a2 = copy.copy(args)
+    a2.steps, a2.warmup, a2.no_cpu_baseline, a2.schedule = 2, 1, True, -1
+    o = run_batch512(a2)
+    c = o["config"]
+    return {"workload": c["workload"], "instances": c["instances"], "products": c["products"],
+            "batched_ms_per_step": round(o["ms_per_step"], 2),
+            "per_instance_ms_per_step": round(c["per_instance_ms_per_step"], 2),
+            "speedup": round(c["batched_speedup"], 3), "batched_semiring_ops_per_s": o["value"],
+            "dominant_kernel": o["roofline"]["kernel"], "dominant_frac": o["roofline"]["frac"]}
 
 
 def held_out_regret(ctx, coo, sel_info, budget):
@@ -1305,6 +1329,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--hub-tile", type=int, default=0, help="rmat18: hub block formed on the matrix cores")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch-comparison", action="store_true",
+                    help="rmat21: skip the batched-vs-per-instance comparison of the 512 ER instances")
     ap.add_argument("--no-regret", action="store_true",
                     help="rmat21: skip timing every schedule on the full product (the selector's held-out regret)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
