@@ -163,9 +163,13 @@ def roofline_of(prof, dominant=None):
                 traffic = k.get("hbm_bytes_per_launch")
         except Exception:
             traffic = None
-    return {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_launch_ms": round(tms / cnt, 4),
-            "algorithmic_bytes_per_launch": round(by / cnt), "launches": cnt}
+    rec = {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_launch_ms": round(tms / cnt, 4),
+           "algorithmic_bytes_per_launch": round(by / cnt), "launches": cnt}
+    if traffic:
+        # the measured form: counted HBM bytes over the same launch time
+        rec["traffic_frac"] = round(traffic / (tms / cnt / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    return rec
 
 
 WORKLOAD_TAG = [""]
@@ -1303,10 +1307,16 @@ def copy_calibration(args):
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(args.steps):
         dst.copy_(src)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": args.steps}), flush=True)
+    ms = e0.elapsed_time(e1) / args.steps
+    # the achievable HBM rate of a plain copy (bytes read + written per second)
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": args.steps,
+                      "ms_per_copy": round(ms, 4), "copy_GBps": round(2 * nbytes / (ms / 1e3) / 1e9, 1)}), flush=True)
 
 
 def main():
