@@ -214,14 +214,14 @@ def rmat21():
     return src, dst
 
 
-@pytest.mark.parametrize("semiring,dtype,heavy,frac", [("plus_times", "f64", 300, 1e-3),
-                                                         ("plus_times", "f32", 100, 5e-4),
-                                                         ("min_plus", "i32", 100, 5e-4)])
+@pytest.mark.parametrize("semiring,dtype,heavy,frac", [("plus_times", "f64", 300, 1e-2),
+                                                         ("plus_times", "f32", 300, 1e-2),
+                                                         ("min_plus", "i32", 300, 1e-2)])
 def test_rmat21_square_in_panels_sampled_rows(rmat21, semiring, dtype, heavy, frac):
     """R-MAT scale 21 (edge factor 16) A.A in full, streamed in row panels
     of at most 8e9 products as the benchmark runs it (schedule chosen by the
-    library); the heaviest rows and a seeded random sample are checked
-    against the oracle computing just those rows."""
+    library); the 300 heaviest rows and a seeded 1% random sample of rows
+    are checked against the oracle computing just those rows."""
     src, dst = rmat21
     n = 1 << 21
     v = synth.edge_values(dtype, src.size, synth.SEED_CFG4, tag=21, lo=1, hi=100)
