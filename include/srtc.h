@@ -161,8 +161,9 @@ typedef void (*srtc_free_fn)(void *user, void *ptr);
 typedef struct srtc_ctx srtc_ctx;
 
 /* Number of SpGEMM schedules (the variant/binning presets the autotuner and
- * the selector choose among). */
+ * the selector choose among); a schedule is named by its index. */
 #define SRTC_NUM_SCHEDULES 8
+typedef int32_t srtc_schedule; /* 0..SRTC_NUM_SCHEDULES-1 */
 #define SRTC_NUM_FEATURES 32
 
 typedef struct srtc_opts {
@@ -484,7 +485,7 @@ srtc_status srtc_apsp_tiskin(srtc_ctx *ctx, const void *add_id, const srtc_tenso
 srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
                                 int32_t ninst, const srtc_tensor *As, const srtc_tensor *Bs,
                                 srtc_tensor *Cs, const char *ia, const char *ib, const char *ic,
-                                const int32_t *scheds, const srtc_opts *opts, void *stream);
+                                const srtc_schedule *scheds, const srtc_opts *opts, void *stream);
 
 /* Batched Bellman-Ford: X_b <- X_b (+) A_b (x) X_b for every instance until
  * each is unchanged; converged instances drop out.  All X_b have the same
@@ -524,7 +525,7 @@ srtc_status srtc_features(srtc_ctx *ctx, srtc_semiring sr, const srtc_tensor *A,
  * NULL). */
 srtc_status srtc_autotune(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
                           const srtc_tensor *A, const srtc_tensor *B, int32_t reps,
-                          int32_t *best, float *times_ms, void *stream);
+                          srtc_schedule *best, float *times_ms, void *stream);
 
 /* Learned selector, the automatically adjusted performance model Section 7
  * proposes (fitted to measured times instead of Section 5.1's analytic
@@ -533,7 +534,7 @@ srtc_status srtc_autotune(srtc_ctx *ctx, srtc_semiring sr, const void *add_id,
  * on the GPU (the network stays on the device; one 128-byte upload, one
  * kernel, one 4-byte read on the context's current stream).
  * SRTC_ERR_UNSUPPORTED if no network is loaded. */
-srtc_status srtc_select(srtc_ctx *ctx, const float *features, int32_t *schedule);
+srtc_status srtc_select(srtc_ctx *ctx, const float *features, srtc_schedule *schedule);
 
 typedef struct srtc_train_cfg {
   int32_t epochs;      /* passes over the data */

@@ -214,7 +214,7 @@ extern "C" {
 
 srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int32_t ninst,
                                 const srtc_tensor *As, const srtc_tensor *Bs, srtc_tensor *Cs, const char *ia,
-                                const char *ib, const char *ic, const int32_t *scheds, const srtc_opts *opts,
+                                const char *ib, const char *ic, const srtc_schedule *scheds, const srtc_opts *opts,
                                 void *stream) {
   return guard(ctx, [&] {
     if (ninst <= 0 || !As || !Bs || !Cs) fail(SRTC_ERR_ARG, "batch: bad arguments");

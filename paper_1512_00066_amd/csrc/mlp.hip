@@ -359,7 +359,7 @@ srtc_status srtc_selector_train(srtc_ctx *ctx, const float *X, const float *T, i
   });
 }
 
-srtc_status srtc_select(srtc_ctx *ctx, const float *features, int32_t *schedule_out) {
+srtc_status srtc_select(srtc_ctx *ctx, const float *features, srtc_schedule *schedule_out) {
   return guard(ctx, [&] {
     if (!features || !schedule_out) fail(SRTC_ERR_ARG, "select: null");
     Ctx *c = &ctx->c;

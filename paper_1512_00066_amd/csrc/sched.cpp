@@ -43,7 +43,7 @@ srtc_status srtc_features(srtc_ctx *ctx, srtc_semiring sr, const srtc_tensor *A,
 }
 
 srtc_status srtc_autotune(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, const srtc_tensor *A,
-                          const srtc_tensor *B, int32_t reps, int32_t *best, float *times_ms, void *stream) {
+                          const srtc_tensor *B, int32_t reps, srtc_schedule *best, float *times_ms, void *stream) {
   return guard(ctx, [&] {
     const CsrView a = matrix_view(A, "A"), b = matrix_view(B, "B");
     if (A->dtype != B->dtype) fail(SRTC_ERR_DTYPE, "A and B value types differ");
