@@ -183,15 +183,38 @@ template <int BS, class V> struct Chunk {
 // just increments), so the search is paid once per batch of U products, not
 // per product, and a lane keeps U independent loads in flight.  Gathering a
 // batch and consuming it are separate steps, so a caller can issue the loads
-// early and use them later.
+// early and use them later.  REC: B's entries are read from rB, (column,
+// value) records, instead of the two arrays.
 template <int U, class V> struct Batch {
   int32_t j[U];
   V a[U], b[U];
 };
 
-template <int BS, int U, bool VALS, class V>
+// B entries of semirings with 4-byte values as 8-byte (column, value bits)
+// records: a product's column and value then come from one cache line.  In
+// the dense windows most B segments are shorter than a line, so with the two
+// arrays a product touched two lines.  (For 8-byte values, 12- and 16-byte
+// records measured slower than the two arrays.)
+template <class SR> constexpr bool b_records() {
+  return SR::HAS_VALS && sizeof(typename SR::val_t) == 4;
+}
+
+// r[i] = entry rowptr[0] + i of B, for the n = nnz entries of the view (the
+// row pointers of a view into a larger matrix need not start at 0)
+template <class V>
+__global__ void pack_records(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ c,
+                             const V *__restrict__ v, int64_t n, uint2 *__restrict__ r) {
+  static_assert(sizeof(V) == 4, "4-byte values");
+  const int64_t lo = rowptr[0];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = make_uint2((uint32_t)c[lo + i], __builtin_bit_cast(uint32_t, v[lo + i]));
+}
+
+template <int BS, int U, bool VALS, class V, bool REC = false>
 __device__ __forceinline__ void gather_batch(const int32_t *__restrict__ cB, const V *__restrict__ vB, int cnt,
-                                             int32_t total, const Chunk<BS, V> &L, int32_t base, Batch<U, V> &g) {
+                                             int32_t total, const Chunk<BS, V> &L, int32_t base, Batch<U, V> &g,
+                                             const uint2 *__restrict__ rB = nullptr) {
+  static_assert(!REC || (VALS && sizeof(V) == 4), "records hold 4-byte values");
   const int32_t q0 = base + (int32_t)threadIdx.x * U;
   // largest lo with off[lo] <= q0 (off is non-decreasing, off[0] = 0)
   int lo = 0;
@@ -201,8 +224,9 @@ __device__ __forceinline__ void gather_batch(const int32_t *__restrict__ cB, con
   }
   int32_t nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
   int64_t pos = L.start[lo] + (q0 - L.off[lo]);
-  const int32_t *pc = cB + pos;
-  const V *pv = VALS ? vB + pos : nullptr;
+  const int32_t *pc = REC ? nullptr : cB + pos;
+  const V *pv = VALS && !REC ? vB + pos : nullptr;
+  const uint2 *pr = REC ? rB + pos : nullptr;
   V av = VALS ? L.a[lo] : V{};
 #pragma unroll
   for (int u = 0; u < U; u++) {
@@ -219,18 +243,31 @@ __device__ __forceinline__ void gather_batch(const int32_t *__restrict__ cB, con
             nxt = lo + 1 < cnt ? L.off[lo + 1] : INT32_MAX;
           } while (q >= nxt);
           pos = L.start[lo] + (q - L.off[lo]);
-          pc = cB + pos;
-          if (VALS) pv = vB + pos;
+          if constexpr (REC) {
+            pr = rB + pos;
+          } else {
+            pc = cB + pos;
+            if (VALS) pv = vB + pos;
+          }
           if (VALS) av = L.a[lo];
+        } else if constexpr (REC) {
+          pr++;
         } else {
           pc++;
           if (VALS) pv++;
         }
       }
-      g.j[u] = *pc;
-      if (VALS) {
+      if constexpr (REC) {
+        const uint2 e = *pr;
+        g.j[u] = (int32_t)e.x;
         g.a[u] = av;
-        g.b[u] = *pv;
+        g.b[u] = __builtin_bit_cast(V, e.y);
+      } else {
+        g.j[u] = *pc;
+        if (VALS) {
+          g.a[u] = av;
+          g.b[u] = *pv;
+        }
       }
     }
   }
@@ -247,23 +284,24 @@ __device__ __forceinline__ void consume_batch(const Batch<U, V> &g, int32_t base
 // All products of a laid-out chunk from the tile starting at product `base`
 // (a multiple of BS*U) on.  PIPE: the next tile's search and loads are
 // issued before the current tile is consumed (twice the batch registers).
-template <int BS, int U, bool VALS, class V, bool PIPE = false, class F>
+template <int BS, int U, bool VALS, class V, bool PIPE = false, bool REC = false, class F>
 __device__ __forceinline__ void walk_chunk(const int32_t *__restrict__ cB, const V *__restrict__ vB, int cnt,
-                                           int32_t total, const Chunk<BS, V> &L, F &&f, int32_t base = 0) {
+                                           int32_t total, const Chunk<BS, V> &L, F &&f, int32_t base = 0,
+                                           const uint2 *__restrict__ rB = nullptr) {
   if constexpr (PIPE) {
     if (base >= total) return;
     Batch<U, V> g;
-    gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, base, g);
+    gather_batch<BS, U, VALS, V, REC>(cB, vB, cnt, total, L, base, g, rB);
     for (int32_t b0 = base; b0 < total; b0 += BS * U) {
       Batch<U, V> h = g;
-      if (b0 + BS * U < total) gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, b0 + BS * U, h);
+      if (b0 + BS * U < total) gather_batch<BS, U, VALS, V, REC>(cB, vB, cnt, total, L, b0 + BS * U, h, rB);
       consume_batch<BS, U, V>(g, b0, total, f);
       g = h;
     }
   } else {
     for (int32_t b0 = base; b0 < total; b0 += BS * U) {
       Batch<U, V> g;
-      gather_batch<BS, U, VALS, V>(cB, vB, cnt, total, L, b0, g);
+      gather_batch<BS, U, VALS, V, REC>(cB, vB, cnt, total, L, b0, g, rB);
       consume_batch<BS, U, V>(g, b0, total, f);
     }
   }
@@ -294,12 +332,13 @@ __device__ __forceinline__ int32_t layout_chunk(int32_t len, int64_t st, V a, Ch
 // their B segments are laid end to end by a block scan and the threads walk
 // that flattened range, so the work per thread is balanced whatever the
 // segment lengths.
-template <int BS, bool VALS, class V, int U = WALK_U, bool PIPE = false, class F>
+template <int BS, bool VALS, class V, int U = WALK_U, bool PIPE = false, bool REC = false, class F>
 __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, const int32_t *__restrict__ cA,
                                              const V *__restrict__ vA, const int64_t *__restrict__ rpB,
                                              const int32_t *__restrict__ cB, const V *__restrict__ vB,
                                              int64_t i, const int32_t *__restrict__ woff, int nwin, int w,
-                                             int w_end, Chunk<BS, V> &L, F &&f) {
+                                             int w_end, Chunk<BS, V> &L, F &&f,
+                                             const uint2 *__restrict__ rB = nullptr) {
   const int t = threadIdx.x;
   const int64_t pa = rpA[i], pe = rpA[i + 1];
   for (int64_t p0 = pa; p0 < pe; p0 += BS) {
@@ -321,7 +360,7 @@ __device__ __forceinline__ void for_products(const int64_t *__restrict__ rpA, co
       if (VALS) a = vA[p0 + t];
     }
     const int32_t total = layout_chunk<BS, VALS, V>(len, st, a, L);
-    walk_chunk<BS, U, VALS, V, PIPE>(cB, vB, cnt, total, L, f);
+    walk_chunk<BS, U, VALS, V, PIPE, REC>(cB, vB, cnt, total, L, f, 0, rB);
     __syncthreads();
   }
 }
@@ -845,7 +884,9 @@ __device__ __forceinline__ int64_t extract_ranked(const typename SR::acc_t *racc
 // entries): windows without products are skipped, and runs of sparse
 // windows become ranked groups (above), so a row with few outputs spread
 // over many windows pays for a few passes instead of one per window.
-// Longer A rows are re-read in chunks for every window.
+// Longer A rows are re-read in chunks for every window.  For 4-byte values
+// B is read from rB, its entries as (column, value) records starting at
+// position rowptr[0].
 // At most 128 VGPRs (four waves per SIMD): two 512-thread blocks per CU when
 // the LDS allows, one 1024-thread block otherwise (at 129 registers the
 // fp64 instance lost half its blocks).
@@ -860,11 +901,14 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
                                                 OutRows orows, int32_t *__restrict__ cC,
                                                 typename SR::val_t *__restrict__ vC, typename SR::acc_t id,
                                                 int64_t *__restrict__ row_kept, int32_t *any_short,
-                                                int64_t *ctr, int step) {
+                                                int64_t *ctr, int step, const uint2 *__restrict__ rB) {
   using V = typename SR::val_t;
   using A = typename SR::acc_t;
   using R = RankWin<SR, BS, W>;
   constexpr bool VALS = SR::HAS_VALS;
+  constexpr bool REC = b_records<SR>();
+  // records indexed by B position
+  if constexpr (REC) rB -= rpB[0];
   constexpr int NWORD = W / 32;
   constexpr int NV = VALS ? W : 1;
   __shared__ __align__(16) A vals[NV];
@@ -1009,7 +1053,7 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
       }
       int32_t total = layout_chunk<BS, VALS, V>(o_nxt - o_cur, rb + o_cur, av, L);
       Batch<WALK_U, V> g;
-      gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, 0, g);
+      gather_batch<BS, WALK_U, VALS, V, REC>(cB, vB, cnt, total, L, 0, g, rB);
       while (ga < nwin) {
         int na = nwin, nb = nwin;
         bool ndense = true;
@@ -1024,7 +1068,7 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
           for (int32_t b0 = 0; b0 < total; b0 += BS * WALK_U) {
             Batch<WALK_U, V> h = g;
             if (b0 + BS * WALK_U < total)
-              gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total, L, b0 + BS * WALK_U, h);
+              gather_batch<BS, WALK_U, VALS, V, REC>(cB, vB, cnt, total, L, b0 + BS * WALK_U, h, rB);
             consume_batch<BS, WALK_U, V>(g, b0, total, dense_add(c0));
             g = h;
           }
@@ -1040,7 +1084,7 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
         int32_t total_n = 0;
         if (na < nwin) {
           total_n = layout_chunk<BS, VALS, V>(o_after - o_nxt, rb + o_nxt, av, L);
-          gather_batch<BS, WALK_U, VALS, V>(cB, vB, cnt, total_n, L, 0, g);
+          gather_batch<BS, WALK_U, VALS, V, REC>(cB, vB, cnt, total_n, L, 0, g, rB);
         }
         if (dense || !R::OK)
           written += extract_window<SR, BS, W>(vals, bits, id, c0 + orows.col_off, base + written, cC, vC, red);
@@ -1058,8 +1102,8 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
       ready(true);
       for (int w = 0; w < nwin; w++) {
         const int64_t w0 = (int64_t)w * W;
-        for_products<BS, VALS, V, WALK_U, true>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin, w,
-                                                w + 1, L, dense_add(w0));
+        for_products<BS, VALS, V, WALK_U, true, REC>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin,
+                                                     w, w + 1, L, dense_add(w0), rB);
         written += extract_window<SR, BS, W>(vals, bits, id, w0 + orows.col_off, base + written, cC, vC, red);
       }
     }
@@ -1411,14 +1455,14 @@ template <class SR> struct NumLaunch {
   }
   template <int BS, int W>
   static void dense(const Launch &L, int64_t rows, const int32_t *list, const int64_t *info, int bin,
-                    const CsrView &Am, const CsrView &Bm, const int32_t *woff, int nwin, OutRows orows,
-                    int32_t *cC, V *vC, A id, int64_t *kept, int32_t *any_short, int64_t *ctr) {
+                    const CsrView &Am, const CsrView &Bm, const int32_t *woff, int nwin, const uint2 *rB,
+                    OutRows orows, int32_t *cC, V *vC, A id, int64_t *kept, int32_t *any_short, int64_t *ctr) {
     if (rows == 0) return;
     constexpr int NV = SR::HAS_VALS ? W : 1;
     const int stat = NV * (int)sizeof(A) + W / 8 + (int)sizeof(Chunk<BS, V>) + (RankWin<SR, BS, W>::OK ? NWPW * 8 : 8) + 64;
     num_dense<SR, BS, W><<<L.grid(rows, stat, BS), BS, 0, L.s>>>(
         list, info, bin, Am.rowptr, Am.col, (const V *)Am.val, Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.n, woff,
-        nwin, orows, cC, vC, id, kept, any_short, ctr, 1);
+        nwin, orows, cC, vC, id, kept, any_short, ctr, 1, rB);
     SRTC_LAUNCH_CHECK("num_dense");
   }
 };
@@ -1569,6 +1613,15 @@ void numeric_launch(Ctx *c, typename SR::acc_t id, const CsrView &Am, const CsrV
       SRTC_LAUNCH_CHECK("build_woff");
     }
     const int32_t *wo = woff.as<int32_t>();
+    Buf recs;
+    if constexpr (b_records<SR>()) {
+      ProfScope pr(c, "spgemm.b_records", 16.0 * Bm.nnz, s);
+      recs = Buf(c, sizeof(uint2) * (size_t)std::max<int64_t>(Bm.nnz, 1));
+      pack_records<V><<<gridn(Bm.nnz), 256, 0, s>>>(Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.nnz,
+                                                    recs.as<uint2>());
+      SRTC_LAUNCH_CHECK("pack_records");
+    }
+    const uint2 *rb = recs.as<uint2>();
     // the window-table lookups (8 B per A entry and window) are overhead of
     // the method, not bytes the product must move: they stay out of the count
     ProfScope ps(c, pname(5).c_str(), num_bytes(5), s);
@@ -1576,12 +1629,12 @@ void numeric_launch(Ctx *c, typename SR::acc_t id, const CsrView &Am, const CsrV
     if (S.dense_wide == 1) {
       // the widest window fills the LDS (one block per CU): 1024 threads keep
       // 16 waves per CU in flight instead of 8
-      NL::template dense<1024, W1>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      NL::template dense<1024, W1>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rb, rpC, cC, vC, id, kp, fl, ctr2 + 5);
     } else if (S.dense_wide == 2) {
-      NL::template dense<512, W2>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      NL::template dense<512, W2>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rb, rpC, cC, vC, id, kp, fl, ctr2 + 5);
     } else {
-      if (S.dense_bs == 512) NL::template dense<512, W0>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
-      else NL::template dense<256, W0>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      if (S.dense_bs == 512) NL::template dense<512, W0>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rb, rpC, cC, vC, id, kp, fl, ctr2 + 5);
+      else NL::template dense<256, W0>(L, hinfo2[5], lst, info2, 5, Am, Bm, wo, nwin, rb, rpC, cC, vC, id, kp, fl, ctr2 + 5);
     }
   }
 }
