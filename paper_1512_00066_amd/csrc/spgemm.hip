@@ -496,7 +496,9 @@ __global__ void __launch_bounds__(BS) sym_bitmap(const int32_t *__restrict__ lis
 
 // -------------------------------------------------------------- numeric --
 // Output bookkeeping: row_kept[i] = entries written; any_short is raised if
-// some result equalled the identity and was dropped.
+// some result equalled the identity and was dropped, or was written with
+// column -1 (ranked groups of the dense windows), so that a compaction
+// follows.
 
 // EXTRACT: 0 = sorted (kept entries compacted, then bitonic-sorted by column), 2 = table order
 template <class SR, int BS, int TBL, int EXTRACT>
@@ -808,7 +810,7 @@ __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint
 // of the bitmap's popcounts then ranks every touched column (its position in
 // column order), and the second pass adds each product into a compact array
 // at its column's rank.  The array is already in column order, so extraction
-// only drops identity results.  The bitmap, the per-word rank prefixes, the
+// writes it out as it stands.  The bitmap, the per-word rank prefixes, the
 // columns and the accumulators share the LDS of the dense window; SPANW (the
 // windows one run may cover) is what the bitmap and prefixes leave room for.
 template <class SR, int BS, int W> struct RankWin {
@@ -856,31 +858,29 @@ __device__ __forceinline__ int32_t rank_run(const uint32_t *rbits, int32_t *rpre
   return (int32_t)tot;
 }
 
-// Extraction of a ranked group: the n accumulators are in column order, the
-// ones that are not the identity are written out (thread t takes a
-// contiguous run, ranks from one block scan); the bitmap is cleared.
-// Returns the number written (the same on every thread).
+// Extraction of a ranked group: the n accumulators are in column order and
+// each is written at its rank (thread t takes ranks t, t + BS, ..., so a
+// wave's stores are contiguous), with no count and no scan.  An identity
+// result (an exact cancellation, a clamped sum) is written with column -1
+// and raises *marked; the compaction after the numeric pass drops such
+// entries.  The bitmap is cleared.  Returns n.
 template <class SR, int BS>
-__device__ __forceinline__ int64_t extract_ranked(const typename SR::acc_t *racc, const int32_t *rcol,
+__device__ __forceinline__ int32_t extract_ranked(const typename SR::acc_t *racc, const int32_t *rcol,
                                                   uint32_t *rbits, int nbw, int n, typename SR::acc_t id,
                                                   int64_t col0, int64_t pos0, int32_t *__restrict__ cC,
-                                                  typename SR::val_t *__restrict__ vC, int64_t *red) {
-  const int per = (n + BS - 1) / BS;
-  const int r0 = threadIdx.x * per, r1 = min(r0 + per, n);
-  int64_t mine = 0;
-  for (int r = r0; r < r1; r++) mine += SR::acc_absent(racc[r], id) ? 0 : 1;
-  int64_t tot;
-  int64_t p = pos0 + block_excl_scan<BS, int64_t, false>(mine, red, &tot);
-  for (int r = r0; r < r1; r++) {
+                                                  typename SR::val_t *__restrict__ vC, int32_t *marked) {
+  bool any = false;
+  for (int r = threadIdx.x; r < n; r += BS) {
     const typename SR::acc_t v = racc[r];
-    if (SR::acc_absent(v, id)) continue;
-    cC[p] = (int32_t)(col0 + rcol[r]);
-    vC[p] = SR::out(v);
-    p++;
+    const bool absent = SR::acc_absent(v, id);
+    any |= absent;
+    cC[pos0 + r] = absent ? -1 : (int32_t)(col0 + rcol[r]);
+    vC[pos0 + r] = SR::out(v);
   }
+  if (any) atomicOr(marked, 1);
   for (int u = threadIdx.x; u < nbw; u += BS) rbits[u] = 0;
   __syncthreads();
-  return tot;
+  return n;
 }
 
 // Dense rows, window by window: W consecutive columns held in LDS as dense
@@ -1103,8 +1103,7 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
           written += extract_window<SR, BS, W>(vals, bits, id, c0 + orows.col_off, base + written, cC, vC, red);
         else
           written += extract_ranked<SR, BS>(racc, rcol, rbits, (gb - ga) * R::WPW, nrank, id, c0 + orows.col_off,
-                                            base + written,
-                                            cC, vC, red);
+                                            base + written, cC, vC, any_short);
         total = total_n;
         o_nxt = o_after;
         ga = na;
@@ -1286,7 +1285,61 @@ __global__ void build_woff(const int64_t *__restrict__ rpB, const int32_t *__res
   }
 }
 
-// Pack rows whose kept count fell short of the symbolic count.
+// Compaction after a numeric pass.  Row i of C was written as Q segments
+// (segment q from start[q m + i], len[q m + i] entries; one segment per row
+// outside the column-block path) that may fall short of the row's symbolic
+// count (identity results dropped) and may hold entries with column -1
+// (identity results of ranked groups, written in place).  The listed rows
+// (rows = null: rows 0..n-1) are counted, then packed: cnt[i] = entries of
+// row i with a column >= 0; they move in order to rp_new[i] onwards.  One
+// wave per row.
+__global__ void count_valid(const int32_t *__restrict__ rows, int64_t n, int Q, int64_t m,
+                            const int64_t *__restrict__ start, const int64_t *__restrict__ len,
+                            const int32_t *__restrict__ col, int64_t *__restrict__ cnt) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  for (int64_t r = wid; r < n; r += nw) {
+    const int64_t i = rows ? rows[r] : r;
+    int64_t acc = 0;
+    for (int q = 0; q < Q; q++) {
+      const int64_t a = start[(int64_t)q * m + i], e = a + len[(int64_t)q * m + i];
+      for (int64_t t = a + lane_id(); t < e; t += WAVE) acc += col[t] >= 0 ? 1 : 0;
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) cnt[i] = acc;
+  }
+}
+
+template <class V>
+__global__ void compact_valid(const int32_t *__restrict__ rows, int64_t n, int Q, int64_t m,
+                              const int64_t *__restrict__ start, const int64_t *__restrict__ len,
+                              const int64_t *__restrict__ rp_new, const int32_t *__restrict__ c_old,
+                              const V *__restrict__ v_old, int32_t *__restrict__ c_new, V *__restrict__ v_new) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  const uint64_t lt = lanemask_lt();
+  for (int64_t r = wid; r < n; r += nw) {
+    const int64_t i = rows ? rows[r] : r;
+    int64_t o = rp_new[i];
+    for (int q = 0; q < Q; q++) {
+      const int64_t a = start[(int64_t)q * m + i], e = a + len[(int64_t)q * m + i];
+      for (int64_t t0 = a; t0 < e; t0 += WAVE) {
+        const int64_t t = t0 + lane_id();
+        const int32_t c = t < e ? c_old[t] : -1;
+        const uint64_t mk = __ballot(c >= 0);
+        if (c >= 0) {
+          const int64_t d = o + __popcll(mk & lt);
+          c_new[d] = c;
+          v_new[d] = v_old[t];
+        }
+        o += __popcll(mk);
+      }
+    }
+  }
+}
+
+// Pack rows whose kept count fell short of a known count (the masked
+// contraction's items).
 template <class V>
 __global__ void compact_rows(const int64_t *rp_old, const int64_t *rp_new, int64_t m, const int32_t *c_old,
                              const V *v_old, int32_t *c_new, V *v_new) {
@@ -1753,14 +1806,19 @@ void spgemm_groups(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, cons
   if (flags_h[1]) fail(SRTC_ERR_DEVICE, "spgemm: numeric hash table overflow (internal invariant)");
   const int32_t short_flag = flags_h[0];
   if (short_flag) {
+    // identity results were dropped or marked: count each row's kept
+    // entries among the kp[i] written, then pack them
+    Buf kv(c, sizeof(int64_t) * (size_t)m);
+    count_valid<<<gridn(m * WAVE, 256, 16384), 256, 0, s>>>(nullptr, m, 1, m, rpC, kp, cC, kv.as<int64_t>());
+    SRTC_LAUNCH_CHECK("count_valid");
     Buf rp2(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
-    excl_scan_i64(c, kp, rp2.as<int64_t>(), m, s);
+    excl_scan_i64(c, kv.as<int64_t>(), rp2.as<int64_t>(), m, s);
     const int64_t t2 = read_i64(c, rp2.as<int64_t>() + m, s);
     Buf col2(c, sizeof(int32_t) * (size_t)std::max<int64_t>(t2, 1), out->kind);
     Buf val2(c, es * (size_t)std::max<int64_t>(t2, 1), out->kind);
-    compact_rows<V><<<gridn(m * WAVE, 256, 16384), 256, 0, s>>>(rpC, rp2.as<int64_t>(), m, cC, vC,
-                                                                 col2.as<int32_t>(), val2.as<V>());
-    SRTC_LAUNCH_CHECK("compact_rows");
+    compact_valid<V><<<gridn(m * WAVE, 256, 16384), 256, 0, s>>>(nullptr, m, 1, m, rpC, kp, rp2.as<int64_t>(), cC,
+                                                                  vC, col2.as<int32_t>(), val2.as<V>());
+    SRTC_LAUNCH_CHECK("compact_valid");
     out->rowptr = std::move(rp2);
     col = std::move(col2);
     val = std::move(val2);
@@ -1891,29 +1949,6 @@ __global__ void block_rows(const int32_t *__restrict__ rows, int64_t n, const in
   }
 }
 
-// Repack rows after identity results were dropped: listed rows of one
-// segment (from old[i], kept[i] entries) or of Q block segments (from
-// start[q m + i], kept_q[q m + i] entries each) go to new[i] onwards.
-template <class V>
-__global__ void compact_segments(const int32_t *__restrict__ rows, int64_t n, int Q, int64_t m,
-                                 const int64_t *__restrict__ start, const int64_t *__restrict__ kept,
-                                 const int64_t *__restrict__ rp_new, const int32_t *__restrict__ c_old,
-                                 const V *__restrict__ v_old, int32_t *__restrict__ c_new, V *__restrict__ v_new) {
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
-  for (int64_t r = wid; r < n; r += nw) {
-    const int64_t i = rows[r];
-    int64_t o = rp_new[i];
-    for (int q = 0; q < Q; q++) {
-      const int64_t a = start[(int64_t)q * m + i], len = kept[(int64_t)q * m + i];
-      for (int64_t t = lane_id(); t < len; t += WAVE) {
-        c_new[o + t] = c_old[a + t];
-        v_new[o + t] = v_old[a + t];
-      }
-      o += len;
-    }
-  }
-}
 
 // C = A (x) B with B cut into Q column blocks of bc columns for the rows of
 // at least thr products (the others multiply the whole B once).  Host reads:
@@ -2062,27 +2097,32 @@ void spgemm_blocked(Ctx *c, IdVal idv, const CsrView &Am, const CsrView &Bm, int
   if (flags_h[2] || flags_h[3]) fail(SRTC_ERR_DEVICE, "spgemm: symbolic hash table overflow (internal invariant)");
   if (flags_h[1]) fail(SRTC_ERR_DEVICE, "spgemm: numeric hash table overflow (internal invariant)");
   if (flags_h[0]) {
-    // identity results were dropped: per-row kept totals, then every
-    // segment moves to its packed place
-    if (nheavy > 0) {
-      block_rows<<<gridn(nheavy), 256, 0, s>>>(heavy, nheavy, keptq.as<int64_t>(), Q, m, kept.as<int64_t>(), nullptr,
-                                              nullptr);
-      SRTC_LAUNCH_CHECK("block_rows");
-    }
+    // identity results were dropped or marked: each row's kept entries
+    // over its segments (one for light rows, one per block for heavy ones),
+    // then every segment's kept entries move to their packed place
+    Buf kv(c, sizeof(int64_t) * (size_t)m);
+    fill_i64(kv.as<int64_t>(), m, 0, s);
+    if (nlight > 0)
+      count_valid<<<gridn(nlight * WAVE, 256, 16384), 256, 0, s>>>(light, nlight, 1, m, rpC, kept.as<int64_t>(), cC,
+                                                                  kv.as<int64_t>());
+    if (nheavy > 0)
+      count_valid<<<gridn(nheavy * WAVE, 256, 16384), 256, 0, s>>>(heavy, nheavy, Q, m, startq.as<int64_t>(),
+                                                                  keptq.as<int64_t>(), cC, kv.as<int64_t>());
+    SRTC_LAUNCH_CHECK("count_valid");
     Buf rp2(c, sizeof(int64_t) * (size_t)(m + 1), out->kind);
-    excl_scan_i64(c, kept.as<int64_t>(), rp2.as<int64_t>(), m, s);
+    excl_scan_i64(c, kv.as<int64_t>(), rp2.as<int64_t>(), m, s);
     const int64_t t2 = read_i64(c, rp2.as<int64_t>() + m, s);
     Buf col2(c, sizeof(int32_t) * (size_t)std::max<int64_t>(t2, 1), out->kind);
     Buf val2(c, es * (size_t)std::max<int64_t>(t2, 1), out->kind);
     if (nlight > 0)
-      compact_segments<V><<<gridn(nlight * WAVE, 256, 16384), 256, 0, s>>>(light, nlight, 1, m, rpC, kept.as<int64_t>(),
-                                                                          rp2.as<int64_t>(), cC, vC,
-                                                                          col2.as<int32_t>(), val2.as<V>());
+      compact_valid<V><<<gridn(nlight * WAVE, 256, 16384), 256, 0, s>>>(light, nlight, 1, m, rpC, kept.as<int64_t>(),
+                                                                         rp2.as<int64_t>(), cC, vC,
+                                                                         col2.as<int32_t>(), val2.as<V>());
     if (nheavy > 0)
-      compact_segments<V><<<gridn(nheavy * WAVE, 256, 16384), 256, 0, s>>>(heavy, nheavy, Q, m, startq.as<int64_t>(),
-                                                                          keptq.as<int64_t>(), rp2.as<int64_t>(), cC,
-                                                                          vC, col2.as<int32_t>(), val2.as<V>());
-    SRTC_LAUNCH_CHECK("compact_segments");
+      compact_valid<V><<<gridn(nheavy * WAVE, 256, 16384), 256, 0, s>>>(heavy, nheavy, Q, m, startq.as<int64_t>(),
+                                                                         keptq.as<int64_t>(), rp2.as<int64_t>(), cC,
+                                                                         vC, col2.as<int32_t>(), val2.as<V>());
+    SRTC_LAUNCH_CHECK("compact_valid");
     out->rowptr = std::move(rp2);
     col = std::move(col2);
     val = std::move(val2);

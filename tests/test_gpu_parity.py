@@ -5,6 +5,8 @@ own kernels and the oracle with its own code, then the results are compared
 element by element: bit-exact for (min,+), (or,and), (max,x); within the
 stated relative bounds for (+,x) (1e-12 fp64, 1e-5 fp32 against fp64)."""
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -164,6 +166,45 @@ def test_spgemm_window_groups_all_schedules(ctx, semiring, dtype, cancel):
         assert exp.rowptr[-1] < pat.rowptr[-1]
     for sch in range(srtc.NUM_SCHEDULES):
         check_csr(ctx.contract(semiring, "ik", GA, "kj", GB, "ij", schedule=sch), exp, semiring, dtype)
+
+
+@pytest.mark.parametrize("case", ["f32_cancel", "f64_cancel_column_blocks", "i32_clamp"])
+def test_spgemm_ranked_groups_with_identity_results(ctx, case):
+    """Identity results inside the ranked groups of dense rows (exact
+    cancellations of +-1 products, (min,+) sums clamped at the identity)
+    are written in place with column -1 and dropped by the compaction that
+    follows the numeric pass, also when B is cut into column blocks (the
+    heavy rows' blocks are then compacted segment by segment); every
+    schedule."""
+    semiring, dtype = ("min_plus", "i32") if case == "i32_clamp" else ("plus_times", case[:3])
+    say("ranked identity results", case)
+    (ar, ac, av, m, k), (br, bc, bv, _, n) = window_structured_pair(semiring, dtype, 63, cancel=case != "i32_clamp")
+    if case == "i32_clamp":
+        # two-hop sums of 5e8..7e8 weights mostly reach the identity
+        av = synth.edge_values("i32", ar.size, 63, 3, lo=500_000_000, hi=700_000_000)
+        bv = synth.edge_values("i32", br.size, 63, 4, lo=500_000_000, hi=700_000_000)
+    GA = gpu_fold(ctx, semiring, dtype, ar, ac, av, m, k)
+    GB = gpu_fold(ctx, semiring, dtype, br, bc, bv, k, n)
+    exp = oracle.spgemm(semiring, dtype, oracle.fold(semiring, dtype, ar, ac, av, m, k),
+                        oracle.fold(semiring, dtype, br, bc, bv, k, n))
+    ones_a, ones_b = np.ones(ar.size, np.uint8), np.ones(br.size, np.uint8)
+    pat = oracle.spgemm("or_and", "bool", oracle.fold("or_and", "bool", ar, ac, ones_a, m, k),
+                        oracle.fold("or_and", "bool", br, bc, ones_b, k, n))
+    assert exp.rowptr[-1] < pat.rowptr[-1]
+    c = ctx
+    if case == "f64_cancel_column_blocks":
+        old = os.environ.get("SRTC_COL_BLOCKS")
+        os.environ["SRTC_COL_BLOCKS"] = "3"
+        try:
+            c = srtc.Context(0)
+        finally:
+            if old is None:
+                os.environ.pop("SRTC_COL_BLOCKS", None)
+            else:
+                os.environ["SRTC_COL_BLOCKS"] = old
+    for sch in range(srtc.NUM_SCHEDULES):
+        say("  schedule", sch)
+        check_csr(c.contract(semiring, "ik", GA, "kj", GB, "ij", schedule=sch), exp, semiring, dtype)
 
 
 def wide_window_pair(semiring, dtype, seed):
