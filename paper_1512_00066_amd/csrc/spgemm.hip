@@ -717,18 +717,23 @@ __global__ void __launch_bounds__(BS) num_hash(const int32_t *__restrict__ list,
 
 // Extraction of one dense window: `bits` marks the touched columns (for the
 // boolean semiring they are the values), `vals` holds the accumulators of a
-// value semiring.  Every touched slot that does not hold the identity is
-// written out in column order; touched slots and their bits are reset.  Wave
+// value semiring.  Every touched slot is written out in column order, one
+// holding the identity (an exact cancellation, a clamped sum) with column -1
+// and *marked raised, so the compaction after the numeric pass drops it;
+// touched slots and their bits are reset.  Ranks need only the bits'
+// popcounts, not the accumulators.  Wave
 // wv owns words [wv*WPW, (wv+1)*WPW); a lane takes one word, or a part of
 // one (LPW lanes per word when a wave has more lanes than words, so no lane
 // idles), and walks its set bits; ranks come from wave scans of the
 // per-lane counts (adjacent lanes hold adjacent parts, so lane order is
 // column order) and one block-level prefix over the waves.  Returns the
-// number of entries written (the same on every thread).
+// number of entries written, marked ones included (the same on every
+// thread).
 template <class SR, int BS, int W>
 __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint32_t *bits, typename SR::acc_t id,
                                                   int64_t w0, int64_t pos0, int32_t *__restrict__ cC,
-                                                  typename SR::val_t *__restrict__ vC, int64_t *red) {
+                                                  typename SR::val_t *__restrict__ vC, int64_t *red,
+                                                  int32_t *marked) {
   using A = typename SR::acc_t;
   constexpr bool VALS = SR::HAS_VALS;
   constexpr int NW = BS / WAVE, NWORD = W / 32, WPW = NWORD / NW;
@@ -740,23 +745,13 @@ __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint
   const int wv = threadIdx.x / WAVE, l = lane_id();
   // kept entries per lane part (value semirings re-read the accumulators;
   // for the boolean one the count is the part's popcount, recomputed below)
-  int32_t cnt[VALS ? NG : 1];
   int64_t wtot = 0;
 #pragma unroll 2
   for (int g = 0; g < NG; g++) {
     const int slot = g * WAVE + l;
     const int uw = slot / LPW, sh = (slot % LPW) * BPL;
     const int u = wv * WPW + uw;
-    uint32_t wd = uw < WPW ? (bits[u] >> sh) & MASK : 0u;
-    if (VALS) {
-      uint32_t t2 = wd;
-      while (t2) {
-        const int b = __ffs(t2) - 1;
-        t2 &= t2 - 1;
-        if (SR::acc_absent(vals[u * 32 + sh + b], id)) wd &= ~(1u << b);
-      }
-      cnt[g] = __popc(wd);
-    }
+    const uint32_t wd = uw < WPW ? (bits[u] >> sh) & MASK : 0u;
     wtot += wave_sum((int32_t)__popc(wd));
   }
   if (l == 0) red[wv] = wtot;
@@ -769,14 +764,13 @@ __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint
     tot += x;
   }
   int64_t pos = pos0 + before;
+  bool any = false;
 #pragma unroll 2
   for (int g = 0; g < NG; g++) {
     const int slot = g * WAVE + l;
     const int uw = slot / LPW, sh = (slot % LPW) * BPL;
     const int u = wv * WPW + uw;
-    int32_t c;
-    if constexpr (VALS) c = cnt[g];
-    else c = uw < WPW ? __popc((bits[u] >> sh) & MASK) : 0;
+    const int32_t c = uw < WPW ? __popc((bits[u] >> sh) & MASK) : 0;
     const int32_t inc = wave_incl_scan(c);
     int64_t p = pos + (inc - c);
     uint32_t wd = uw < WPW ? (bits[u] >> sh) & MASK : 0u;
@@ -788,17 +782,20 @@ __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint
       wd &= wd - 1;
       const int s = u * 32 + sh + b;
       A v = (A)1;
+      bool absent = false;
       if (VALS) {
         v = vals[s];
         vals[s] = id;
-        if (SR::acc_absent(v, id)) continue;
+        absent = SR::acc_absent(v, id);
+        any |= absent;
       }
-      cC[p] = (int32_t)(w0 + s);
+      cC[p] = absent ? -1 : (int32_t)(w0 + s);
       vC[p] = SR::out(v);
       p++;
     }
     pos += lane63(inc);
   }
+  if (any) atomicOr(marked, 1);
   __syncthreads();
   return tot;
 }
@@ -1100,7 +1097,7 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
           gather_batch<BS, WALK_U, VALS, V, REC>(cB, vB, cnt, total_n, L, 0, g, rB);
         }
         if (dense || !R::OK)
-          written += extract_window<SR, BS, W>(vals, bits, id, c0 + orows.col_off, base + written, cC, vC, red);
+          written += extract_window<SR, BS, W>(vals, bits, id, c0 + orows.col_off, base + written, cC, vC, red, any_short);
         else
           written += extract_ranked<SR, BS>(racc, rcol, rbits, (gb - ga) * R::WPW, nrank, id, c0 + orows.col_off,
                                             base + written, cC, vC, any_short);
@@ -1116,7 +1113,7 @@ __global__ void __launch_bounds__(BS, 4) num_dense(const int32_t *__restrict__ l
         const int64_t w0 = (int64_t)w * W;
         for_products<BS, VALS, V, WALK_U, true, REC>(rpA, cA, vA, rpB, cB, vB, i, nwin > 1 ? woff : nullptr, nwin,
                                                      w, w + 1, L, dense_add(w0), rB);
-        written += extract_window<SR, BS, W>(vals, bits, id, w0 + orows.col_off, base + written, cC, vC, red);
+        written += extract_window<SR, BS, W>(vals, bits, id, w0 + orows.col_off, base + written, cC, vC, red, any_short);
       }
     }
     if (t == 0) {
