@@ -1373,7 +1373,7 @@ const Schedule kSchedules[SRTC_NUM_SCHEDULES] = {
     {2048, 32, 256, 2048, 4096, 0, 256, 0},   // 0 balanced
     {2048, 32, 256, 2048, 4096, 1, 256, 0},   // 1 as 0 with one wave per row in the 512-slot bin
     {2048, 32, 256, 256, 256, 1, 256, 0},     // 2 dense windows from 257 outputs
-    {8192, 32, 256, 2048, 4096, 0, 1024, 1},  // 3 hash-heavy, wide dense windows (1024-thread blocks)
+    {8192, 32, 256, 2048, 2048, 0, 1024, 1},  // 3 wide dense windows (1024-thread blocks) from 2049 outputs
     {0, 0, 0, 0, 0, 0, 256, 0},               // 4 dense windows for every row
     {2048, 32, 256, 256, 256, 0, 512, 0},     // 5 as 0, 512-thread dense windows from 257 outputs
     {2048, 32, 256, 2048, 4096, 0, 512, 2},   // 6 as 5 with narrow dense windows (more blocks per CU)
