@@ -959,6 +959,16 @@ srtc_status srtc_contract_panels(srtc_ctx *ctx, srtc_semiring sr, const void *ad
       read_to_host(c, hrp.data(), av.rowptr, sizeof(int64_t) * (size_t)(m + 1), s);
     }
     int64_t dims[2] = {m, fb.view.n};
+    // B's window tables and value records are built for the first panel and
+    // kept for the others (fb stays allocated and unchanged until the end)
+    struct KeepB {
+      Ctx *c;
+      KeepB(Ctx *cc, const CsrView &b) : c(cc) { c->keep_b = Ctx::KeptB{b.rowptr, b.col, b.val, b.m, b.n, b.nnz}; }
+      ~KeepB() {
+        c->keep_b = Ctx::KeptB{};
+        c->b_tables.clear();
+      }
+    } keep(c, fb.view);
     c->tracef("srtc_contract_panels: %lld rows, %lld products, schedule %d, at most %lld products per panel",
               (long long)m, (long long)pre[m], sched, (long long)panel_products);
     int64_t r0 = 0;

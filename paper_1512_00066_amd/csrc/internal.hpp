@@ -49,6 +49,23 @@ struct Ctx {
   int hub_tile = 0;
   // this device's fixed buffer of srtc_contract_noalloc (device address)
   void *fixed_scratch = nullptr;
+  // Tables built from B alone (window tables, value records), kept while one
+  // B multiplies several A's (the row panels of srtc_contract_panels, whose
+  // folded B stays allocated and unchanged throughout): keep_b names that B
+  // (rowptr null: nothing is kept), b_tables holds what was built from it,
+  // by key (a window width; -1 for the value records).
+  struct KeptB {
+    const int64_t *rowptr = nullptr;
+    const int32_t *col = nullptr;
+    const void *val = nullptr;
+    int64_t m = 0, n = 0, nnz = 0;
+  };
+  struct BTable {
+    int64_t key;
+    Buf buf;
+  };
+  KeptB keep_b;
+  std::vector<BTable> b_tables;
   void release_cache();
   void tracef(const char *fmt, ...);
   // per-kernel profile: HIP events around each launch on its stream, with

@@ -1366,6 +1366,29 @@ void heavy_first(Ctx *c, int32_t *seg, int64_t nb, const int64_t *w, hipStream_t
   radix_sort_pairs(c, keys.as<int64_t>(), reinterpret_cast<uint32_t *>(seg), nb, 16, s);
 }
 
+// A table built from B alone for `key` (a window width, or -1 for the value
+// records), `bytes` long: taken from the context when it keeps this B's
+// tables (the row panels of one product), built there the first time;
+// otherwise built into `local`.  build(dst) launches the kernels that fill
+// it.
+template <class Build>
+const void *b_table(Ctx *c, const CsrView &Bm, int64_t key, size_t bytes, Buf &local, Build &&build) {
+  const Ctx::KeptB &k = c->keep_b;
+  const bool kept = k.rowptr && k.rowptr == Bm.rowptr && k.col == Bm.col && k.val == Bm.val && k.m == Bm.m &&
+                    k.n == Bm.n && k.nnz == Bm.nnz;
+  if (!kept) {
+    local = Buf(c, bytes);
+    build(local.p);
+    return local.p;
+  }
+  for (const Ctx::BTable &t : c->b_tables)
+    if (t.key == key) return t.buf.p;
+  c->b_tables.push_back(Ctx::BTable{key, Buf(c, bytes)});
+  void *p = c->b_tables.back().buf.p;
+  build(p);
+  return p;
+}
+
 // Schedules: symbolic hash ceiling, numeric bin edges, extraction and dense
 // window shape.  Index = schedule id.
 const Schedule kSchedules[SRTC_NUM_SCHEDULES] = {
@@ -1484,16 +1507,17 @@ int64_t run_symbolic(const Launch &L, const Schedule &S, const CsrView &Am, cons
     const int64_t wcols = (int64_t)ww * 32;
     const int nwin = (int)((n + wcols - 1) / wcols);
     Buf woff;
-    if (nwin > 1) {
-      woff = Buf(L.c, sizeof(int32_t) * (size_t)(Bm.m * (nwin + 1)));
-      build_woff<<<gridn(Bm.m * (nwin + 1)), 256, 0, s>>>(Bm.rowptr, Bm.col, Bm.m, nwin, wcols, woff.as<int32_t>());
-      SRTC_LAUNCH_CHECK("build_woff");
-    }
+    const int32_t *wo = nullptr;
+    if (nwin > 1)
+      wo = (const int32_t *)b_table(L.c, Bm, wcols, sizeof(int32_t) * (size_t)(Bm.m * (nwin + 1)), woff, [&](void *d) {
+        build_woff<<<gridn(Bm.m * (nwin + 1)), 256, 0, s>>>(Bm.rowptr, Bm.col, Bm.m, nwin, wcols, (int32_t *)d);
+        SRTC_LAUNCH_CHECK("build_woff");
+      });
     auto kern = sym_bitmap<BS>;
     if (ww * 4 > 64 * 1024)
       SRTC_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, ww * 4));
     kern<<<L.grid(hinfo[5], stat + ww * 4, BS), BS, (size_t)ww * 4, s>>>(list, info1, 5, Am.rowptr, Am.col,
-                                                                      Bm.rowptr, Bm.col, n, ww, woff.as<int32_t>(),
+                                                                      Bm.rowptr, Bm.col, n, ww, wo,
                                                                       nwin, nnz_row, ctr1 + 5, 1);
     SRTC_LAUNCH_CHECK("sym_bitmap");
   }
@@ -1669,22 +1693,21 @@ void numeric_launch(Ctx *c, typename SR::acc_t id, const CsrView &Am, const CsrV
     const int64_t W = dense_width<SR>(S.dense_wide);
     const int nwin = (int)((n + W - 1) / W);
     Buf woff;
-    if (nwin > 1) {
-      ProfScope ps(c, "spgemm.window_table", 8.0 * (Bm.m + 1) + 4.0 * Bm.nnz + 4.0 * Bm.m * (nwin + 1), s);
-      woff = Buf(c, sizeof(int32_t) * (size_t)(Bm.m * (nwin + 1)));
-      build_woff<<<gridn(Bm.m * (nwin + 1)), 256, 0, s>>>(Bm.rowptr, Bm.col, Bm.m, nwin, W, woff.as<int32_t>());
-      SRTC_LAUNCH_CHECK("build_woff");
-    }
-    const int32_t *wo = woff.as<int32_t>();
+    const int32_t *wo = nullptr;
+    if (nwin > 1)
+      wo = (const int32_t *)b_table(c, Bm, W, sizeof(int32_t) * (size_t)(Bm.m * (nwin + 1)), woff, [&](void *d) {
+        ProfScope ps(c, "spgemm.window_table", 8.0 * (Bm.m + 1) + 4.0 * Bm.nnz + 4.0 * Bm.m * (nwin + 1), s);
+        build_woff<<<gridn(Bm.m * (nwin + 1)), 256, 0, s>>>(Bm.rowptr, Bm.col, Bm.m, nwin, W, (int32_t *)d);
+        SRTC_LAUNCH_CHECK("build_woff");
+      });
     Buf recs;
-    if constexpr (b_records<SR>()) {
-      ProfScope pr(c, "spgemm.b_records", 16.0 * Bm.nnz, s);
-      recs = Buf(c, sizeof(uint2) * (size_t)std::max<int64_t>(Bm.nnz, 1));
-      pack_records<V><<<gridn(Bm.nnz), 256, 0, s>>>(Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.nnz,
-                                                    recs.as<uint2>());
-      SRTC_LAUNCH_CHECK("pack_records");
-    }
-    const uint2 *rb = recs.as<uint2>();
+    const uint2 *rb = nullptr;
+    if constexpr (b_records<SR>())
+      rb = (const uint2 *)b_table(c, Bm, -1, sizeof(uint2) * (size_t)std::max<int64_t>(Bm.nnz, 1), recs, [&](void *d) {
+        ProfScope pr(c, "spgemm.b_records", 16.0 * Bm.nnz, s);
+        pack_records<V><<<gridn(Bm.nnz), 256, 0, s>>>(Bm.rowptr, Bm.col, (const V *)Bm.val, Bm.nnz, (uint2 *)d);
+        SRTC_LAUNCH_CHECK("pack_records");
+      });
     // the window-table lookups (8 B per A entry and window) are overhead of
     // the method, not bytes the product must move: they stay out of the count
     ProfScope ps(c, pname(5).c_str(), num_bytes(5), s);

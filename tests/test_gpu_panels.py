@@ -65,6 +65,28 @@ def test_panels_equal_the_product(ctx, semiring, dtype):
         check_csr(stitch(panels, n), exp, semiring, dtype)
 
 
+@pytest.mark.parametrize("semiring,dtype", [("plus_times", "f64"), ("plus_times", "f32"), ("min_plus", "i32")])
+def test_panels_reuse_b_tables(ctx, semiring, dtype):
+    """R-MAT 15 (32,768 columns: two to eight dense windows per row, so the
+    window tables exist) in about a dozen panels: B's window tables and value
+    records are built for the first panel and reused by the others; every
+    panel's rows equal the oracle's."""
+    scale = 15
+    n = 1 << scale
+    src, dst = synth.rmat_edges(scale, 8, 0.57, 0.19, 0.19, SEED, tag=3)
+    G, O = pair_inputs(ctx, semiring, dtype, src, dst, n, SEED, 4)
+    exp = oracle.spgemm(semiring, dtype, O, O)
+    nb = np.diff(O.rowptr)
+    budget = int(nb[O.col].sum() // 12)
+    for sch in (3, 0, 6):
+        panels = []
+        count = ctx.contract_panels(semiring, "ik", G, "kj", G, "ij", lambda r0, P: panels.append((r0, P)),
+                                    panel_products=budget, schedule=sch)
+        say("panels reusing B's tables", semiring, dtype, "schedule", sch, "count", count)
+        assert count == len(panels) >= 12
+        check_csr(stitch(panels, n), exp, semiring, dtype)
+
+
 def test_panels_single_rows_and_stop(ctx):
     n = 2000
     src, dst = synth.er_edges(n, 8.0, SEED, tag=3)
