@@ -327,7 +327,10 @@ typedef int32_t (*srtc_panel_fn)(void *user, int64_t row0, int64_t nrows, srtc_t
  * as many entries as products.  Operands are folded once and the schedule is
  * chosen once for the whole product (opts->schedule, or as srtc_contract
  * chooses from the features of all rows); every panel is one SpGEMM of its
- * rows of A with all of B, then `consume` receives it.  Rules as
+ * rows of A with all of B, then `consume` receives it.  Tables built from B
+ * alone (its window tables and value records) are built for the first panel
+ * and reused by the others, so A and B must not change until the call
+ * returns (the consumer may not write them).  Rules as
  * srtc_contract, except: no letter in all three tensors, and C lists its
  * row letters first.  SRTC_ERR_ARG if the consumer stops the product (the
  * panels handed over so far stay the consumer's).  Synchronizes a few times
