@@ -338,6 +338,9 @@ def batch_comparison(args):
             "batched_ms_per_step": round(o["ms_per_step"], 2),
             "per_instance_ms_per_step": round(c["per_instance_ms_per_step"], 2),
             "speedup": round(c["batched_speedup"], 3), "batched_semiring_ops_per_s": o["value"],
+            "batch_tuned_schedule": c["batch_tuned"]["schedule"],
+            "batch_tuned_ms_per_step": round(c["batch_tuned"]["ms_per_step"], 2),
+            "batch_tuned_speedup": round(c["batch_tuned"]["speedup_vs_per_instance"], 3),
             "dominant_kernel": o["roofline"]["kernel"], "dominant_frac": o["roofline"]["frac"]}
 
 
@@ -594,7 +597,8 @@ def run_batch512(args):
     [4,32], int32 weights [1,100]): each gets a (min,+) A.A and an 8-source
     Bellman-Ford fixpoint.  The step runs all instances batched (one set of
     persistent launches per phase); the same work as per-instance calls is
-    timed in the same run for comparison."""
+    timed in the same run for comparison, and so is the batched step with
+    one schedule for the whole batch from the batch tuner."""
     import torch
     import oracle
     import paper_1512_00066_amd as srtc
@@ -666,6 +670,27 @@ def run_batch512(args):
     srtc.lib().srtc_profile_enable(ctx._h, 0)
     t_s, its_s = timed(single, max(1, args.steps // 2))
     assert list(its_b) == list(its_s), "batched and per-instance fixpoints took different step counts"
+    # the same batched step with one schedule for the whole batch, chosen by
+    # the batch tuner (every schedule timed on the batch as a whole)
+    batch_tuned = None
+    if args.schedule < 0:
+        t0 = time.perf_counter()
+        bbest, btimes = ctx.batch_autotune("min_plus", As, As, reps=3)
+        tune_s = time.perf_counter() - t0
+
+        def batched_one():
+            Cs = ctx.batch_contract("min_plus", As, As)  # the batch tuner's cached pick
+            Xs = [x.clone() for x in X0s]
+            its = ctx.batch_fixpoint("min_plus", As, Xs, steps_per_check=4)
+            del Cs, Xs
+            return its
+
+        t_1, its_1 = timed(batched_one, args.steps)
+        assert list(its_1) == list(its_b), "the batch-tuned step took different fixpoint step counts"
+        batch_tuned = {"schedule": int(bbest), "tune_s": round(tune_s, 1),
+                       "spgemm_ms_per_schedule": [round(float(x), 2) for x in btimes],
+                       "ms_per_step": t_1 * 1e3, "speedup_vs_per_instance": t_s / t_1}
+        log(f"batch-tuned schedule {bbest}: {t_1 * 1e3:.2f} ms per step, {t_s / t_1:.2f}x the per-instance calls")
     ops_step = products + sum(it * z * nsrc for it, z in zip(its_b, nnz))
     log(f"batched {t_b * 1e3:.2f} ms, per-instance {t_s * 1e3:.2f} ms, speedup {t_s / t_b:.2f}x")
     log("kernel profile (batched steps):")
@@ -680,7 +705,8 @@ def run_batch512(args):
                       "sum_n": int(ns.sum()), "sum_nnz": int(sum(nnz)), "products": products,
                       "bf_steps_max": int(max(its_b)), "per_instance_ms_per_step": t_s * 1e3,
                       "batched_speedup": t_s / t_b, "per_instance_value": ops_step / t_s,
-                      "schedules": {int(k): int(v) for k, v in zip(*np.unique(scheds, return_counts=True))}},
+                      "schedules": {int(k): int(v) for k, v in zip(*np.unique(scheds, return_counts=True))},
+                      "batch_tuned": batch_tuned},
            "roofline": {"bound": "hbm", "kernel": nm, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                         "avg_launch_ms": round(tms / cnt, 4), "algorithmic_bytes_per_launch": round(by / cnt)}}

@@ -490,6 +490,23 @@ srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add
                                 srtc_tensor *Cs, const char *ia, const char *ib, const char *ic,
                                 const srtc_schedule *scheds, const srtc_opts *opts, void *stream);
 
+/* Exhaustive autotuner for a batch (Section 5.1's search over mappings,
+ * measured, applied to the batched problem as a whole): time every schedule
+ * on the batch's block-diagonal product, exactly as srtc_batch_contract
+ * forms it with one schedule for every instance (median of `reps` runs
+ * after one warm-up), cache the winner under that product's feature vector
+ * and return it in *best, with the median times in times_ms (host
+ * float[SRTC_NUM_SCHEDULES], may be NULL).  A later srtc_batch_contract of
+ * the same batch with scheds = NULL and opts->schedule = -1 takes the cached
+ * schedule.  Per-instance choices (srtc_autotune on each instance alone)
+ * can mispredict the batch: a small instance's own time is mostly host
+ * syncs and launch gaps that the batch pays once.  Arguments as
+ * srtc_batch_contract (no Cs; the products are discarded).  Synchronizes
+ * after every run. */
+srtc_status srtc_batch_autotune(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int32_t ninst,
+                                const srtc_tensor *As, const srtc_tensor *Bs, const char *ia, const char *ib,
+                                const char *ic, int32_t reps, srtc_schedule *best, float *times_ms, void *stream);
+
 /* Batched Bellman-Ford: X_b <- X_b (+) A_b (x) X_b for every instance until
  * each is unchanged; converged instances drop out.  All X_b have the same
  * width s.  iters_out: host array of ninst step counts. */

@@ -116,6 +116,8 @@ def lib():
                                      ctypes.c_int),
             "srtc_batch_fixpoint": ([P, ctypes.c_int, P, I32_, T, T, I64_, I32_, ctypes.POINTER(I64_), P],
                                     ctypes.c_int),
+            "srtc_batch_autotune": ([P, ctypes.c_int, P, I32_, T, T, S, S, S, I32_, ctypes.POINTER(I32_),
+                                     ctypes.POINTER(ctypes.c_float), P], ctypes.c_int),
             "srtc_features": ([P, ctypes.c_int, T, T, ctypes.POINTER(ctypes.c_float), P], ctypes.c_int),
             "srtc_autotune": ([P, ctypes.c_int, P, T, T, I32_, ctypes.POINTER(I32_), ctypes.POINTER(ctypes.c_float),
                                P], ctypes.c_int),
@@ -571,6 +573,22 @@ class Context:
         times = (ctypes.c_float * NUM_SCHEDULES)()
         st = lib().srtc_autotune(self._h, _sr(semiring), _add_id(add_id, ad.dtype), ctypes.byref(ad),
                                  ctypes.byref(bd), int(reps), ctypes.byref(best), times, self._stream())
+        self._check(st)
+        return best.value, np.array(times[:], dtype=np.float32)
+
+    def batch_autotune(self, semiring, As: List[CSR], Bs: List[CSR], reps: int = 3, add_id=None,
+                       ia: str = "ik", ib: str = "kj", ic: str = "ij"):
+        """(best schedule, median ms per schedule) for the whole batch as
+        batch_contract forms it with one schedule; the winner is cached, so a
+        later batch_contract of the batch without schedules takes it."""
+        n = len(As)
+        arrA = (_Tensor * n)(*[_desc(a) for a in As])
+        arrB = (_Tensor * n)(*[_desc(b) for b in Bs])
+        best = ctypes.c_int32(-1)
+        times = (ctypes.c_float * NUM_SCHEDULES)()
+        st = lib().srtc_batch_autotune(self._h, _sr(semiring), _add_id(add_id, arrA[0].dtype), n, arrA, arrB,
+                                       ia.encode(), ib.encode(), ic.encode(), int(reps), ctypes.byref(best), times,
+                                       self._stream())
         self._check(st)
         return best.value, np.array(times[:], dtype=np.float32)
 

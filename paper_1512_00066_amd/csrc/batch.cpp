@@ -208,6 +208,107 @@ __global__ void fill_rows(const int64_t *__restrict__ starts, const int64_t *__r
   }
 }
 
+// The operands of a batched product (srtc_batch_contract's argument rules):
+// every instance as a (row letter, column letter) CSR, borrowed or folded,
+// and the batch as one block-diagonal pair (A's columns follow B's row
+// blocks; B keeps each instance's own columns, so C comes out with
+// instance-local columns).
+struct BatchOperands {
+  int dt = 0;
+  IdVal id{};
+  std::vector<CsrOut> owned;
+  std::vector<CsrView> av, bv;
+  BlockDiag A, B;
+};
+
+void prepare_batch(Ctx *c, srtc_semiring sr, const void *add_id, int32_t ninst, const srtc_tensor *As,
+                   const srtc_tensor *Bs, const char *ia, const char *ib, const char *ic, const srtc_schedule *scheds,
+                   int validate, hipStream_t s, BatchOperands *P) {
+  if (ninst <= 0 || !As || !Bs) fail(SRTC_ERR_ARG, "batch: bad arguments");
+  if (!ia || !ib || !ic) fail(SRTC_ERR_INDEX, "batch: null index string");
+  const std::string a(ia), b(ib), cs(ic);
+  // each instance is C[ic] = A[ia] (x) B[ib] over matrices: one row, one
+  // contracted and one column letter (the instance number is the letter
+  // shared by all three tensors, Section 3.3.1)
+  if (a.size() != 2 || b.size() != 2 || cs.size() != 2 || a[0] == a[1] || b[0] == b[1] || cs[0] == cs[1])
+    fail(SRTC_ERR_INDEX, "batch: two distinct letters per matrix");
+  char kk = 0;
+  for (char ch : a)
+    if (b.find(ch) != std::string::npos) kk = ch;
+  if (!kk || cs.find(kk) != std::string::npos) fail(SRTC_ERR_INDEX, "batch: A and B must share one contracted letter");
+  const char ri = a[0] == kk ? a[1] : a[0], cj = b[0] == kk ? b[1] : b[0];
+  if (ri == cj || cs != std::string{ri, cj})
+    fail(SRTC_ERR_INDEX, "batch: C's letters must be A's free letter, then B's");
+  const int dt = As[0].dtype;
+  P->dt = dt;
+  P->id = make_id_public(sr, dt, add_id);
+  const IdVal &id = P->id;
+  for (int q = 0; q < ninst; q++) {
+    for (const srtc_tensor *t : {&As[q], &Bs[q]}) {
+      if (t->order != 2 || t->format == SRTC_DENSE) fail(SRTC_ERR_FORMAT, "batch: sparse matrices (COO or CSR) required");
+      if (t->nnz < 0 || (t->format == SRTC_CSR && (!t->rowptr || t->split != 1)) ||
+          (t->nnz > 0 && (!t->vals || (t->format == SRTC_CSR ? !t->colidx : !t->coo_keys))))
+        fail(SRTC_ERR_ARG, "batch: bad sparse operand");
+      if (t->dtype != dt) fail(SRTC_ERR_DTYPE, "batch: mixed value types");
+      if (t->dims[0] <= 0 || t->dims[1] <= 0) fail(SRTC_ERR_DIM, "batch: nonpositive dimension");
+    }
+    if (As[q].dims[a[0] == kk ? 0 : 1] != Bs[q].dims[b[0] == kk ? 0 : 1])
+      fail(SRTC_ERR_DIM, "batch: inner dimensions differ");
+    if (scheds && (scheds[q] < -1 || scheds[q] >= SRTC_NUM_SCHEDULES)) fail(SRTC_ERR_ARG, "batch: schedule id out of range");
+  }
+  if (validate || c->validate_all)
+    for (int q = 0; q < ninst; q++) {
+      validate_operand(c, sr, &As[q], "A", s, &id);
+      validate_operand(c, sr, &Bs[q], "B", s, &id);
+    }
+  // every operand as a (row letter, column letter) CSR: borrowed when it
+  // already is one, else folded (transposed) per instance
+  const std::string arow{ri}, acol{kk}, brow{kk}, bcol{cj};
+  std::vector<CsrOut> &owned = P->owned;
+  owned.reserve(2 * (size_t)ninst);
+  std::vector<CsrView> &av = P->av, &bv = P->bv;
+  av.resize(ninst);
+  bv.resize(ninst);
+  auto as_csr = [&](const srtc_tensor &t, const std::string &idx, const std::string &rows, const std::string &cols) {
+    if (t.format == SRTC_CSR && idx == rows + cols) return view_of(t);
+    std::vector<int> rm{(int)idx.find(rows[0])}, cm{(int)idx.find(cols[0])};
+    const int64_t nr = t.dims[rm[0]], nc = t.dims[cm[0]];
+    Buf keys(c, sizeof(int64_t) * (size_t)std::max<int64_t>(t.nnz, 1));
+    const int64_t *src = t.coo_keys;
+    Buf tmp;
+    if (t.format == SRTC_CSR) {
+      tmp = Buf(c, sizeof(int64_t) * (size_t)std::max<int64_t>(t.nnz, 1));
+      csr_to_keys(view_of(t), tmp.as<int64_t>(), s);
+      src = tmp.as<int64_t>();
+    }
+    remap_keys(c, src, t.nnz, 2, t.dims, 1, rm.data(), 1, cm.data(), keys.as<int64_t>(), s);
+    owned.emplace_back();
+    owned.back().kind = SCRATCH;
+    fold_keys_to_csr(c, sr, dt, id, keys.as<int64_t>(), t.vals, t.nnz, nr, nc, &owned.back(), s);
+    const CsrOut &f = owned.back();
+    return CsrView{f.m, f.n, f.nnz, f.rowptr.as<int64_t>(), f.col.as<int32_t>(), f.val.p};
+  };
+  for (int q = 0; q < ninst; q++) {
+    av[q] = as_csr(As[q], a, arow, acol);
+    bv[q] = as_csr(Bs[q], b, brow, bcol);
+  }
+  // A's columns follow B's row blocks; B keeps each instance's own columns
+  // (a row of A only reaches B rows of its instance), so C comes out with
+  // instance-local columns and every column-width cost of the SpGEMM
+  // (bitmaps, dense windows) is that of the widest instance, not of the sum
+  std::vector<int64_t> a_shift(ninst), b_shift(ninst, 0);
+  int64_t kt = 0, nn = 0;
+  for (int q = 0; q < ninst; q++) {
+    a_shift[q] = kt;
+    kt += av[q].n;
+    nn = std::max<int64_t>(nn, bv[q].n);
+  }
+  if (kt >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "batch: more than 2^31-2 inner rows in total");
+  build_block_diag(c, av, dt, a_shift, kt, &P->A, s);
+  build_block_diag(c, bv, dt, b_shift, nn, &P->B, s);
+  if (P->A.rows >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "batch: more than 2^31-2 rows in total");
+}
+
 }  // namespace
 
 extern "C" {
@@ -217,91 +318,18 @@ srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add
                                 const char *ib, const char *ic, const srtc_schedule *scheds, const srtc_opts *opts,
                                 void *stream) {
   return guard(ctx, [&] {
-    if (ninst <= 0 || !As || !Bs || !Cs) fail(SRTC_ERR_ARG, "batch: bad arguments");
-    if (!ia || !ib || !ic) fail(SRTC_ERR_INDEX, "batch: null index string");
-    const std::string a(ia), b(ib), cs(ic);
-    // each instance is C[ic] = A[ia] (x) B[ib] over matrices: one row, one
-    // contracted and one column letter (the instance number is the letter
-    // shared by all three tensors, Section 3.3.1)
-    if (a.size() != 2 || b.size() != 2 || cs.size() != 2 || a[0] == a[1] || b[0] == b[1] || cs[0] == cs[1])
-      fail(SRTC_ERR_INDEX, "batch: two distinct letters per matrix");
-    char kk = 0;
-    for (char ch : a)
-      if (b.find(ch) != std::string::npos) kk = ch;
-    if (!kk || cs.find(kk) != std::string::npos) fail(SRTC_ERR_INDEX, "batch: A and B must share one contracted letter");
-    const char ri = a[0] == kk ? a[1] : a[0], cj = b[0] == kk ? b[1] : b[0];
-    if (ri == cj || cs != std::string{ri, cj})
-      fail(SRTC_ERR_INDEX, "batch: C's letters must be A's free letter, then B's");
-    const int dt = As[0].dtype;
+    if (!Cs) fail(SRTC_ERR_ARG, "batch: bad arguments");
     srtc_opts o{-1, 1, 0, 0};
     if (opts) o = *opts;
-    const IdVal id = make_id_public(sr, dt, add_id);
     Ctx *c = &ctx->c;
     hipStream_t s = (hipStream_t)stream;
     ctx->c.stream = s;
-    for (int q = 0; q < ninst; q++) {
-      for (const srtc_tensor *t : {&As[q], &Bs[q]}) {
-        if (t->order != 2 || t->format == SRTC_DENSE) fail(SRTC_ERR_FORMAT, "batch: sparse matrices (COO or CSR) required");
-        if (t->nnz < 0 || (t->format == SRTC_CSR && (!t->rowptr || t->split != 1)) ||
-            (t->nnz > 0 && (!t->vals || (t->format == SRTC_CSR ? !t->colidx : !t->coo_keys))))
-          fail(SRTC_ERR_ARG, "batch: bad sparse operand");
-        if (t->dtype != dt) fail(SRTC_ERR_DTYPE, "batch: mixed value types");
-        if (t->dims[0] <= 0 || t->dims[1] <= 0) fail(SRTC_ERR_DIM, "batch: nonpositive dimension");
-      }
-      if (As[q].dims[a[0] == kk ? 0 : 1] != Bs[q].dims[b[0] == kk ? 0 : 1])
-        fail(SRTC_ERR_DIM, "batch: inner dimensions differ");
-      if (scheds && (scheds[q] < -1 || scheds[q] >= SRTC_NUM_SCHEDULES)) fail(SRTC_ERR_ARG, "batch: schedule id out of range");
-    }
-    if (o.validate || c->validate_all)
-      for (int q = 0; q < ninst; q++) {
-        validate_operand(c, sr, &As[q], "A", s, &id);
-        validate_operand(c, sr, &Bs[q], "B", s, &id);
-      }
-    // every operand as a (row letter, column letter) CSR: borrowed when it
-    // already is one, else folded (transposed) per instance
-    const std::string arow{ri}, acol{kk}, brow{kk}, bcol{cj};
-    std::vector<CsrOut> owned;
-    owned.reserve(2 * (size_t)ninst);
-    std::vector<CsrView> av(ninst), bv(ninst);
-    auto as_csr = [&](const srtc_tensor &t, const std::string &idx, const std::string &rows, const std::string &cols) {
-      if (t.format == SRTC_CSR && idx == rows + cols) return view_of(t);
-      std::vector<int> rm{(int)idx.find(rows[0])}, cm{(int)idx.find(cols[0])};
-      const int64_t nr = t.dims[rm[0]], nc = t.dims[cm[0]];
-      Buf keys(c, sizeof(int64_t) * (size_t)std::max<int64_t>(t.nnz, 1));
-      const int64_t *src = t.coo_keys;
-      Buf tmp;
-      if (t.format == SRTC_CSR) {
-        tmp = Buf(c, sizeof(int64_t) * (size_t)std::max<int64_t>(t.nnz, 1));
-        csr_to_keys(view_of(t), tmp.as<int64_t>(), s);
-        src = tmp.as<int64_t>();
-      }
-      remap_keys(c, src, t.nnz, 2, t.dims, 1, rm.data(), 1, cm.data(), keys.as<int64_t>(), s);
-      owned.emplace_back();
-      owned.back().kind = SCRATCH;
-      fold_keys_to_csr(c, sr, dt, id, keys.as<int64_t>(), t.vals, t.nnz, nr, nc, &owned.back(), s);
-      const CsrOut &f = owned.back();
-      return CsrView{f.m, f.n, f.nnz, f.rowptr.as<int64_t>(), f.col.as<int32_t>(), f.val.p};
-    };
-    for (int q = 0; q < ninst; q++) {
-      av[q] = as_csr(As[q], a, arow, acol);
-      bv[q] = as_csr(Bs[q], b, brow, bcol);
-    }
-    // A's columns follow B's row blocks; B keeps each instance's own columns
-    // (a row of A only reaches B rows of its instance), so C comes out with
-    // instance-local columns and every column-width cost of the SpGEMM
-    // (bitmaps, dense windows) is that of the widest instance, not of the sum
-    std::vector<int64_t> a_shift(ninst), b_shift(ninst, 0);
-    int64_t kt = 0, nn = 0;
-    for (int q = 0; q < ninst; q++) {
-      a_shift[q] = kt;
-      kt += av[q].n;
-      nn = std::max<int64_t>(nn, bv[q].n);
-    }
-    if (kt >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "batch: more than 2^31-2 inner rows in total");
-    BlockDiag A, B;
-    build_block_diag(c, av, dt, a_shift, kt, &A, s);
-    build_block_diag(c, bv, dt, b_shift, nn, &B, s);
-    if (A.rows >= 0x7fffffff) fail(SRTC_ERR_UNSUPPORTED, "batch: more than 2^31-2 rows in total");
+    BatchOperands P;
+    prepare_batch(c, sr, add_id, ninst, As, Bs, ia, ib, ic, scheds, o.validate, s, &P);
+    const int dt = P.dt;
+    const IdVal &id = P.id;
+    const std::vector<CsrView> &av = P.av, &bv = P.bv;
+    const BlockDiag &A = P.A, &B = P.B;
     // schedules: per instance (-1 chooses for that instance), else one for
     // the whole batch; instances sharing a schedule form one row group
     std::vector<int> isched(ninst);
@@ -368,6 +396,39 @@ srtc_status srtc_batch_contract(srtc_ctx *ctx, srtc_semiring sr, const void *add
       out.colidx = col + hst[q];
       out.vals = val + es * (size_t)hst[q];
     }
+  });
+}
+
+srtc_status srtc_batch_autotune(srtc_ctx *ctx, srtc_semiring sr, const void *add_id, int32_t ninst,
+                                const srtc_tensor *As, const srtc_tensor *Bs, const char *ia, const char *ib,
+                                const char *ic, int32_t reps, srtc_schedule *best, float *times_ms, void *stream) {
+  return guard(ctx, [&] {
+    Ctx *c = &ctx->c;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->c.stream = s;
+    BatchOperands P;
+    prepare_batch(c, sr, add_id, ninst, As, Bs, ia, ib, ic, nullptr, 0, s, &P);
+    // the block-diagonal pair as two CSR descriptors for the exhaustive
+    // tuner, which times and caches under their features
+    srtc_tensor at{}, bt{};
+    const BlockDiag *blk[2] = {&P.A, &P.B};
+    srtc_tensor *td[2] = {&at, &bt};
+    for (int q = 0; q < 2; q++) {
+      const CsrView v = blk[q]->view();
+      srtc_tensor &t = *td[q];
+      t.order = 2;
+      t.format = SRTC_CSR;
+      t.dtype = P.dt;
+      t.split = 1;
+      t.dims[0] = v.m;
+      t.dims[1] = v.n;
+      t.nnz = v.nnz;
+      t.rowptr = const_cast<int64_t *>(v.rowptr);
+      t.colidx = const_cast<int32_t *>(v.col);
+      t.vals = const_cast<void *>(v.val);
+    }
+    const srtc_status st = srtc_autotune(ctx, sr, add_id, &at, &bt, reps, best, times_ms, stream);
+    if (st != SRTC_OK) fail(st, c->err);
   });
 }
 

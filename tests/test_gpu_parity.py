@@ -536,6 +536,34 @@ def test_batch_contract_and_fixpoint(ctx):
         assert np.array_equal(X.cpu().numpy(), exp)
 
 
+def test_batch_autotune_one_schedule_for_the_batch():
+    """The batch tuner times every schedule on the whole batch (as
+    batch_contract forms it with one schedule) and caches the winner: a
+    later batch_contract of the same batch without schedules takes it, and
+    its results equal the oracle's and those of the winner given
+    explicitly (bit-exact over (min,+)); malformed batches are refused."""
+    say("batch autotune")
+    c = srtc.Context(0)
+    ns = [300, 2500, 40, 1200, 4000, 900, 64, 1800]
+    As, Os = [], []
+    for b, n in enumerate(ns):
+        src, dst = synth.er_edges(n, 8, seed=3000 + b)
+        w = synth.edge_values("i32", src.size, 3000 + b, lo=1, hi=100)
+        As.append(gpu_fold(c, "min_plus", "i32", dst, src, w, n, n))
+        Os.append(oracle.fold("min_plus", "i32", dst, src, w, n, n))
+    best, times = c.batch_autotune("min_plus", As, As, reps=3)
+    say("  batch schedule", best, "times", np.round(times, 3))
+    assert 0 <= best < srtc.NUM_SCHEDULES
+    assert (times > 0).all() and times[best] == times.min()
+    chosen = c.batch_contract("min_plus", As, As)
+    given = c.batch_contract("min_plus", As, As, schedules=[best] * len(As))
+    for C, G, O in zip(chosen, given, Os):
+        check_csr(C, oracle.spgemm("min_plus", "i32", O, O), "min_plus", "i32")
+        assert torch.equal(C.rowptr, G.rowptr) and torch.equal(C.col, G.col) and torch.equal(C.val, G.val)
+    with pytest.raises(srtc.SrtcError):
+        c.batch_autotune("min_plus", As, As, ia="ik", ib="kj", ic="ik")
+
+
 # -------------------------------------------------------------------- MLP --
 def test_batch_index_strings_and_per_instance_schedules(ctx):
     """Batched C_b = A_b (x) B_b with one schedule per instance (every
