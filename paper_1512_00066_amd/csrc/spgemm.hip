@@ -10,12 +10,13 @@
 //   3. symbolic       nnz_i per row: LDS hash of column keys (light rows) or
 //                     an LDS bitmap over the columns (heavy rows)
 //   4. scan           rowptr of C; the single host sync sizes C
-//   5. numeric        per bin: LDS hash, then the kept entries compacted and
-//                     bitonic-sorted in LDS (up to 4096 outputs), or dense
-//                     LDS accumulator windows over the columns (heavy rows,
-//                     whose outputs are a sizeable fraction of n)
+//   5. numeric        per bin: LDS hash, then the kept entries placed by
+//                     rank or bitonic-sorted in LDS, or dense LDS
+//                     accumulator windows and ranked groups over the columns
+//                     (heavy rows)
 //   6. compaction     only if some result equalled the additive identity
-//                     (dropped), the rows are packed again.
+//                     (dropped, or written with column -1), the rows are
+//                     packed again.
 // Every per-bin kernel is persistent: a grid sized to the machine pulls rows
 // from an atomic work counter.
 #include <algorithm>
@@ -743,8 +744,7 @@ __device__ __forceinline__ int64_t extract_window(typename SR::acc_t *vals, uint
   constexpr int NG = (WPW * LPW + WAVE - 1) / WAVE;
   static_assert(NWORD % NW == 0 && 32 % LPW == 0, "window split");
   const int wv = threadIdx.x / WAVE, l = lane_id();
-  // kept entries per lane part (value semirings re-read the accumulators;
-  // for the boolean one the count is the part's popcount, recomputed below)
+  // touched columns per lane part (popcounts, recomputed in the write pass)
   int64_t wtot = 0;
 #pragma unroll 2
   for (int g = 0; g < NG; g++) {
@@ -1285,8 +1285,9 @@ __global__ void build_woff(const int64_t *__restrict__ rpB, const int32_t *__res
 // Compaction after a numeric pass.  Row i of C was written as Q segments
 // (segment q from start[q m + i], len[q m + i] entries; one segment per row
 // outside the column-block path) that may fall short of the row's symbolic
-// count (identity results dropped) and may hold entries with column -1
-// (identity results of ranked groups, written in place).  The listed rows
+// count (identity results dropped by the hash bins) and may hold entries
+// with column -1 (identity results of dense windows and ranked groups,
+// written in place).  The listed rows
 // (rows = null: rows 0..n-1) are counted, then packed: cnt[i] = entries of
 // row i with a column >= 0; they move in order to rp_new[i] onwards.  One
 // wave per row.
@@ -1639,7 +1640,8 @@ void numeric_bin(Ctx *c, const CsrView &Am, const int64_t *nnz_row, const RowGro
 
 // Numeric kernels of one binned group (hinfo2: the host copy of its bin
 // table), writing at rpC.  kp[row] = entries written; fl[0] is raised when a
-// row came out short (identity results dropped), fl[1] on a broken hash
+// row came out short (identity results dropped) or holds an entry with
+// column -1 (an identity result written in place), fl[1] on a broken hash
 // invariant.
 template <class SR>
 void numeric_launch(Ctx *c, typename SR::acc_t id, const CsrView &Am, const CsrView &Bm, const int64_t *w,
